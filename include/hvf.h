@@ -1,0 +1,125 @@
+/*
+ * hvf.h -- ray intersection through hybrid voxel formats on AMD Instinct MI355X (gfx950).
+ *
+ * A hybrid voxel format is an ordered list of levels, each a base format: a Raw grid
+ * R(W,H,D) of 2^W x 2^H x 2^D cells, a sparse voxel octree S(L) or a sparse voxel DAG
+ * G(L) of depth L (Hybrid Voxel Formats, Sec. 3.1-3.2 and the table of implemented
+ * formats). A cell of an upper level is a sub-volume stored in the next level's format;
+ * a cell of the last level is a single voxel. Every level below the first must be a
+ * cube (Sec. 5). The whole format lives in one buffer of 32-bit words whose word 0
+ * holds the root pointer (Sec. 3.3, Sec. 4.1); this limits a format to 2^32 words.
+ *
+ * The query (Sec. 4.2): for each ray, the first occupied voxel along it.
+ *
+ * Coordinates are in finest-voxel units: the volume is [0,Nx) x [0,Ny) x [0,Nz) and voxel
+ * (x,y,z) is the box [x,x+1) x [y,y+1) x [z,z+1). A ray is o + t*d for t in [tmin, tmax].
+ * Numerics, shared bit-for-bit by every entry point: inv_a = 1/d_a (fp32, correctly
+ * rounded); an axis with a non-finite inv_a is parallel; the crossing time of integer
+ * plane p is T_a(p) = (float(p) - o_a) * inv_a (two rounded fp32 ops, never fused);
+ * max(a,b) = a<b ? b : a and min(a,b) = b<a ? b : a. The ray is clipped to
+ * [t0, t1) = [max(tmin, entry), min(tmax, exit)). Voxel v is visited iff
+ * e(v) < x(v), where e(v) = max(t0, max_a T_a(near_a)) and x(v) = min(t1, min_a T_a(far_a))
+ * over non-parallel axes, and a parallel axis needs v_a == floor(o_a). The result is the
+ * visited occupied voxel of least e(v), reported with t = e(v). Rays with a NaN or
+ * infinite origin or direction component, or a zero direction, miss.
+ *
+ * Errors: every hvf_status-returning call returns HVF_OK or an error code and leaves its
+ * out-parameters untouched on error; hvf_last_error() gives a thread-local message.
+ */
+#ifndef HVF_H
+#define HVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One ray, 32 bytes, in grid units. tmax may be +inf. */
+typedef struct hvf_ray {
+  float ox, oy, oz, tmin;
+  float dx, dy, dz, tmax;
+} hvf_ray;
+
+/* One result, 16 bytes. Hit: voxel (x,y,z) >= 0 and its entry time t.
+ * Miss: x = y = z = -1, t = +inf. The hit flag is (x >= 0). */
+typedef struct hvf_hit {
+  int32_t x, y, z;
+  float t;
+} hvf_hit;
+
+typedef enum hvf_status {
+  HVF_OK = 0,
+  HVF_E_SPEC = 1,        /* malformed format spec, or a non-cubic level below the first */
+  HVF_E_INPUT = 2,       /* null pointer, codes not strictly ascending or outside the volume */
+  HVF_E_OVERFLOW = 3,    /* the built format would need 2^32 words or more */
+  HVF_E_NOMEM = 4,       /* host or device allocation failed, or a memory budget is exceeded */
+  HVF_E_DEVICE = 5,      /* a HIP runtime error; the message names it */
+  HVF_E_UNSUPPORTED = 6, /* a valid spec this build does not implement (distance-field levels) */
+  HVF_E_STATE = 7        /* call not valid in the object's current state */
+} hvf_status;
+
+typedef struct hvf_volume hvf_volume; /* opaque; immutable once built */
+
+#define HVF_MAX_LEVELS 8
+#define HVF_MAX_DEPTH 16
+
+/* Summary of a built volume. Level kinds: 'R', 'S', 'G'. */
+typedef struct hvf_info {
+  int32_t num_levels;
+  char kinds[HVF_MAX_LEVELS];
+  int32_t level_exp[HVF_MAX_LEVELS][3]; /* log2 cells per axis of each level */
+  int32_t extent_log2[3];               /* log2 voxels per axis of the whole volume */
+  int32_t whole_level_dedup;
+  int32_t num_depths;                   /* node depths of the traversal (Raw: 1, S/G(L): L) */
+  uint64_t num_words;                   /* words in the buffer, including word 0 */
+  uint64_t level_nodes[HVF_MAX_LEVELS]; /* nodes (octree levels) or arrays (Raw) per level */
+  uint64_t depth_nodes[HVF_MAX_DEPTH];
+  uint64_t depth_offset[HVF_MAX_DEPTH]; /* first word of each depth: depths are stored in order */
+  uint64_t num_voxels;                  /* occupied voxels */
+} hvf_info;
+
+/* Build a volume on the host (Sec. 4.1).
+ * format_spec: e.g. "G(7) R(4,4,4) --whole-level-dedup"; R(k^3) means R(k,k,k).
+ * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
+ *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
+ * out: receives a new handle owned by the caller (release with hvf_free).
+ * Errors: HVF_E_SPEC, HVF_E_UNSUPPORTED, HVF_E_INPUT, HVF_E_OVERFLOW, HVF_E_NOMEM.
+ * Makes no HIP call. */
+hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, hvf_volume** out);
+
+/* Copy the word buffer to device memory owned by the handle, on hip_stream (a
+ * hipStream_t, or NULL for the null stream). Called implicitly by the first trace.
+ * Errors: HVF_E_INPUT, HVF_E_NOMEM, HVF_E_DEVICE. */
+hvf_status hvf_upload(hvf_volume* vol, void* hip_stream);
+
+/* Trace n rays (Sec. 4.2). d_rays, d_hits: device pointers to n hvf_ray / hvf_hit,
+ * caller-owned. Asynchronous on hip_stream; the caller synchronises. Uploads the volume
+ * first if needed. n == 0 is a no-op. Errors: HVF_E_INPUT, HVF_E_DEVICE, HVF_E_NOMEM. */
+hvf_status hvf_trace(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* hip_stream);
+
+/* Synchronous convenience form: host ray and hit arrays, staged through device memory. */
+hvf_status hvf_trace_host(hvf_volume* vol, const hvf_ray* rays, size_t n, hvf_hit* hits);
+
+/* Sizes and per-level / per-depth node counts. */
+hvf_status hvf_info_get(const hvf_volume* vol, hvf_info* out);
+
+/* Copy the word buffer (host copy) into words[0..cap); *n_words receives its length. */
+hvf_status hvf_words(const hvf_volume* vol, uint32_t* words, size_t cap, size_t* n_words);
+
+/* Save / load a built volume (header with magic, spec, word count and checksum, then the
+ * words). hvf_load returns a new handle owned by the caller. */
+hvf_status hvf_save(const hvf_volume* vol, const char* path);
+hvf_status hvf_load(const char* path, hvf_volume** out);
+
+/* Release a handle and its host and device memory. NULL is ignored. */
+void hvf_free(hvf_volume* vol);
+
+const char* hvf_status_string(hvf_status s);
+const char* hvf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HVF_H */

@@ -1,0 +1,199 @@
+"""Ray intersection through hybrid voxel formats on MI355X: Python binding of libhvf.so.
+
+Argument marshalling only. Every step of building and tracing runs in the native
+library (host C++ builder, HIP kernels); there is no Python or CPU fallback, and
+importing this module without a built libhvf.so raises.
+
+PyTorch supplies device memory and streams: ``Volume.trace`` takes CUDA (HIP) tensors
+of rays (float32 [n, 8]: ox, oy, oz, tmin, dx, dy, dz, tmax) and hits (int32 [n, 4]:
+x, y, z and the float32 bits of t).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libhvf.so")
+
+HVF_MAX_LEVELS = 8
+HVF_MAX_DEPTH = 16
+
+STATUS = {0: "HVF_OK", 1: "HVF_E_SPEC", 2: "HVF_E_INPUT", 3: "HVF_E_OVERFLOW", 4: "HVF_E_NOMEM",
+          5: "HVF_E_DEVICE", 6: "HVF_E_UNSUPPORTED", 7: "HVF_E_STATE"}
+
+
+class HvfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class hvf_info(ctypes.Structure):
+    _fields_ = [
+        ("num_levels", ctypes.c_int32),
+        ("kinds", ctypes.c_char * HVF_MAX_LEVELS),
+        ("level_exp", (ctypes.c_int32 * 3) * HVF_MAX_LEVELS),
+        ("extent_log2", ctypes.c_int32 * 3),
+        ("whole_level_dedup", ctypes.c_int32),
+        ("num_depths", ctypes.c_int32),
+        ("num_words", ctypes.c_uint64),
+        ("level_nodes", ctypes.c_uint64 * HVF_MAX_LEVELS),
+        ("depth_nodes", ctypes.c_uint64 * HVF_MAX_DEPTH),
+        ("depth_offset", ctypes.c_uint64 * HVF_MAX_DEPTH),
+        ("num_voxels", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhvf.so (built by ``paper_2410_14128_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise ImportError(f"{SO_PATH} is not built; run `python -m paper_2410_14128_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(SO_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        L.hvf_build.restype = i32
+        L.hvf_build.argtypes = [ctypes.c_char_p, vp, sz, ctypes.POINTER(vp)]
+        L.hvf_upload.restype = i32
+        L.hvf_upload.argtypes = [vp, vp]
+        L.hvf_trace.restype = i32
+        L.hvf_trace.argtypes = [vp, vp, sz, vp, vp]
+        L.hvf_trace_host.restype = i32
+        L.hvf_trace_host.argtypes = [vp, vp, sz, vp]
+        L.hvf_info_get.restype = i32
+        L.hvf_info_get.argtypes = [vp, ctypes.POINTER(hvf_info)]
+        L.hvf_words.restype = i32
+        L.hvf_words.argtypes = [vp, vp, sz, ctypes.POINTER(sz)]
+        L.hvf_save.restype = i32
+        L.hvf_save.argtypes = [vp, ctypes.c_char_p]
+        L.hvf_load.restype = i32
+        L.hvf_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.hvf_free.restype = None
+        L.hvf_free.argtypes = [vp]
+        L.hvf_status_string.restype = ctypes.c_char_p
+        L.hvf_status_string.argtypes = [i32]
+        L.hvf_last_error.restype = ctypes.c_char_p
+        L.hvf_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise HvfError(st, lib().hvf_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Volume:
+    """A built hybrid format (host word buffer; device copy made on first trace)."""
+
+    def __init__(self, spec: str, codes: np.ndarray | None = None, *, _handle=None):
+        if _handle is not None:
+            self._h = _handle
+        else:
+            c = np.ascontiguousarray(codes if codes is not None else np.zeros(0), dtype=np.uint64)
+            h = ctypes.c_void_p()
+            _check(lib().hvf_build(spec.encode(), c.ctypes.data if len(c) else None, len(c), ctypes.byref(h)))
+            self._h = h.value
+        self.spec = spec
+
+    @classmethod
+    def load(cls, path: str) -> "Volume":
+        h = ctypes.c_void_p()
+        _check(lib().hvf_load(path.encode(), ctypes.byref(h)))
+        v = cls("", _handle=h.value)
+        return v
+
+    def save(self, path: str):
+        _check(lib().hvf_save(self._h, path.encode()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hvf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def info(self) -> dict:
+        I = hvf_info()
+        _check(lib().hvf_info_get(self._h, ctypes.byref(I)))
+        n = I.num_levels
+        nd = I.num_depths
+        return {
+            "num_levels": n,
+            "kinds": I.kinds[:n].decode(),
+            "level_exp": [tuple(I.level_exp[k]) for k in range(n)],
+            "extent_log2": tuple(I.extent_log2),
+            "whole_level_dedup": bool(I.whole_level_dedup),
+            "num_depths": nd,
+            "num_words": int(I.num_words),
+            "bytes": int(I.num_words) * 4,
+            "level_nodes": [int(I.level_nodes[k]) for k in range(n)],
+            "depth_nodes": [int(I.depth_nodes[d]) for d in range(nd)],
+            "depth_offset": [int(I.depth_offset[d]) for d in range(nd)],
+            "num_voxels": int(I.num_voxels),
+        }
+
+    def words(self) -> np.ndarray:
+        n = ctypes.c_size_t()
+        _check(lib().hvf_words(self._h, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.uint32)
+        _check(lib().hvf_words(self._h, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out
+
+    def upload(self, stream=None):
+        _check(lib().hvf_upload(self._h, _stream_ptr(stream)))
+
+    def trace(self, rays, hits=None, stream=None):
+        """Trace device rays (torch float32 [n, 8] on the GPU) into hits (int32 [n, 4]).
+
+        Asynchronous on ``stream`` (default: torch's current stream). Returns ``hits``.
+        """
+        import torch
+        assert rays.is_cuda and rays.dtype == torch.float32 and rays.shape[-1] == 8 and rays.is_contiguous()
+        n = rays.shape[0]
+        if hits is None:
+            hits = torch.empty((n, 4), dtype=torch.int32, device=rays.device)
+        assert hits.is_cuda and hits.dtype == torch.int32 and hits.shape == (n, 4) and hits.is_contiguous()
+        _check(lib().hvf_trace(self._h, rays.data_ptr(), n, hits.data_ptr(), _stream_ptr(stream)))
+        return hits
+
+    def trace_host(self, rays: np.ndarray) -> np.ndarray:
+        """Synchronous host-array form: float32 [n, 8] in, int32 [n, 4] out."""
+        r = np.ascontiguousarray(rays, dtype=np.float32)
+        assert r.ndim == 2 and r.shape[1] == 8
+        out = np.empty((len(r), 4), dtype=np.int32)
+        _check(lib().hvf_trace_host(self._h, r.ctypes.data, len(r), out.ctypes.data))
+        return out
+
+
+def exported_symbols() -> list[str]:
+    """Names declared in include/hvf.h (for the export check)."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "hvf.h")
+    src = open(hdr).read()
+    return sorted(set(re.findall(r"\b(hvf_[a-z_0-9]+)\s*\(", src)))

@@ -1,0 +1,287 @@
+// C-ABI entry points: build, upload, trace, info, save/load, errors.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hvf_internal.h"
+
+namespace hvf {
+hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s);
+}
+
+namespace {
+thread_local std::string g_err;
+
+hvf_status fail(hvf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+hvf_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return (e == hipErrorOutOfMemory) ? HVF_E_NOMEM : HVF_E_DEVICE;
+}
+
+uint64_t fnv64(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+const char MAGIC[8] = {'H', 'V', 'F', 'W', 'O', 'R', 'D', '1'};
+}  // namespace
+
+void hvf_set_error(const std::string& s) { g_err = s; }
+
+extern "C" {
+
+const char* hvf_last_error(void) { return g_err.c_str(); }
+
+const char* hvf_status_string(hvf_status s) {
+  switch (s) {
+    case HVF_OK: return "ok";
+    case HVF_E_SPEC: return "malformed format spec";
+    case HVF_E_INPUT: return "invalid input";
+    case HVF_E_OVERFLOW: return "format exceeds 2^32 words";
+    case HVF_E_NOMEM: return "out of memory";
+    case HVF_E_DEVICE: return "HIP device error";
+    case HVF_E_UNSUPPORTED: return "unsupported format";
+    case HVF_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, hvf_volume** out) {
+  if (!out) return fail(HVF_E_INPUT, "null output handle pointer");
+  hvf::Spec spec;
+  std::string err;
+  hvf_status st = hvf::parse_spec(format_spec, spec, err);
+  if (st != HVF_OK) return fail(st, err);
+  hvf_volume* v = new (std::nothrow) hvf_volume();
+  if (!v) return fail(HVF_E_NOMEM, "host allocation failed");
+  v->spec = spec;
+  v->layout = hvf::make_layout(spec);
+  st = hvf::build_words(v->spec, v->layout, morton, n, v->built, err);
+  if (st != HVF_OK) {
+    delete v;
+    return fail(st, err);
+  }
+  *out = v;
+  return HVF_OK;
+}
+
+hvf_status hvf_upload(hvf_volume* v, void* stream) {
+  if (!v) return fail(HVF_E_INPUT, "null volume");
+  if (v->dbuf) return HVF_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const size_t bytes = v->built.words.size() * sizeof(uint32_t);
+  uint32_t* p = nullptr;
+  e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc of the word buffer");
+  e = hipMemcpyAsync(p, v->built.words.data(), bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e, "upload of the word buffer");
+  }
+  v->dbuf = p;
+  v->device = dev;
+  return HVF_OK;
+}
+
+hvf_status hvf_trace(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* stream) {
+  if (!v) return fail(HVF_E_INPUT, "null volume");
+  if (n == 0) return HVF_OK;
+  if (!d_rays || !d_hits) return fail(HVF_E_INPUT, "null ray or hit buffer");
+  hvf_status st = hvf_upload(v, stream);
+  if (st != HVF_OK) return st;
+  const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  return hvf::launch_trace(F, d_rays, n, d_hits, (hipStream_t)stream);
+}
+
+hvf_status hvf_trace_host(hvf_volume* v, const hvf_ray* rays, size_t n, hvf_hit* hits) {
+  if (!v) return fail(HVF_E_INPUT, "null volume");
+  if (n == 0) return HVF_OK;
+  if (!rays || !hits) return fail(HVF_E_INPUT, "null ray or hit array");
+  hvf_ray* dr = nullptr;
+  hvf_hit* dh = nullptr;
+  hipError_t e = hipMalloc(&dr, n * sizeof(hvf_ray));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc rays");
+  e = hipMalloc(&dh, n * sizeof(hvf_hit));
+  if (e != hipSuccess) {
+    (void)hipFree(dr);
+    return hip_fail(e, "hipMalloc hits");
+  }
+  hvf_status st = HVF_OK;
+  e = hipMemcpy(dr, rays, n * sizeof(hvf_ray), hipMemcpyHostToDevice);
+  if (e != hipSuccess) st = hip_fail(e, "copy rays");
+  if (st == HVF_OK) st = hvf_trace(v, dr, n, dh, nullptr);
+  if (st == HVF_OK) {
+    e = hipMemcpy(hits, dh, n * sizeof(hvf_hit), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = hip_fail(e, "copy hits");
+  }
+  (void)hipFree(dr);
+  (void)hipFree(dh);
+  return st;
+}
+
+hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
+  if (!v || !out) return fail(HVF_E_INPUT, "null argument");
+  hvf_info I;
+  std::memset(&I, 0, sizeof(I));
+  I.num_levels = (int32_t)v->spec.lv.size();
+  for (int k = 0; k < I.num_levels; ++k) {
+    const int kind = v->spec.lv[k].kind;
+    I.kinds[k] = kind == hvf::LK_RAW ? 'R' : kind == hvf::LK_SVO ? 'S' : 'G';
+    for (int a = 0; a < 3; ++a) I.level_exp[k][a] = v->spec.lv[k].e[a];
+    I.level_nodes[k] = v->built.level_nodes.empty() ? 0 : v->built.level_nodes[k];
+  }
+  for (int a = 0; a < 3; ++a) I.extent_log2[a] = v->spec.ext[a];
+  I.whole_level_dedup = v->spec.wld ? 1 : 0;
+  I.num_depths = (int32_t)v->layout.d.size();
+  I.num_words = v->built.words.size();
+  for (size_t d = 0; d < v->layout.d.size() && d < HVF_MAX_DEPTH; ++d) {
+    I.depth_nodes[d] = d < v->built.depth_nodes.size() ? v->built.depth_nodes[d] : 0;
+    I.depth_offset[d] = d < v->built.depth_offset.size() ? v->built.depth_offset[d] : 0;
+  }
+  I.num_voxels = v->built.nvox;
+  *out = I;
+  return HVF_OK;
+}
+
+hvf_status hvf_words(const hvf_volume* v, uint32_t* words, size_t cap, size_t* n_words) {
+  if (!v || !n_words) return fail(HVF_E_INPUT, "null argument");
+  const size_t n = v->built.words.size();
+  if (words) std::memcpy(words, v->built.words.data(), (cap < n ? cap : n) * sizeof(uint32_t));
+  *n_words = n;
+  return HVF_OK;
+}
+
+namespace {
+// Reads/writes that fold every byte into a running FNV-1a checksum.
+struct HashedFile {
+  FILE* f;
+  uint64_t h = 1469598103934665603ull;
+  bool ok = true;
+  void put(const void* p, size_t n) {
+    if (ok && n) ok = std::fwrite(p, 1, n, f) == n;
+    h = fnv64(p, n, h);
+  }
+  void get(void* p, size_t n) {
+    if (ok && n) ok = std::fread(p, 1, n, f) == n;
+    if (ok) h = fnv64(p, n, h);
+  }
+};
+}  // namespace
+
+hvf_status hvf_save(const hvf_volume* v, const char* path) {
+  if (!v || !path) return fail(HVF_E_INPUT, "null argument");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(HVF_E_INPUT, std::string("cannot open ") + path);
+  const hvf::Built& B = v->built;
+  const uint64_t slen = v->spec.text.size(), nw = B.words.size(), nd = B.depth_nodes.size(),
+                 nl = B.level_nodes.size();
+  HashedFile w{f};
+  w.put(MAGIC, 8);
+  w.put(&slen, 8);
+  w.put(v->spec.text.data(), slen);
+  w.put(&nw, 8);
+  w.put(&B.nvox, 8);
+  w.put(&nd, 8);
+  w.put(&nl, 8);
+  w.put(B.depth_nodes.data(), 8 * nd);
+  w.put(B.depth_offset.data(), 8 * nd);
+  w.put(B.depth_words.data(), 8 * nd);
+  w.put(B.level_nodes.data(), 8 * nl);
+  w.put(B.words.data(), 4 * nw);
+  const uint64_t sum = w.h;
+  bool ok = w.ok && std::fwrite(&sum, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? HVF_OK : fail(HVF_E_INPUT, std::string("write failed: ") + path);
+}
+
+hvf_status hvf_load(const char* path, hvf_volume** out) {
+  if (!path || !out) return fail(HVF_E_INPUT, "null argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(HVF_E_INPUT, std::string("cannot open ") + path);
+  char magic[8];
+  uint64_t slen = 0, nw = 0, nd = 0, nl = 0, sum = 0;
+  hvf_volume* v = new (std::nothrow) hvf_volume();
+  HashedFile r{f};
+  bool ok = v != nullptr;
+  if (ok) {
+    r.get(magic, 8);
+    ok = r.ok && std::memcmp(magic, MAGIC, 8) == 0;
+  }
+  if (ok) {
+    r.get(&slen, 8);
+    ok = r.ok && slen < 4096;
+  }
+  std::string text(ok ? slen : 0, '\0');
+  if (ok) {
+    r.get(&text[0], slen);
+    r.get(&nw, 8);
+    r.get(&v->built.nvox, 8);
+    r.get(&nd, 8);
+    r.get(&nl, 8);
+    ok = r.ok && nw >= 1 && nw < (1ull << 32) && nd <= HVF_MAX_DEPTH && nl <= HVF_MAX_LEVELS;
+  }
+  if (ok) {
+    v->built.depth_nodes.resize(nd);
+    v->built.depth_offset.resize(nd);
+    v->built.depth_words.resize(nd);
+    v->built.level_nodes.resize(nl);
+    r.get(v->built.depth_nodes.data(), 8 * nd);
+    r.get(v->built.depth_offset.data(), 8 * nd);
+    r.get(v->built.depth_words.data(), 8 * nd);
+    r.get(v->built.level_nodes.data(), 8 * nl);
+    ok = r.ok;
+  }
+  if (ok) {
+    try {
+      v->built.words.resize(nw);
+    } catch (const std::bad_alloc&) {
+      ok = false;
+    }
+    if (ok) r.get(v->built.words.data(), 4 * nw);
+    ok = ok && r.ok && std::fread(&sum, 8, 1, f) == 1 && sum == r.h;
+  }
+  std::fclose(f);
+  std::string err;
+  if (ok) {
+    hvf_status st = hvf::parse_spec(text.c_str(), v->spec, err);
+    ok = (st == HVF_OK);
+    if (ok) {
+      v->layout = hvf::make_layout(v->spec);
+      ok = v->layout.d.size() == nd && v->spec.lv.size() == nl;
+    }
+  }
+  if (!ok) {
+    delete v;
+    return fail(HVF_E_INPUT, std::string("not a valid volume file: ") + path + (err.empty() ? "" : " (" + err + ")"));
+  }
+  *out = v;
+  return HVF_OK;
+}
+
+void hvf_free(hvf_volume* v) {
+  if (!v) return;
+  if (v->dbuf) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != v->device) {
+      (void)hipSetDevice(v->device);
+      (void)hipFree(v->dbuf);
+      (void)hipSetDevice(cur);
+    } else {
+      (void)hipFree(v->dbuf);
+    }
+  }
+  delete v;
+}
+
+}  // extern "C"

@@ -1,0 +1,520 @@
+// Host side: spec parser, traversal layout and the builder of the GPU word buffer.
+//
+// Construction follows Sec. 4.1 (and Sec. 5 for Morton order): every level maps the lower
+// corner of a sub-volume to its constructed content, recursing into the next level for
+// each non-empty cell; empty sub-volumes are represented by 0. SVO children are laid out
+// contiguously and found from the valid mask; SVDAG nodes carry one pointer per valid
+// child and are de-duplicated per sub-volume or, with --whole-level-dedup, per level
+// (Sec. 4.3). The memory layout follows Sec. 3.3 with these deviations, none of which
+// changes which voxels are occupied:
+//  * the input is binary occupancy, so the last level carries no RGBA words: a last Raw
+//    level is a bit brick (Morton bit order inside cubic bricks), and the deepest octree
+//    depth of a last SVO/SVDAG level is its valid mask;
+//  * a terminating integer below an SVDAG node is stored in the parent's pointer slot
+//    instead of a separate one-word leaf node; an SVO node just above the next level
+//    points to a packed array of those pointers instead of two-word leaf nodes;
+//  * nodes are grouped by traversal depth (all depth-0 nodes, then depth 1, ...), so the
+//    upper levels form one contiguous prefix of the buffer.
+#include <algorithm>
+#include <cstring>
+#include <unordered_map>
+
+#include "hvf_internal.h"
+
+namespace hvf {
+
+// ------------------------------------------------------------------ parser
+namespace {
+
+bool read_num(const std::string& s, size_t& i, int& v) {
+  while (i < s.size() && (s[i] == ' ' || s[i] == '\t')) ++i;
+  size_t j = i;
+  while (j < s.size() && std::isdigit((unsigned char)s[j])) ++j;
+  if (j == i || j - i > 2) return false;
+  v = std::atoi(s.substr(i, j - i).c_str());
+  i = j;
+  while (i < s.size() && (s[i] == ' ' || s[i] == '\t')) ++i;
+  return true;
+}
+
+}  // namespace
+
+hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
+  if (!text) {
+    err = "null format spec";
+    return HVF_E_INPUT;
+  }
+  Spec s;
+  s.text = text;
+  const std::string str(text);
+  size_t i = 0;
+  bool unsupported = false;
+  while (i < str.size()) {
+    char c = str[i];
+    if (c == ' ' || c == '\t') {
+      ++i;
+      continue;
+    }
+    if (c == '-') {
+      size_t j = i;
+      while (j < str.size() && str[j] != ' ' && str[j] != '\t') ++j;
+      std::string flag = str.substr(i, j - i);
+      if (flag == "--whole-level-dedup" || flag == "-whole-level-dedup" || flag == "--wld") {
+        s.wld = true;
+      } else if (flag == "--restart-sv" || flag == "-restart-sv") {
+        unsupported = true;
+        err = "restarting sparse-voxel intersection is not implemented";
+      } else {
+        err = "unknown flag '" + flag + "'";
+        return HVF_E_SPEC;
+      }
+      i = j;
+      continue;
+    }
+    if (c != 'R' && c != 'S' && c != 'G' && c != 'D') {
+      err = std::string("unknown level kind '") + c + "'";
+      return HVF_E_SPEC;
+    }
+    ++i;
+    while (i < str.size() && str[i] == ' ') ++i;
+    if (i >= str.size() || str[i] != '(') {
+      err = "expected '(' after level kind";
+      return HVF_E_SPEC;
+    }
+    ++i;
+    std::vector<int> a;
+    int v;
+    if (!read_num(str, i, v)) {
+      err = "expected a number";
+      return HVF_E_SPEC;
+    }
+    a.push_back(v);
+    if (i < str.size() && str[i] == '^') {
+      ++i;
+      int p;
+      if (!read_num(str, i, p) || p != 3) {
+        err = "only the k^3 shorthand is accepted";
+        return HVF_E_SPEC;
+      }
+      a = {v, v, v};
+    }
+    while (i < str.size() && str[i] == ',') {
+      ++i;
+      if (!read_num(str, i, v)) {
+        err = "expected a number";
+        return HVF_E_SPEC;
+      }
+      a.push_back(v);
+    }
+    if (i >= str.size() || str[i] != ')') {
+      err = "expected ')'";
+      return HVF_E_SPEC;
+    }
+    ++i;
+    LevelSpec L{};
+    if (c == 'R') {
+      if (a.size() != 3) {
+        err = "R(W,H,D) takes three exponents";
+        return HVF_E_SPEC;
+      }
+      L.kind = LK_RAW;
+      for (int k = 0; k < 3; ++k) L.e[k] = a[k];
+    } else if (c == 'D') {
+      if (a.size() != 4 && !(a.size() == 3)) {
+        err = "D(W,H,D,M) takes four numbers";
+        return HVF_E_SPEC;
+      }
+      unsupported = true;
+      err = "distance-field levels are not implemented";
+      L.kind = LK_RAW;
+      for (int k = 0; k < 3; ++k) L.e[k] = a[k];
+    } else {
+      if (a.size() != 1 || a[0] < 1) {
+        err = std::string(1, c) + "(L) takes one depth >= 1";
+        return HVF_E_SPEC;
+      }
+      L.kind = (c == 'S') ? LK_SVO : LK_DAG;
+      L.e[0] = L.e[1] = L.e[2] = a[0];
+    }
+    s.lv.push_back(L);
+  }
+  if (s.lv.empty()) {
+    err = "no levels";
+    return HVF_E_SPEC;
+  }
+  if (s.lv.size() > HVF_MAX_LEVELS) {
+    err = "too many levels";
+    return HVF_E_SPEC;
+  }
+  const int n = (int)s.lv.size();
+  for (int k = 1; k < n; ++k)
+    if (s.lv[k].e[0] != s.lv[k].e[1] || s.lv[k].e[0] != s.lv[k].e[2]) {
+      err = "every level below the first must be cubic";
+      return HVF_E_SPEC;
+    }
+  s.sub.assign(n + 1, 0);
+  for (int k = n - 1; k >= 1; --k) s.sub[k] = s.sub[k + 1] + s.lv[k].e[0];
+  int depths = 0;
+  for (int k = 0; k < n; ++k) depths += (s.lv[k].kind == LK_RAW) ? 1 : s.lv[k].e[0];
+  for (int a = 0; a < 3; ++a) {
+    s.ext[a] = s.sub[1] + s.lv[0].e[a];
+    if (s.ext[a] > 16) {
+      err = "volume side above 2^16 voxels";
+      return HVF_E_SPEC;
+    }
+  }
+  if (depths > HVF_MAX_DEPTH) {
+    err = "more than 16 node depths";
+    return HVF_E_SPEC;
+  }
+  if (unsupported) return HVF_E_UNSUPPORTED;
+  out = s;
+  return HVF_OK;
+}
+
+Layout make_layout(const Spec& s) {
+  Layout L;
+  const int n = (int)s.lv.size();
+  for (int k = 0; k < n; ++k) {
+    const LevelSpec& lv = s.lv[k];
+    const bool last = (k == n - 1);
+    const int cs_level = s.sub[k + 1];
+    if (lv.kind == LK_RAW) {
+      DepthInfo d{};
+      d.level = k;
+      d.j = 0;
+      d.nk = last ? NK_RAW_BITS : NK_RAW_PTR;
+      d.hk = HK_RAW;
+      d.cs = cs_level;
+      d.w = lv.e[0];
+      L.d.push_back(d);
+    } else {
+      const int D = lv.e[0];
+      for (int j = 0; j < D; ++j) {
+        DepthInfo d{};
+        d.level = k;
+        d.j = j;
+        d.cs = cs_level + (D - 1 - j);
+        d.w = 1;
+        d.hk = (lv.kind == LK_SVO) ? HK_SVO : HK_DAG;
+        if (j < D - 1)
+          d.nk = (lv.kind == LK_SVO) ? NK_SVO_INNER : NK_OCT_PTR;
+        else
+          d.nk = last ? NK_OCT_FINAL : NK_OCT_PTR;
+        L.d.push_back(d);
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) L.top_w[a] = (s.lv[0].kind == LK_RAW) ? s.lv[0].e[a] : 1;
+  L.bits_linear = (n == 1 && s.lv[0].kind == LK_RAW &&
+                   !(s.lv[0].e[0] == s.lv[0].e[1] && s.lv[0].e[0] == s.lv[0].e[2]));
+  return L;
+}
+
+DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf) {
+  DevFormat f{};
+  f.buf = dbuf;
+  for (int a = 0; a < 3; ++a) {
+    f.ext[a] = s.ext[a];
+    f.top_w[a] = L.top_w[a];
+  }
+  f.ndepth = (int)L.d.size();
+  f.bits_linear = L.bits_linear ? 1 : 0;
+  for (size_t i = 0; i < L.d.size(); ++i) {
+    f.cs_tab |= (uint64_t)(L.d[i].cs & 15) << (4 * i);
+    f.w_tab |= (uint64_t)(L.d[i].w & 15) << (4 * i);
+    f.nk_tab |= (uint64_t)(L.d[i].nk & 15) << (4 * i);
+    f.hk_tab |= (uint64_t)(L.d[i].hk & 15) << (4 * i);
+  }
+  return f;
+}
+
+// ------------------------------------------------------------------ builder
+namespace {
+
+inline uint64_t spread3(uint64_t v) {
+  v &= 0x1FFFFFull;
+  v = (v | (v << 32)) & 0x1F00000000FFFFull;
+  v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+  v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+inline uint64_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+  v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+  v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
+  v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
+  v = (v ^ (v >> 32)) & 0x1FFFFFull;
+  return v;
+}
+inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2); }
+
+struct Overflow {};
+
+// Content-addressed node map for SVDAG de-duplication: key = (depth, node words), where
+// child references are already canonical ids; value = node id in that depth's arena.
+struct NodeMap {
+  std::unordered_map<uint64_t, std::vector<uint32_t>> buckets;
+  static uint64_t hash(int depth, const uint32_t* w, size_t n) {
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ ((uint64_t)depth << 40) ^ n;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= w[i] + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+      h *= 0xBF58476D1CE4E5B9ull;
+    }
+    return h ^ (h >> 31);
+  }
+};
+
+struct Builder {
+  const Spec& S;
+  const Layout& L;
+  const uint64_t* codes;
+  std::vector<std::vector<uint32_t>> arena;  // per depth: node words (child refs as ids)
+  std::vector<std::vector<uint32_t>> aux;    // per depth: pointer arrays of SVO nodes
+  std::vector<uint64_t> nodes;               // per depth
+  std::vector<NodeMap> level_map;            // whole-level maps, per level
+  std::vector<int> level_first_depth;
+  std::string err;
+
+  Builder(const Spec& s, const Layout& l, const uint64_t* c) : S(s), L(l), codes(c) {
+    arena.resize(L.d.size());
+    aux.resize(L.d.size());
+    nodes.assign(L.d.size(), 0);
+    level_map.resize(S.lv.size());
+    level_first_depth.assign(S.lv.size(), 0);
+    for (int d = (int)L.d.size() - 1; d >= 0; --d) level_first_depth[L.d[d].level] = d;
+  }
+
+  // End of the run of codes starting at i that share code >> shift (one aligned cube).
+  size_t group_end(size_t i, size_t hi, int shift) const {
+    const uint64_t g = codes[i] >> shift;
+    if (shift >= 63) return hi;
+    return (size_t)(std::lower_bound(codes + i, codes + hi, (g + 1) << shift) - codes);
+  }
+
+  // Build the node at depth d whose region has lower corner (x,y,z); codes[lo,hi) lie in
+  // it (non-empty). Returns its id (word offset) in arena[d]. map: the SVDAG dedup map
+  // in force (per sub-volume or per level), null outside SVDAG levels.
+  uint32_t build(int d, uint64_t x, uint64_t y, uint64_t z, size_t lo, size_t hi, NodeMap* map) {
+    const DepthInfo& di = L.d[d];
+    const LevelSpec& lv = S.lv[di.level];
+    const int cs = di.cs;
+    std::vector<uint32_t>& A = arena[d];
+    if (di.nk == NK_RAW_BITS) {
+      const int wx = (d == 0) ? L.top_w[0] : di.w, wy = (d == 0) ? L.top_w[1] : di.w,
+                wz = (d == 0) ? L.top_w[2] : di.w;
+      const uint64_t bits = 1ull << (wx + wy + wz);
+      if ((bits >> 5) >= (1ull << 31)) throw Overflow();
+      const uint64_t nw = std::max<uint64_t>(2, bits / 32);
+      const uint32_t id = (uint32_t)A.size();
+      A.resize(A.size() + nw, 0u);
+      const uint64_t base = morton(x, y, z);
+      for (size_t i = lo; i < hi; ++i) {
+        uint64_t bit;
+        if (L.bits_linear) {
+          uint64_t vx = compact3(codes[i]) - x, vy = compact3(codes[i] >> 1) - y, vz = compact3(codes[i] >> 2) - z;
+          bit = vx | (vy << wx) | (vz << (wx + wy));
+        } else {
+          bit = codes[i] - base;  // Morton index inside an aligned cubic brick
+        }
+        A[id + (bit >> 5)] |= 1u << (bit & 31);
+      }
+      ++nodes[d];
+      return id;
+    }
+    if (di.nk == NK_RAW_PTR) {
+      const int wx = (d == 0) ? L.top_w[0] : di.w, wy = (d == 0) ? L.top_w[1] : di.w,
+                wz = (d == 0) ? L.top_w[2] : di.w;
+      const uint64_t cells = 1ull << (wx + wy + wz);
+      if (cells >= (1ull << 31)) throw Overflow();
+      std::vector<uint32_t> arr(cells, 0u);
+      // Non-empty children in Morton order (Sec. 5): each is one run of codes.
+      for (size_t a = lo; a < hi;) {
+        const size_t b = group_end(a, hi, 3 * cs);
+        const uint64_t g = codes[a] >> (3 * cs);
+        const uint64_t cx = compact3(g) - (x >> cs), cy = compact3(g >> 1) - (y >> cs), cz = compact3(g >> 2) - (z >> cs);
+        uint32_t child = build_root_of_next(d + 1, x + (cx << cs), y + (cy << cs), z + (cz << cs), a, b);
+        arr[cx | (cy << wx) | (cz << (wx + wy))] = child + 1;  // id + 1; 0 = empty
+        a = b;
+      }
+      const uint32_t id = (uint32_t)A.size();
+      A.insert(A.end(), arr.begin(), arr.end());
+      ++nodes[d];
+      return id;
+    }
+    // Octree node (SVO or SVDAG) at depth j of its level.
+    const bool svo = (lv.kind == LK_SVO);
+    uint32_t valid = 0;
+    uint32_t kids[8];
+    int nk = 0;
+    for (size_t a = lo; a < hi;) {
+      const size_t b = group_end(a, hi, 3 * cs);
+      const int o = (int)((codes[a] >> (3 * cs)) & 7);
+      const uint64_t X = x + ((uint64_t)(o & 1) << cs), Y = y + ((uint64_t)((o >> 1) & 1) << cs),
+                     Z = z + ((uint64_t)((o >> 2) & 1) << cs);
+      valid |= 1u << o;
+      if (di.nk != NK_OCT_FINAL) {
+        if (di.nk == NK_SVO_INNER || (d + 1 < (int)L.d.size() && L.d[d + 1].level == di.level))
+          kids[nk++] = build(d + 1, X, Y, Z, a, b, map);
+        else
+          kids[nk++] = build_root_of_next(d + 1, X, Y, Z, a, b);
+      }
+      a = b;
+    }
+    const bool deepest = (di.nk == NK_OCT_FINAL) || !(d + 1 < (int)L.d.size() && L.d[d + 1].level == di.level);
+    const uint32_t leafmask = deepest ? valid : 0u;
+    const uint32_t masks = valid | (leafmask << 8);
+    if (svo) {
+      uint32_t w0 = 0;
+      if (di.nk == NK_SVO_INNER) {
+        w0 = kids[0];  // children are consecutive 2-word nodes in arena[d+1]
+      } else if (di.nk == NK_OCT_PTR) {
+        w0 = (uint32_t)aux[d].size();
+        aux[d].insert(aux[d].end(), kids, kids + nk);
+      }
+      const uint32_t id = (uint32_t)A.size();
+      A.push_back(w0);
+      A.push_back(masks);
+      ++nodes[d];
+      return id;
+    }
+    // SVDAG: mask word then one pointer per valid child; de-duplicate (not the root of
+    // a sub-volume, which its parent level writes as is).
+    uint32_t w[9];
+    w[0] = masks;
+    size_t len = 1;
+    for (int i = 0; i < nk; ++i) w[len++] = kids[i];
+    const bool root = (di.j == 0);
+    uint64_t h = 0;
+    if (!root && map) {
+      h = NodeMap::hash(d, w, len);
+      auto it = map->buckets.find(h);
+      if (it != map->buckets.end())
+        for (uint32_t cand : it->second)
+          if (cand + len <= A.size() && std::memcmp(&A[cand], w, len * 4) == 0) return cand;
+    }
+    const uint32_t id = (uint32_t)A.size();
+    A.insert(A.end(), w, w + len);
+    ++nodes[d];
+    if (!root && map) map->buckets[h].push_back(id);
+    return id;
+  }
+
+  // Build the root node of the level starting at depth d (a sub-volume of that level).
+  uint32_t build_root_of_next(int d, uint64_t x, uint64_t y, uint64_t z, size_t lo, size_t hi) {
+    const DepthInfo& di = L.d[d];
+    if (S.lv[di.level].kind == LK_DAG) {
+      if (S.wld) return build(d, x, y, z, lo, hi, &level_map[di.level]);
+      NodeMap local;
+      return build(d, x, y, z, lo, hi, &local);
+    }
+    return build(d, x, y, z, lo, hi, nullptr);
+  }
+};
+
+}  // namespace
+
+hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, size_t n, Built& out,
+                       std::string& err) {
+  if (n && !codes) {
+    err = "null Morton code array";
+    return HVF_E_INPUT;
+  }
+  for (size_t i = 0; i < n; ++i) {
+    if (i && codes[i] <= codes[i - 1]) {
+      err = "Morton codes must be strictly ascending (index " + std::to_string(i) + ")";
+      return HVF_E_INPUT;
+    }
+    uint64_t x = compact3(codes[i]), y = compact3(codes[i] >> 1), z = compact3(codes[i] >> 2);
+    if ((x >> s.ext[0]) || (y >> s.ext[1]) || (z >> s.ext[2]) || (codes[i] >> 63)) {
+      err = "Morton code outside the volume (index " + std::to_string(i) + ")";
+      return HVF_E_INPUT;
+    }
+  }
+  Built B;
+  B.nvox = n;
+  const size_t D = L.d.size();
+  B.depth_nodes.assign(D, 0);
+  B.depth_offset.assign(D, 0);
+  B.depth_words.assign(D, 0);
+  B.level_nodes.assign(s.lv.size(), 0);
+  if (n == 0) {
+    B.words.assign(1, 0u);
+    out = std::move(B);
+    return HVF_OK;
+  }
+  Builder b(s, L, codes);
+  uint32_t root_id;
+  try {
+    root_id = b.build_root_of_next(0, 0, 0, 0, 0, n);
+  } catch (const std::bad_alloc&) {
+    err = "host allocation failed while building";
+    return HVF_E_NOMEM;
+  } catch (const Overflow&) {
+    err = "a single node of this format needs 2^31 words or more, beyond 32-bit word offsets";
+    return HVF_E_OVERFLOW;
+  }
+  // Lay the depths out in order, each arena aligned to 64 bytes, SVO pointer arrays
+  // right after their depth. Compute sizes before allocating.
+  std::vector<uint64_t> base(D), auxb(D);
+  uint64_t cur = 1;
+  for (size_t d = 0; d < D; ++d) {
+    cur = (cur + 15) & ~15ull;
+    base[d] = cur;
+    cur += b.arena[d].size();
+    auxb[d] = cur;
+    cur += b.aux[d].size();
+  }
+  if (cur >= (1ull << 32)) {
+    err = "format needs " + std::to_string(cur) + " words, beyond 32-bit word offsets";
+    return HVF_E_OVERFLOW;
+  }
+  try {
+    B.words.assign(cur, 0u);
+  } catch (const std::bad_alloc&) {
+    err = "host allocation failed";
+    return HVF_E_NOMEM;
+  }
+  B.words[0] = (uint32_t)(base[0] + root_id);
+  for (size_t d = 0; d < D; ++d) {
+    const DepthInfo& di = L.d[d];
+    std::vector<uint32_t>& A = b.arena[d];
+    uint32_t* dst = B.words.data() + base[d];
+    std::memcpy(dst, A.data(), A.size() * 4);
+    const uint64_t nb = (d + 1 < D) ? base[d + 1] : 0;
+    switch (di.nk) {
+      case NK_RAW_PTR:
+        for (size_t i = 0; i < A.size(); ++i) dst[i] = A[i] ? (uint32_t)(nb + A[i] - 1) : 0u;
+        break;
+      case NK_SVO_INNER:
+        for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(nb + A[i]);
+        break;
+      case NK_OCT_PTR:
+        if (di.hk == HK_SVO) {
+          for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(auxb[d] + A[i]);
+          uint32_t* ad = B.words.data() + auxb[d];
+          for (size_t i = 0; i < b.aux[d].size(); ++i) ad[i] = (uint32_t)(nb + b.aux[d][i]);
+        } else {
+          for (size_t i = 0; i < A.size();) {
+            uint32_t cnt = (uint32_t)__builtin_popcount(A[i] & 0xFFu);
+            for (uint32_t k = 1; k <= cnt; ++k) dst[i + k] = (uint32_t)(nb + A[i + k]);
+            i += 1 + cnt;
+          }
+        }
+        break;
+      default:
+        break;  // bit bricks and final octree masks hold no pointers
+    }
+    B.depth_nodes[d] = b.nodes[d];
+    B.depth_offset[d] = base[d];
+    B.depth_words[d] = A.size() + b.aux[d].size();
+    B.level_nodes[di.level] += b.nodes[d];
+  }
+  out = std::move(B);
+  return HVF_OK;
+}
+
+}  // namespace hvf

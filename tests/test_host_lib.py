@@ -1,0 +1,165 @@
+"""Host side of the GPU library, on the CPU: exports, spec parsing, builder, save/load.
+
+No compute call needs a device here: hvf_build and the info/words/save/load calls are
+host-only. The builder is checked against an independent reader of its layout
+(losslessness) and against counts fixed by the format definitions.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.layout_decode import decode_codes
+
+H = pytest.importorskip("paper_2410_14128_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not os.path.exists(H.SO_PATH):
+        from paper_2410_14128_amd import build
+        build.build()
+    H.lib()
+
+
+def test_exports_every_declared_symbol():
+    names = H.exported_symbols()
+    hdr = open(os.path.join(ROOT, "include", "hvf.h")).read()
+    assert "hvf_build" in names and "hvf_trace" in names
+    dll = ctypes.CDLL(H.SO_PATH)
+    for n in names:
+        assert hasattr(dll, n), n
+    # every function the header declares has a C (unmangled) symbol
+    decl = set(re.findall(r"^(?:hvf_status|void|const char\*)\s+(hvf_[a-z_0-9]+)\(", hdr, re.M))
+    assert decl and decl <= set(names)
+
+
+SPECS = ["R(3,3,3)", "S(3)", "G(3)", "R(1,1,1) R(2,2,2)", "R(2,2,2) S(1)", "R(1,1,1) G(2)", "S(1) R(2,2,2)",
+         "S(2) S(1)", "S(1) G(2)", "G(2) R(1,1,1)", "G(1) S(2)", "G(1) G(2)", "R(1,1,1) S(1) G(1)",
+         "S(1) G(1) R(1,1,1)", "G(1) R(1,1,1) S(1)", "G(1) G(1) G(1) --whole-level-dedup", "R(1,1,1) G(2) --wld"]
+
+
+@pytest.mark.parametrize("spec", SPECS)
+def test_build_is_lossless(spec):
+    codes = W.scene_bernoulli(7, 3, 3, 3, 0.2)
+    v = H.Volume(spec, codes)
+    assert np.array_equal(decode_codes(v.info(), v.words(), W.morton_encode), codes)
+    assert v.info()["num_voxels"] == len(codes)
+
+
+def test_build_lossless_larger_and_noncubic():
+    codes = W.scene_solid_noise(1)
+    for spec in ["R(2,2,2) S(2) R(2,2,2)", "G(4) R(2,2,2) --whole-level-dedup", "S(2) G(2) R(2,2,2)"]:
+        v = H.Volume(spec, codes)
+        assert np.array_equal(decode_codes(v.info(), v.words(), W.morton_encode), codes), spec
+    nc = W.scene_bernoulli(3, 3, 2, 4, 0.15)
+    for spec in ["R(1,0,2) R(2,2,2)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)", "R(3,2,4)"]:
+        v = H.Volume(spec, nc)
+        assert tuple(v.info()["extent_log2"]) == (3, 2, 4)
+        assert np.array_equal(decode_codes(v.info(), v.words(), W.morton_encode), nc), spec
+
+
+def _nonempty_cubes(codes, side_log2):
+    return len(np.unique(codes >> np.uint64(3 * side_log2)))
+
+
+def test_svo_node_counts_are_nonempty_cubes():
+    codes = W.scene_bernoulli(5, 4, 4, 4, 0.03)
+    info = H.Volume("S(4)", codes).info()
+    # depth j node covers a cube of side 2^(4-j); there is one node per non-empty cube
+    assert info["depth_nodes"] == [_nonempty_cubes(codes, 4 - j) for j in range(4)]
+    info = H.Volume("R(2,2,2) S(2)", codes).info()
+    assert info["depth_nodes"] == [1, _nonempty_cubes(codes, 2), _nonempty_cubes(codes, 1)]
+
+
+def test_dag_full_volume_one_node_per_depth():
+    full = np.arange(1 << 12, dtype=np.uint64)
+    info = H.Volume("G(4)", full).info()
+    assert info["depth_nodes"] == [1, 1, 1, 1]
+    assert info["level_nodes"] == [4]
+
+
+def test_whole_level_dedup_never_grows():
+    codes = W.scene_shell(11, 6, 6, 3, 1.0)
+    for spec in ["R(3,3,3) G(3)", "R(2,2,2) G(4)", "S(2) G(4)", "G(2) G(2) G(2)"]:
+        a = H.Volume(spec, codes).info()["num_words"]
+        b = H.Volume(spec + " --whole-level-dedup", codes).info()["num_words"]
+        assert b <= a, spec
+
+
+def test_empty_volume():
+    v = H.Volume("G(3) R(2,2,2)", np.zeros(0, np.uint64))
+    assert v.info()["num_words"] == 1 and v.words()[0] == 0
+
+
+def test_table_of_formats():
+    for line in open(os.path.join(GOLD, "table_formats.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        label, side, spec = line.split(maxsplit=2)
+        spec = spec.strip()
+        if "D(" in spec:
+            with pytest.raises(H.HvfError) as e:
+                H.Volume(spec, np.zeros(0, np.uint64))
+            assert e.value.name == "HVF_E_UNSUPPORTED"
+            continue
+        info = H.Volume(spec, np.zeros(0, np.uint64)).info()
+        assert info["extent_log2"] == (int(side).bit_length() - 1,) * 3, (label, spec)
+
+
+@pytest.mark.parametrize("spec,status", [
+    ("R(2,2,2) S(1,1,1)", "HVF_E_SPEC"), ("S(2) R(1,0,2)", "HVF_E_SPEC"), ("Q(3)", "HVF_E_SPEC"),
+    ("R(3,3)", "HVF_E_SPEC"), ("S(0)", "HVF_E_SPEC"), ("", "HVF_E_SPEC"), ("R(3,3,3) --bogus", "HVF_E_SPEC"),
+    ("G(9) G(9)", "HVF_E_SPEC"), ("D(4,4,4,6) G(5)", "HVF_E_UNSUPPORTED"), ("R(4,4,4) G(5) --restart-sv", "HVF_E_UNSUPPORTED"),
+])
+def test_spec_errors(spec, status):
+    with pytest.raises(H.HvfError) as e:
+        H.Volume(spec, np.zeros(0, np.uint64))
+    assert e.value.name == status
+
+
+def test_input_errors():
+    for codes in (np.array([5, 3], np.uint64), np.array([5, 5], np.uint64), np.array([1 << 40], np.uint64)):
+        with pytest.raises(H.HvfError) as e:
+            H.Volume("R(3,3,3)", codes)
+        assert e.value.name == "HVF_E_INPUT"
+    with pytest.raises(H.HvfError) as e:
+        H.Volume("R(1,0,2) R(2,2,2)", W.morton_encode(np.array([[0, 4, 0]], np.int32)))
+    assert e.value.name == "HVF_E_INPUT"
+
+
+def test_overflow_reported_before_allocating():
+    with pytest.raises(H.HvfError) as e:
+        H.Volume("R(11,11,11) R(1,1,1)", np.array([0], np.uint64))
+    assert e.value.name == "HVF_E_OVERFLOW"
+
+
+def test_save_load_roundtrip(tmp_path):
+    codes = W.scene_solid_noise(2)
+    v = H.Volume("R(2,2,2) G(2) R(2,2,2) --whole-level-dedup", codes)
+    p = str(tmp_path / "v.hvf")
+    v.save(p)
+    u = H.Volume.load(p)
+    assert np.array_equal(u.words(), v.words())
+    assert u.info() == v.info()
+    # a corrupted file is rejected
+    b = bytearray(open(p, "rb").read())
+    b[200] ^= 0xFF
+    open(p, "wb").write(bytes(b))
+    with pytest.raises(H.HvfError):
+        H.Volume.load(p)
+
+
+def test_gpu_calls_without_device_fail_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("device present")
+    v = H.Volume("G(3)", np.arange(10, dtype=np.uint64))
+    with pytest.raises(H.HvfError) as e:
+        v.upload(0)
+    assert e.value.name in ("HVF_E_DEVICE", "HVF_E_NOMEM")
