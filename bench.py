@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark: ray intersection through hybrid voxel formats on one MI355X.
+
+Default workload (one "step"): the 512^3 surface volume (shell of 32 spheres + 16
+tori) in nine formats, four seeded 1920x1080 pinhole views each, i.e. 36 hvf_trace
+launches over 74,649,600 primary rays. Inputs are resident in HBM before timing.
+value = rays traced per second over the timed steps (Mrays/s).
+
+Also reported (extra keys): the 2048^3 surface volume in its two formats, 1080p
+primary rays and one cosine-weighted bounce ray per primary hit (incoherent).
+
+roofline: algorithmic bytes per ray (32 B ray + 16 B hit + 64 B per distinct 64-byte
+sector of the format the traversal reads, from the counting kernel on a ray sample)
+times rays per launch, over the launch time measured with HIP events on the stream the
+kernels run on; peak = 8 TB/s HBM.
+
+cpu_baseline: the CPU oracle on a bounded sample of the same rays and formats.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+RAY_B, HIT_B = 32, 16
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("hvf_trace.hip", "hvf_build.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2410_14128_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def distinct_per_ray(logt, cnt, shift: int):
+    """Distinct (word_index >> shift) values per ray, from the counting kernel's log."""
+    import torch
+    cap = logt.shape[1]
+    k = torch.clamp(cnt, max=cap)
+    valid = torch.arange(cap, device=logt.device)[None, :] < k[:, None]
+    v = torch.where(valid, logt >> shift, torch.full_like(logt, 2 ** 31 - 1))
+    v, _ = torch.sort(v, dim=1)
+    new = torch.ones_like(v, dtype=torch.bool)
+    new[:, 1:] = v[:, 1:] != v[:, :-1]
+    new &= v != 2 ** 31 - 1
+    return new.sum(dim=1)
+
+
+def byte_model(vol, rays_sample, cap=4096):
+    """Mean algorithmic bytes per ray: (word model, sector model), plus overflow count."""
+    import torch
+    hits, logt, cnt = vol.trace_count(rays_sample, cap=cap)
+    torch.cuda.synchronize()
+    words = distinct_per_ray(logt, cnt, 0).double()
+    sectors = distinct_per_ray(logt, cnt, 4).double()
+    over = int((cnt > cap).sum())
+    return (RAY_B + HIT_B + 4.0 * words.mean().item(), RAY_B + HIT_B + 64.0 * sectors.mean().item(),
+            float(cnt.double().mean().item()), over, hits)
+
+
+def traffic_from_profile(name: str):
+    """HBM bytes per ray from a committed rocprofv3 PMC summary, if it matches this kernel."""
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("workloads", {}).get(name)
+
+
+def time_launches(fn_list, steps, warmup):
+    """Run a step = every fn in fn_list once, timing each launch with events on the
+    current (launch) stream. Returns (ms_per_step, per-launch mean ms list)."""
+    import torch
+    for _ in range(warmup):
+        for fn in fn_list:
+            fn()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fn_list]
+          for _ in range(steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for s in range(steps):
+        for j, fn in enumerate(fn_list):
+            ev[s][j][0].record()
+            fn()
+            ev[s][j][1].record()
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    per = [float(np.mean([ev[s][j][0].elapsed_time(ev[s][j][1]) for s in range(steps)])) for j in range(len(fn_list))]
+    return total_ms / steps, per
+
+
+def run_surface512(args, torch, H, W, C):
+    cfg = C.SURF512
+    n = 1 << cfg["log2n"]
+    t0 = time.time()
+    codes = C.scene(cfg)
+    log(f"[bench] surface-512: {len(codes)} voxels ({len(codes) / n ** 3:.4%}) in {time.time() - t0:.1f}s")
+    views = [C.primary_rays(cfg, v) for v in range(cfg["views"])]
+    d_views = [torch.from_numpy(r).cuda() for r in views]
+    hits = [torch.empty((len(r), 4), dtype=torch.int32, device="cuda") for r in views]
+    vols = []
+    for spec in cfg["specs"]:
+        v = H.Volume(spec, codes)
+        v.upload()
+        vols.append(v)
+    torch.cuda.synchronize()
+    fns = []
+    for v in vols:
+        for j in range(len(views)):
+            fns.append(lambda v=v, j=j: v.trace(d_views[j], hits[j]))
+    log(f"[bench] surface-512: {len(fns)} launches per step; warmup {args.warmup}, timing {args.steps} steps")
+    ms, per = time_launches(fns, args.steps, args.warmup)
+    rays_per_step = sum(len(r) for r in views) * len(vols)
+    value = rays_per_step / (ms * 1e-3) / 1e6
+    log(f"[bench] surface-512: {ms:.2f} ms/step, {value:.1f} Mrays/s")
+    # Byte model per format on a seeded sample of each view's pixels.
+    rng = np.random.default_rng(12345)
+    sample_idx = [np.sort(rng.choice(len(r), size=min(args.sample, len(r)), replace=False)) for r in views]
+    per_format = []
+    alg_bytes = 0.0
+    for fi, (spec, v) in enumerate(zip(cfg["specs"], vols)):
+        info = v.info()
+        bw, bs, loads, over = [], [], [], 0
+        for j, r in enumerate(views):
+            smp = torch.from_numpy(r[sample_idx[j]]).cuda()
+            w_, s_, l_, o_, _ = byte_model(v, smp)
+            bw.append(w_)
+            bs.append(s_)
+            loads.append(l_)
+            over += o_
+        launch_ms = per[fi * len(views):(fi + 1) * len(views)]
+        nrays = sum(len(r) for r in views)
+        fmt_bytes = float(np.mean(bs)) * nrays
+        alg_bytes += fmt_bytes
+        fmt_ms = float(np.sum(launch_ms))
+        per_format.append({
+            "format": spec, "format_bytes": info["bytes"], "mrays_s": nrays / (fmt_ms * 1e-3) / 1e6,
+            "ms": fmt_ms, "B_ray_sector": round(float(np.mean(bs)), 1), "B_ray_word": round(float(np.mean(bw)), 1),
+            "loads_per_ray": round(float(np.mean(loads)), 1), "log_overflow_rays": over,
+            "roof_mrays_s": HBM_PEAK_GBS * 1e9 / float(np.mean(bs)) / 1e6,
+        })
+        per_format[-1]["frac_roofline"] = per_format[-1]["mrays_s"] / per_format[-1]["roof_mrays_s"]
+        log(f"[bench]   {spec:42s} {per_format[-1]['mrays_s']:8.1f} Mrays/s  B_ray {np.mean(bs):7.1f} B "
+            f"({per_format[-1]['frac_roofline']:.1%} of HBM roof)  size {info['bytes'] / 2 ** 20:.1f} MiB")
+    launch_total_ms = float(np.sum(per))
+    achieved = alg_bytes / (launch_total_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile("surface-512")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+    return {
+        "value": value, "ms": ms, "rays_per_step": rays_per_step, "roofline": roofline, "per_format": per_format,
+        "codes": codes, "views": views, "sample_idx": sample_idx, "occupancy": len(codes) / n ** 3,
+    }
+
+
+def run_surface2048(args, torch, H, W, C):
+    cfg = C.SURF2048
+    n = 1 << cfg["log2n"]
+    t0 = time.time()
+    codes = C.scene(cfg)
+    log(f"[bench] surface-2048: {len(codes)} voxels ({len(codes) / n ** 3:.4%}) in {time.time() - t0:.1f}s")
+    prim = C.primary_rays(cfg, 0)
+    d_prim = torch.from_numpy(prim).cuda()
+    out = []
+    for spec in cfg["specs"]:
+        v = H.Volume(spec, codes)
+        v.upload()
+        h = v.trace(d_prim)
+        torch.cuda.synchronize()
+        b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+        d_b = torch.from_numpy(b).cuda()
+        hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+        ms_p, _ = time_launches([lambda: v.trace(d_prim, h)], args.steps, args.warmup)
+        ms_b, _ = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
+        rng = np.random.default_rng(7)
+        sp = torch.from_numpy(prim[rng.choice(len(prim), min(args.sample, len(prim)), replace=False)]).cuda()
+        sb = torch.from_numpy(b[rng.choice(len(b), min(args.sample, len(b)), replace=False)]).cuda()
+        wp, bp, lp, _, _ = byte_model(v, sp)
+        wb, bb, lb, _, _ = byte_model(v, sb)
+        rec = {"format": spec, "format_bytes": v.info()["bytes"],
+               "primary": {"rays": len(prim), "ms": ms_p, "mrays_s": len(prim) / ms_p / 1e3, "B_ray_sector": bp,
+                           "B_ray_word": wp, "loads_per_ray": lp},
+               "incoherent": {"rays": len(b), "ms": ms_b, "mrays_s": len(b) / ms_b / 1e3, "B_ray_sector": bb,
+                              "B_ray_word": wb, "loads_per_ray": lb}}
+        for k in ("primary", "incoherent"):
+            r = rec[k]
+            r["achieved_gbs"] = r["B_ray_sector"] * r["rays"] / (r["ms"] * 1e-3) / 1e9
+            r["frac_roofline"] = r["achieved_gbs"] / HBM_PEAK_GBS
+            r.update({kk: round(vv, 4) for kk, vv in r.items() if isinstance(vv, float)})
+        log(f"[bench]   2048 {spec:36s} primary {rec['primary']['mrays_s']:8.1f} Mrays/s "
+            f"({rec['primary']['frac_roofline']:.1%})  incoherent {rec['incoherent']['mrays_s']:8.1f} Mrays/s "
+            f"({rec['incoherent']['frac_roofline']:.1%}, B_ray {bb:.0f} B)")
+        out.append(rec)
+        v.close()
+    return {"occupancy": len(codes) / n ** 3, "formats": out}
+
+
+def cpu_baseline(res512, C, budget_rays):
+    """The oracle, as it stands, on a bounded sample of the 512^3 workload."""
+    import oracle
+    cfg = C.SURF512
+    nthreads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(99)
+    total_rays, t_all, t_one = 0, 0.0, 0.0
+    per_fmt = max(1, budget_rays // (len(cfg["specs"]) * len(res512["views"])))
+    for spec in cfg["specs"]:
+        t0 = time.time()
+        ov = oracle.Volume(spec, res512["codes"])
+        log(f"[bench] oracle build {spec}: {time.time() - t0:.1f}s (not timed)")
+        for r in res512["views"]:
+            smp = r[np.sort(rng.choice(len(r), per_fmt, replace=False))]
+            t0 = time.perf_counter()
+            ov.trace(smp, nthreads=nthreads)
+            t_all += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            ov.trace(smp[: max(1, per_fmt // 8)], nthreads=1)
+            t_one += (time.perf_counter() - t0) * 8
+            total_rays += len(smp)
+        del ov
+    return {"value": round(total_rays / t_all / 1e6, 4), "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
+            "value_1core": round(total_rays / t_one / 1e6, 4),
+            "sample": f"{per_fmt} random pixels per view x 4 views x {len(cfg['specs'])} formats of the 512^3 "
+                      f"workload ({total_rays} rays); oracle built in the same formats; static thread split"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sample", type=int, default=16384, help="rays per view for the byte model")
+    ap.add_argument("--cpu-rays", type=int, default=200000, help="oracle sample size (rays)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-2048", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2410_14128_amd as H
+    import workloads as W
+    from workloads import configs as C
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    H.lib()
+    torch.cuda.set_device(0)
+    res = run_surface512(args, torch, H, W, C)
+    extra = None
+    if not args.no_2048:
+        extra = run_surface2048(args, torch, H, W, C)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(res, C, args.cpu_rays)
+    line = {
+        "metric": "Mrays/s (primary & incoherent) per format; % HBM roofline; p50/p99 ms served",
+        "value": round(res["value"], 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["ms"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded SDF shell scenes, seeded pinhole cameras)",
+        "config": {"workload": "surface-512: 512^3 shell of 32 spheres + 16 tori, 9 formats x 4 views x 1920x1080 "
+                               "primary rays", "rays_per_step": res["rays_per_step"],
+                   "occupancy": round(res["occupancy"], 5), "formats": C.SURF512["specs"]},
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+        "per_format": res["per_format"],
+        "surface_2048": extra,
+        "kernel_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,14 @@ hvf_status hvf_upload(hvf_volume* vol, void* hip_stream);
  * first if needed. n == 0 is a no-op. Errors: HVF_E_INPUT, HVF_E_DEVICE, HVF_E_NOMEM. */
 hvf_status hvf_trace(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* hip_stream);
 
+/* Counting variant of hvf_trace, for byte accounting: the same traversal and results,
+ * and for ray i the word index of each format load it makes, in order, in
+ * d_log[i * cap + k] for k < cap, with the total number of loads in d_count[i] (it may
+ * exceed cap; the log then holds the first cap). d_log (n * cap uint32) and d_count
+ * (n uint32) are caller-owned device buffers. Slower than hvf_trace; not for timing. */
+hvf_status hvf_trace_count(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
+                           uint32_t cap, uint32_t* d_count, void* hip_stream);
+
 /* Synchronous convenience form: host ray and hit arrays, staged through device memory. */
 hvf_status hvf_trace_host(hvf_volume* vol, const hvf_ray* rays, size_t n, hvf_hit* hits);
 

@@ -66,6 +66,8 @@ def lib():
         L.hvf_upload.argtypes = [vp, vp]
         L.hvf_trace.restype = i32
         L.hvf_trace.argtypes = [vp, vp, sz, vp, vp]
+        L.hvf_trace_count.restype = i32
+        L.hvf_trace_count.argtypes = [vp, vp, sz, vp, vp, ctypes.c_uint32, vp, vp]
         L.hvf_trace_host.restype = i32
         L.hvf_trace_host.argtypes = [vp, vp, sz, vp]
         L.hvf_info_get.restype = i32
@@ -181,6 +183,18 @@ class Volume:
         assert hits.is_cuda and hits.dtype == torch.int32 and hits.shape == (n, 4) and hits.is_contiguous()
         _check(lib().hvf_trace(self._h, rays.data_ptr(), n, hits.data_ptr(), _stream_ptr(stream)))
         return hits
+
+    def trace_count(self, rays, cap: int = 4096, stream=None):
+        """Counting variant: returns (hits, log int32 [n, cap] of word indices, count [n])."""
+        import torch
+        assert rays.is_cuda and rays.dtype == torch.float32 and rays.shape[-1] == 8 and rays.is_contiguous()
+        n = rays.shape[0]
+        hits = torch.empty((n, 4), dtype=torch.int32, device=rays.device)
+        log = torch.empty((n, cap), dtype=torch.int32, device=rays.device)
+        cnt = torch.empty((n,), dtype=torch.int32, device=rays.device)
+        _check(lib().hvf_trace_count(self._h, rays.data_ptr(), n, hits.data_ptr(), log.data_ptr(), cap,
+                                     cnt.data_ptr(), _stream_ptr(stream)))
+        return hits, log, cnt
 
     def trace_host(self, rays: np.ndarray) -> np.ndarray:
         """Synchronous host-array form: float32 [n, 8] in, int32 [n, 4] out."""

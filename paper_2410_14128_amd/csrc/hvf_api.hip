@@ -10,6 +10,8 @@
 
 namespace hvf {
 hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s);
+hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
+                              uint32_t cap, uint32_t* d_count, hipStream_t s);
 }
 
 namespace {
@@ -102,6 +104,17 @@ hvf_status hvf_trace(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_
   if (st != HVF_OK) return st;
   const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
   return hvf::launch_trace(F, d_rays, n, d_hits, (hipStream_t)stream);
+}
+
+hvf_status hvf_trace_count(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
+                           uint32_t cap, uint32_t* d_count, void* stream) {
+  if (!v) return fail(HVF_E_INPUT, "null volume");
+  if (n == 0) return HVF_OK;
+  if (!d_rays || !d_hits || !d_count || (cap && !d_log)) return fail(HVF_E_INPUT, "null buffer");
+  hvf_status st = hvf_upload(v, stream);
+  if (st != HVF_OK) return st;
+  const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  return hvf::launch_trace_count(F, d_rays, n, d_hits, d_log, cap, d_count, (hipStream_t)stream);
 }
 
 hvf_status hvf_trace_host(hvf_volume* v, const hvf_ray* rays, size_t n, hvf_hit* hits) {

@@ -108,10 +108,29 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
 
 __device__ __forceinline__ uint32_t tab(uint64_t t, int d) { return (uint32_t)(t >> (4 * d)) & 15u; }
 
+// Memory policies. Plain: just load. Counting: also log every word index a lane reads
+// (the byte accounting of the roofline counts distinct words / 64-byte sectors per ray).
+struct Plain {
+  __device__ __forceinline__ void note(uint32_t, uint32_t) {}
+};
+struct Counting {
+  uint32_t* log;  // this lane's log: cap entries
+  uint32_t cap;
+  uint32_t k = 0;
+  __device__ __forceinline__ void note(uint32_t idx, uint32_t nwords) {
+    for (uint32_t w = 0; w < nwords; ++w) {
+      if (k < cap) log[k] = idx + w;
+      ++k;
+    }
+  }
+};
+
 // Trace one lane's ray; writes the result to *out.
-__device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* stk, int4& out) {
+template <class Mem>
+__device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* stk, int4& out, Mem& mem) {
   const uint32_t* __restrict__ buf = F.buf;
   const uint32_t root = buf[0];  // word 0: pointer to the root sub-volume; 0 = empty
+  mem.note(0, 1);
   if (root == 0) return;
   int p[3];
   const int cs0 = (int)tab(F.cs_tab, 0);
@@ -123,10 +142,12 @@ __device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* s
     const uint32_t hk = tab(F.hk_tab, 0);
     if (hk == HK_SVO) {
       const uint2 h = *reinterpret_cast<const uint2*>(buf + root);
+      mem.note(root, 2);
       base = h.x;
       valid = h.y & 0xFFu;
     } else if (hk == HK_DAG) {
       valid = buf[root] & 0xFFu;
+      mem.note(root, 1);
       base = root + 1;
     }
   }
@@ -149,7 +170,9 @@ __device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* s
       const uint32_t cy = ((uint32_t)p[1] >> cs) & ((1u << wy) - 1u);
       const uint32_t cz = ((uint32_t)p[2] >> cs) & ((1u << wz) - 1u);
       if (nk == NK_RAW_PTR) {
-        child = buf[base + (cx | (cy << wx) | (cz << (wx + wy)))];
+        const uint32_t ix = base + (cx | (cy << wx) | (cz << (wx + wy)));
+        child = buf[ix];
+        mem.note(ix, 1);
         occ = child != 0u;
       } else {
         uint32_t word_ix, bit;
@@ -168,6 +191,7 @@ __device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* s
           bit = (uint32_t)m & 31u;
         }
         occ = (buf[base + word_ix] >> bit) & 1u;
+        mem.note(base + word_ix, 1);
       }
     } else {
       const uint32_t oct = (((uint32_t)p[0] >> cs) & 1u) | ((((uint32_t)p[1] >> cs) & 1u) << 1) |
@@ -175,7 +199,12 @@ __device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* s
       occ = (valid >> oct) & 1u;
       if (occ && nk != NK_OCT_FINAL) {
         const uint32_t rank = __popc(valid & ((1u << oct) - 1u));
-        child = (nk == NK_SVO_INNER) ? base + 2u * rank : buf[base + rank];
+        if (nk == NK_SVO_INNER) {
+          child = base + 2u * rank;
+        } else {
+          child = buf[base + rank];
+          mem.note(base + rank, 1);
+        }
       }
     }
     if (occ) {
@@ -200,10 +229,12 @@ __device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* s
           base = child;
         } else if (hk == HK_SVO) {
           const uint2 h = *reinterpret_cast<const uint2*>(buf + child);
+          mem.note(child, 2);
           base = h.x;
           valid = h.y & 0xFFu;
         } else {
           valid = buf[child] & 0xFFu;
+          mem.note(child, 1);
           base = child + 1u;
         }
         const int ncs = (int)tab(F.cs_tab, d);
@@ -262,8 +293,27 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
   int4 out = make_int4(-1, -1, -1, __float_as_int(INFINITY));
   Lane L;
-  if (setup(r0, r1, F.ext, L)) walk(F, L, stk_all + threadIdx.x, out);
+  Plain mem;
+  if (setup(r0, r1, F.ext, L)) walk(F, L, stk_all + threadIdx.x, out, mem);
   hits[i] = out;
+}
+
+// Same traversal, logging the word index of every format load: log[i * cap + k] for the
+// first cap loads of ray i; count[i] = number of loads (may exceed cap).
+__global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                            int4* __restrict__ hits, uint32_t n,
+                                                            uint32_t* __restrict__ log, uint32_t cap,
+                                                            uint32_t* __restrict__ count) {
+  extern __shared__ uint2 stk_all[];
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  int4 out = make_int4(-1, -1, -1, __float_as_int(INFINITY));
+  Lane L;
+  Counting mem{log + (size_t)i * cap, cap};
+  if (setup(r0, r1, F.ext, L)) walk(F, L, stk_all + threadIdx.x, out, mem);
+  hits[i] = out;
+  count[i] = mem.k;
 }
 
 }  // namespace
@@ -281,6 +331,25 @@ hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     hvf_set_error(std::string("trace launch failed: ") + hipGetErrorString(e));
+    return HVF_E_DEVICE;
+  }
+  return HVF_OK;
+}
+
+hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
+                              uint32_t cap, uint32_t* d_count, hipStream_t s) {
+  if (n == 0) return HVF_OK;
+  if (n >= (1ull << 32)) {
+    hvf_set_error("at most 2^32 - 1 rays per call");
+    return HVF_E_INPUT;
+  }
+  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  const size_t lds = (size_t)F.ndepth * BLOCK * sizeof(uint2);
+  hipLaunchKernelGGL(trace_count_kernel, dim3(grid), dim3(BLOCK), lds, s, F, reinterpret_cast<const float4*>(d_rays),
+                     reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log, cap, d_count);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    hvf_set_error(std::string("counting trace launch failed: ") + hipGetErrorString(e));
     return HVF_E_DEVICE;
   }
   return HVF_OK;

@@ -1,0 +1,142 @@
+"""GPU parity at the benchmark's full sizes and launch configuration, on sampled rays.
+
+* 512^3 surface volume, nine formats: every 1080p view is traced in full on the GPU
+  (as the benchmark does); the oracle, built in the same format, traces a seeded sample
+  of each view; one low-resolution view is compared in full. The plain Raw format
+  R(9,9,9) is checked against the oracle's flat DDA, which is that format's traversal.
+* 2048^3 surface volume, both formats: 1080p primary rays traced in full on the GPU,
+  a sample checked against the oracle; bounce rays are generated from the ORACLE's hits
+  on that sample and traced by both. The oracle traces the same volume built as G(11):
+  every format of one volume has the same first hits (pinned on the CPU), and G(11) is
+  the format the oracle builds in seconds at this size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_util import compare
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2410_14128_amd as H
+    H.lib()
+    return H
+
+
+@pytest.fixture(scope="module")
+def surf512():
+    cfg = C.SURF512
+    codes = C.scene(cfg)
+    views = [C.primary_rays(cfg, v) for v in range(cfg["views"])]
+    return cfg, codes, views
+
+
+def _dense(codes, log2n):
+    n = 1 << log2n
+    xyz = W.morton_decode(codes)
+    g = np.zeros((n, n, n), np.uint8)
+    g[xyz[:, 2], xyz[:, 1], xyz[:, 0]] = 1
+    return g
+
+
+def _trace_full(vol, rays):
+    import torch
+    d = torch.from_numpy(rays).cuda()
+    h = vol.trace(d)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+@pytest.mark.parametrize("spec", C.SURF512["specs"])
+def test_surface512(H, surf512, spec):
+    cfg, codes, views = surf512
+    vol = H.Volume(spec, codes)
+    if spec.startswith("R(9,9,9)"):
+        dense = _dense(codes, 9)
+        ref_fn = lambda r: oracle.flat_dda(dense, (9, 9, 9), r)
+    else:
+        ov = oracle.Volume(spec, codes)
+        ref_fn = lambda r: ov.trace(r, nthreads=8)
+    rng = np.random.default_rng(2024)
+    hits_total = 0
+    for j, rays in enumerate(views):
+        got = _trace_full(vol, rays)
+        idx = rng.choice(len(rays), 6000, replace=False)
+        assert compare(got[idx], ref_fn(rays[idx]), f"{spec} view {j}") == 0
+        hits_total += int((got[:, 0] >= 0).sum())
+    assert hits_total > 0.1 * sum(len(r) for r in views)
+    small = C.primary_rays(cfg, 1, 240, 135)
+    assert compare(_trace_full(vol, small), ref_fn(small), f"{spec} 240x135") == 0
+
+
+@pytest.fixture(scope="module")
+def surf2048():
+    cfg = C.SURF2048
+    codes = C.scene(cfg)
+    prim = C.primary_rays(cfg, 0)
+    ov = oracle.Volume("G(11) --whole-level-dedup", codes)
+    rng = np.random.default_rng(77)
+    idx = np.sort(rng.choice(len(prim), 20000, replace=False))
+    ref_p = ov.trace(prim[idx], nthreads=8)
+    bounce, src = W.bounce_rays(cfg["bounce_seed"], prim[idx], ref_p)
+    ref_b = ov.trace(bounce, nthreads=8)
+    rnd = W.random_rays(5, (2048,) * 3, 20000)
+    ref_r = ov.trace(rnd, nthreads=8)
+    return cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r
+
+
+@pytest.mark.parametrize("spec", C.SURF2048["specs"])
+def test_surface2048(H, surf2048, spec):
+    cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
+    vol = H.Volume(spec, codes)
+    got = _trace_full(vol, prim)
+    assert compare(got[idx], ref_p, f"{spec} primary") == 0
+    assert (ref_p[:, 0] >= 0).mean() > 0.1 and len(bounce) > 2000
+    assert compare(_trace_full(vol, bounce), ref_b, f"{spec} bounce") == 0
+    assert compare(_trace_full(vol, rnd), ref_r, f"{spec} random") == 0
+
+
+def test_counting_variant_matches_plain(H, surf512):
+    import torch
+    cfg, codes, views = surf512
+    vol = H.Volume("G(6) R(3,3,3) --whole-level-dedup", codes)
+    rays = torch.from_numpy(views[0][::97].copy()).cuda()
+    plain = vol.trace(rays)
+    hits, logt, cnt = vol.trace_count(rays, cap=2048)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, hits)
+    c = cnt.cpu().numpy()
+    assert c.max() <= 2048
+    # a ray that misses the root box reads nothing; every other ray reads word 0 first
+    entered = c > 0
+    assert entered.mean() > 0.3 and np.all(c[hits.cpu().numpy()[:, 0] >= 0] >= 2)
+    lg = logt.cpu().numpy()
+    nw = vol.info()["num_words"]
+    for i in np.nonzero(entered)[0][::101]:
+        assert lg[i, 0] == 0  # the root pointer
+        assert np.all(lg[i, : c[i]] < nw)
+
+
+def test_max_extent_volume(H):
+    """The largest supported side (2^16): a few voxels in G(16), rays from outside."""
+    pts = np.array([[0, 0, 0], [65535, 65535, 65535], [40000, 123, 65000], [32768, 32767, 32768]], np.int32)
+    codes = np.sort(W.morton_encode(pts))
+    spec = "G(16)"
+    rays = []
+    for p in pts:
+        c = p.astype(np.float64) + 0.5
+        o = c + np.array([-70000.0, 3000.0, -1234.0])
+        d = (c - o) / np.linalg.norm(c - o)
+        rays.append([o[0], o[1], o[2], 0, d[0], d[1], d[2], np.inf])
+    rays = np.array(rays, np.float32)
+    got = _trace_full(H.Volume(spec, codes), rays)
+    ref = oracle.brute(codes, (16, 16, 16), rays)
+    assert compare(got, ref, "max extent") == 0
+    assert np.all(got[:, 0] >= 0)
