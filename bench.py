@@ -129,7 +129,19 @@ def run_surface512(args, torch, H, W, C):
     for v in vols:
         for j in range(len(views)):
             fns.append(lambda v=v, j=j: v.trace(d_views[j], hits[j]))
-    log(f"[bench] surface-512: {len(fns)} launches per step; warmup {args.warmup}, timing {args.steps} steps")
+    # Untuned reference pass (one lane per ray), then autotune each format on a held-out
+    # view (a fifth seeded camera at 960x540) and time the tuned schedules.
+    ms_plain, per_plain = time_launches(fns, args.steps, args.warmup)
+    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"], 960, 540)).cuda()
+    scheds = []
+    for v in vols:
+        if args.no_tune:
+            scheds.append(H.schedule_dict(v.get_schedule()))
+        else:
+            scheds.append(H.schedule_dict(v.autotune(tune)))
+    del tune
+    log(f"[bench] surface-512: {len(fns)} launches per step; warmup {args.warmup}, timing {args.steps} steps; "
+        f"untuned {ms_plain:.2f} ms/step")
     ms, per = time_launches(fns, args.steps, args.warmup)
     rays_per_step = sum(len(r) for r in views) * len(vols)
     value = rays_per_step / (ms * 1e-3) / 1e6
@@ -143,6 +155,9 @@ def run_surface512(args, torch, H, W, C):
         info = v.info()
         bw, bs, loads, over = [], [], [], 0
         for j, r in enumerate(views):
+            if args.sample <= 0:
+                bw.append(float("nan")), bs.append(float("nan")), loads.append(float("nan"))
+                continue
             smp = torch.from_numpy(r[sample_idx[j]]).cuda()
             w_, s_, l_, o_, _ = byte_model(v, smp)
             bw.append(w_)
@@ -154,14 +169,17 @@ def run_surface512(args, torch, H, W, C):
         fmt_bytes = float(np.mean(bs)) * nrays
         alg_bytes += fmt_bytes
         fmt_ms = float(np.sum(launch_ms))
+        plain_ms = float(np.sum(per_plain[fi * len(views):(fi + 1) * len(views)]))
         per_format.append({
             "format": spec, "format_bytes": info["bytes"], "mrays_s": nrays / (fmt_ms * 1e-3) / 1e6,
+            "mrays_s_untuned": nrays / (plain_ms * 1e-3) / 1e6, "schedule": scheds[fi],
             "ms": fmt_ms, "B_ray_sector": round(float(np.mean(bs)), 1), "B_ray_word": round(float(np.mean(bw)), 1),
             "loads_per_ray": round(float(np.mean(loads)), 1), "log_overflow_rays": over,
             "roof_mrays_s": HBM_PEAK_GBS * 1e9 / float(np.mean(bs)) / 1e6,
         })
         per_format[-1]["frac_roofline"] = per_format[-1]["mrays_s"] / per_format[-1]["roof_mrays_s"]
-        log(f"[bench]   {spec:42s} {per_format[-1]['mrays_s']:8.1f} Mrays/s  B_ray {np.mean(bs):7.1f} B "
+        log(f"[bench]   {spec:42s} {per_format[-1]['mrays_s']:8.1f} Mrays/s (untuned "
+            f"{per_format[-1]['mrays_s_untuned']:7.1f}, {scheds[fi]})  B_ray {np.mean(bs):7.1f} B "
             f"({per_format[-1]['frac_roofline']:.1%} of HBM roof)  size {info['bytes'] / 2 ** 20:.1f} MiB")
     launch_total_ms = float(np.sum(per))
     achieved = alg_bytes / (launch_total_ms * 1e-3) / 1e9
@@ -170,7 +188,8 @@ def run_surface512(args, torch, H, W, C):
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
     return {
-        "value": value, "ms": ms, "rays_per_step": rays_per_step, "roofline": roofline, "per_format": per_format,
+        "value": value, "ms": ms, "ms_untuned": ms_plain, "rays_per_step": rays_per_step, "roofline": roofline,
+        "per_format": per_format,
         "codes": codes, "views": views, "sample_idx": sample_idx, "occupancy": len(codes) / n ** 3,
     }
 
@@ -183,35 +202,50 @@ def run_surface2048(args, torch, H, W, C):
     log(f"[bench] surface-2048: {len(codes)} voxels ({len(codes) / n ** 3:.4%}) in {time.time() - t0:.1f}s")
     prim = C.primary_rays(cfg, 0)
     d_prim = torch.from_numpy(prim).cuda()
+    held = C.primary_rays(cfg, 1, 960, 540)
+    d_held = torch.from_numpy(held).cuda()
     out = []
     for spec in cfg["specs"]:
         v = H.Volume(spec, codes)
         v.upload()
         h = v.trace(d_prim)
+        hh = v.trace(d_held)
         torch.cuda.synchronize()
         b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+        bh, _ = W.bounce_rays(cfg["bounce_seed"] + 1, held, hh.cpu().numpy())
         d_b = torch.from_numpy(b).cuda()
         hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+        plain = H.schedule()
+        ms_p0, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
+        ms_b0, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
+        sched_p = H.schedule_dict(v.autotune(d_held)) if not args.no_tune else H.schedule_dict(plain)
         ms_p, _ = time_launches([lambda: v.trace(d_prim, h)], args.steps, args.warmup)
+        sched_b = H.schedule_dict(v.autotune(torch.from_numpy(bh).cuda())) if not args.no_tune else sched_p
         ms_b, _ = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
         rng = np.random.default_rng(7)
-        sp = torch.from_numpy(prim[rng.choice(len(prim), min(args.sample, len(prim)), replace=False)]).cuda()
-        sb = torch.from_numpy(b[rng.choice(len(b), min(args.sample, len(b)), replace=False)]).cuda()
-        wp, bp, lp, _, _ = byte_model(v, sp)
-        wb, bb, lb, _, _ = byte_model(v, sb)
+        if args.sample > 0:
+            sp = torch.from_numpy(prim[rng.choice(len(prim), min(args.sample, len(prim)), replace=False)]).cuda()
+            sb = torch.from_numpy(b[rng.choice(len(b), min(args.sample, len(b)), replace=False)]).cuda()
+            wp, bp, lp, _, _ = byte_model(v, sp)
+            wb, bb, lb, _, _ = byte_model(v, sb)
+        else:
+            wp = bp = lp = wb = bb = lb = float("nan")
         rec = {"format": spec, "format_bytes": v.info()["bytes"],
                "primary": {"rays": len(prim), "ms": ms_p, "mrays_s": len(prim) / ms_p / 1e3, "B_ray_sector": bp,
-                           "B_ray_word": wp, "loads_per_ray": lp},
+                           "B_ray_word": wp, "loads_per_ray": lp, "schedule": sched_p,
+                           "mrays_s_untuned": len(prim) / ms_p0 / 1e3},
                "incoherent": {"rays": len(b), "ms": ms_b, "mrays_s": len(b) / ms_b / 1e3, "B_ray_sector": bb,
-                              "B_ray_word": wb, "loads_per_ray": lb}}
+                              "B_ray_word": wb, "loads_per_ray": lb, "schedule": sched_b,
+                              "mrays_s_untuned": len(b) / ms_b0 / 1e3}}
         for k in ("primary", "incoherent"):
             r = rec[k]
             r["achieved_gbs"] = r["B_ray_sector"] * r["rays"] / (r["ms"] * 1e-3) / 1e9
             r["frac_roofline"] = r["achieved_gbs"] / HBM_PEAK_GBS
             r.update({kk: round(vv, 4) for kk, vv in r.items() if isinstance(vv, float)})
         log(f"[bench]   2048 {spec:36s} primary {rec['primary']['mrays_s']:8.1f} Mrays/s "
-            f"({rec['primary']['frac_roofline']:.1%})  incoherent {rec['incoherent']['mrays_s']:8.1f} Mrays/s "
-            f"({rec['incoherent']['frac_roofline']:.1%}, B_ray {bb:.0f} B)")
+            f"({rec['primary']['frac_roofline']:.1%}, untuned {rec['primary']['mrays_s_untuned']:.1f}, {sched_p})  "
+            f"incoherent {rec['incoherent']['mrays_s']:8.1f} Mrays/s ({rec['incoherent']['frac_roofline']:.1%}, "
+            f"B_ray {bb:.0f} B, untuned {rec['incoherent']['mrays_s_untuned']:.1f}, {sched_b})")
         out.append(rec)
         v.close()
     return {"occupancy": len(codes) / n ** 3, "formats": out}
@@ -254,6 +288,9 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=200000, help="oracle sample size (rays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2048", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
+    ap.add_argument("--only", choices=["surface512", "surface2048"], default=None,
+                    help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only",
@@ -268,7 +305,12 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     H.lib()
     torch.cuda.set_device(0)
+    if args.only == "surface2048":
+        run_surface2048(args, torch, H, W, C)
+        return
     res = run_surface512(args, torch, H, W, C)
+    if args.only == "surface512":
+        return
     extra = None
     if not args.no_2048:
         extra = run_surface2048(args, torch, H, W, C)

@@ -80,6 +80,23 @@ typedef struct hvf_info {
   uint64_t num_voxels;                  /* occupied voxels */
 } hvf_info;
 
+/* How a trace is scheduled on the device. Results never depend on it.
+ * persistent = 0: one lane per ray, one launch-sized grid.
+ * persistent = 1: a grid sized to the device; each wave refills its idle lanes from a
+ *   global ray counter whenever at least `refill` of its 64 lanes are idle, checking after
+ *   every `inner` traversal steps.
+ * sort = 1: trace rays in the order of a coherence key (origin cell of side 2^sort_bits
+ *   voxels in Morton order, then direction octant) computed and sorted on the device;
+ *   results are still written at each ray's own index. */
+typedef struct hvf_schedule {
+  int32_t persistent;
+  int32_t refill;
+  int32_t inner;
+  int32_t sort;
+  int32_t sort_bits;
+  int32_t reserved[3];
+} hvf_schedule;
+
 /* Build a volume on the host (Sec. 4.1).
  * format_spec: e.g. "G(7) R(4,4,4) --whole-level-dedup"; R(k^3) means R(k,k,k).
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
@@ -99,13 +116,31 @@ hvf_status hvf_upload(hvf_volume* vol, void* hip_stream);
  * first if needed. n == 0 is a no-op. Errors: HVF_E_INPUT, HVF_E_DEVICE, HVF_E_NOMEM. */
 hvf_status hvf_trace(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* hip_stream);
 
+/* hvf_trace with an explicit schedule (NULL: the volume's current schedule). */
+hvf_status hvf_trace_sched(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                           const hvf_schedule* sched, void* hip_stream);
+
+/* Get / set the schedule hvf_trace uses for this volume (initially one lane per ray).
+ * Not thread-safe against concurrent traces of the same volume. */
+hvf_status hvf_get_schedule(const hvf_volume* vol, hvf_schedule* out);
+hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
+
+/* Autotune: time candidate schedules (one lane per ray; persistent with refill
+ * thresholds 8/16/32 and 4 or 16 steps between checks; sorted with cell sides 2^2, 2^4,
+ * 2^6) on the caller's device ray sample, pick the fastest, store it as the volume's
+ * schedule and copy it to *out (may be NULL). d_hits_scratch: n device hits, overwritten.
+ * Synchronises hip_stream. Results never depend on the schedule chosen. */
+hvf_status hvf_autotune(hvf_volume* vol, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits_scratch,
+                        hvf_schedule* out, void* hip_stream);
+
 /* Counting variant of hvf_trace, for byte accounting: the same traversal and results,
  * and for ray i the word index of each format load it makes, in order, in
  * d_log[i * cap + k] for k < cap, with the total number of loads in d_count[i] (it may
- * exceed cap; the log then holds the first cap). d_log (n * cap uint32) and d_count
- * (n uint32) are caller-owned device buffers. Slower than hvf_trace; not for timing. */
+ * exceed cap; the log then holds the first cap), and, if d_steps is not NULL, the number
+ * of traversal steps in d_steps[i]. d_log (n * cap uint32), d_count and d_steps (n uint32)
+ * are caller-owned device buffers. Slower than hvf_trace; not for timing. */
 hvf_status hvf_trace_count(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
-                           uint32_t cap, uint32_t* d_count, void* hip_stream);
+                           uint32_t cap, uint32_t* d_count, uint32_t* d_steps, void* hip_stream);
 
 /* Synchronous convenience form: host ray and hit arrays, staged through device memory. */
 hvf_status hvf_trace_host(hvf_volume* vol, const hvf_ray* rays, size_t n, hvf_hit* hits);

@@ -48,6 +48,20 @@ class hvf_info(ctypes.Structure):
     ]
 
 
+class hvf_schedule(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("refill", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("sort", ctypes.c_int32), ("sort_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+def schedule(persistent: int = 0, refill: int = 16, inner: int = 8, sort: int = 0, sort_bits: int = 4) -> hvf_schedule:
+    """A device schedule for a trace (results never depend on it)."""
+    return hvf_schedule(persistent, refill, inner, sort, sort_bits)
+
+
+def schedule_dict(s: hvf_schedule) -> dict:
+    return {"persistent": s.persistent, "refill": s.refill, "inner": s.inner, "sort": s.sort, "sort_bits": s.sort_bits}
+
+
 _lib = None
 
 
@@ -66,8 +80,16 @@ def lib():
         L.hvf_upload.argtypes = [vp, vp]
         L.hvf_trace.restype = i32
         L.hvf_trace.argtypes = [vp, vp, sz, vp, vp]
+        L.hvf_trace_sched.restype = i32
+        L.hvf_trace_sched.argtypes = [vp, vp, sz, vp, ctypes.POINTER(hvf_schedule), vp]
+        L.hvf_get_schedule.restype = i32
+        L.hvf_get_schedule.argtypes = [vp, ctypes.POINTER(hvf_schedule)]
+        L.hvf_set_schedule.restype = i32
+        L.hvf_set_schedule.argtypes = [vp, ctypes.POINTER(hvf_schedule)]
+        L.hvf_autotune.restype = i32
+        L.hvf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(hvf_schedule), vp]
         L.hvf_trace_count.restype = i32
-        L.hvf_trace_count.argtypes = [vp, vp, sz, vp, vp, ctypes.c_uint32, vp, vp]
+        L.hvf_trace_count.argtypes = [vp, vp, sz, vp, vp, ctypes.c_uint32, vp, vp, vp]
         L.hvf_trace_host.restype = i32
         L.hvf_trace_host.argtypes = [vp, vp, sz, vp]
         L.hvf_info_get.restype = i32
@@ -170,10 +192,11 @@ class Volume:
     def upload(self, stream=None):
         _check(lib().hvf_upload(self._h, _stream_ptr(stream)))
 
-    def trace(self, rays, hits=None, stream=None):
+    def trace(self, rays, hits=None, stream=None, sched: hvf_schedule | None = None):
         """Trace device rays (torch float32 [n, 8] on the GPU) into hits (int32 [n, 4]).
 
-        Asynchronous on ``stream`` (default: torch's current stream). Returns ``hits``.
+        Asynchronous on ``stream`` (default: torch's current stream). ``sched`` overrides
+        the volume's schedule for this call. Returns ``hits``.
         """
         import torch
         assert rays.is_cuda and rays.dtype == torch.float32 and rays.shape[-1] == 8 and rays.is_contiguous()
@@ -181,20 +204,45 @@ class Volume:
         if hits is None:
             hits = torch.empty((n, 4), dtype=torch.int32, device=rays.device)
         assert hits.is_cuda and hits.dtype == torch.int32 and hits.shape == (n, 4) and hits.is_contiguous()
-        _check(lib().hvf_trace(self._h, rays.data_ptr(), n, hits.data_ptr(), _stream_ptr(stream)))
+        if sched is None:
+            _check(lib().hvf_trace(self._h, rays.data_ptr(), n, hits.data_ptr(), _stream_ptr(stream)))
+        else:
+            _check(lib().hvf_trace_sched(self._h, rays.data_ptr(), n, hits.data_ptr(), ctypes.byref(sched),
+                                         _stream_ptr(stream)))
         return hits
 
-    def trace_count(self, rays, cap: int = 4096, stream=None):
-        """Counting variant: returns (hits, log int32 [n, cap] of word indices, count [n])."""
+    def autotune(self, sample_rays, stream=None) -> hvf_schedule:
+        """Pick the fastest schedule on a device ray sample; it becomes this volume's."""
+        import torch
+        assert sample_rays.is_cuda and sample_rays.dtype == torch.float32 and sample_rays.is_contiguous()
+        n = sample_rays.shape[0]
+        scratch = torch.empty((n, 4), dtype=torch.int32, device=sample_rays.device)
+        out = hvf_schedule()
+        _check(lib().hvf_autotune(self._h, sample_rays.data_ptr(), n, scratch.data_ptr(), ctypes.byref(out),
+                                  _stream_ptr(stream)))
+        return out
+
+    def get_schedule(self) -> hvf_schedule:
+        s = hvf_schedule()
+        _check(lib().hvf_get_schedule(self._h, ctypes.byref(s)))
+        return s
+
+    def set_schedule(self, sched: hvf_schedule):
+        _check(lib().hvf_set_schedule(self._h, ctypes.byref(sched)))
+
+    def trace_count(self, rays, cap: int = 4096, stream=None, steps: bool = False):
+        """Counting variant: returns (hits, log int32 [n, cap] of word indices, count [n]),
+        plus per-ray traversal step counts when ``steps``."""
         import torch
         assert rays.is_cuda and rays.dtype == torch.float32 and rays.shape[-1] == 8 and rays.is_contiguous()
         n = rays.shape[0]
         hits = torch.empty((n, 4), dtype=torch.int32, device=rays.device)
         log = torch.empty((n, cap), dtype=torch.int32, device=rays.device)
         cnt = torch.empty((n,), dtype=torch.int32, device=rays.device)
+        st = torch.empty((n,), dtype=torch.int32, device=rays.device) if steps else None
         _check(lib().hvf_trace_count(self._h, rays.data_ptr(), n, hits.data_ptr(), log.data_ptr(), cap,
-                                     cnt.data_ptr(), _stream_ptr(stream)))
-        return hits, log, cnt
+                                     cnt.data_ptr(), st.data_ptr() if steps else None, _stream_ptr(stream)))
+        return (hits, log, cnt, st) if steps else (hits, log, cnt)
 
     def trace_host(self, rays: np.ndarray) -> np.ndarray:
         """Synchronous host-array form: float32 [n, 8] in, int32 [n, 4] out."""

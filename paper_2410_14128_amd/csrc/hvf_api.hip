@@ -5,13 +5,20 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hvf_internal.h"
 
 namespace hvf {
 hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s);
 hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
-                              uint32_t cap, uint32_t* d_count, hipStream_t s);
+                              uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s);
+hvf_status launch_trace_persistent(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                                   uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
+hvf_status persistent_grid(const DevFormat& F, unsigned* grid);
+hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule& sc,
+                        uint32_t* d_counter, hipStream_t s);
 }
 
 namespace {
@@ -96,25 +103,120 @@ hvf_status hvf_upload(hvf_volume* v, void* stream) {
   return HVF_OK;
 }
 
-hvf_status hvf_trace(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* stream) {
+namespace {
+hvf_status check_sched(const hvf_schedule& sc) {
+  if (sc.persistent < 0 || sc.persistent > 1 || sc.refill < 1 || sc.refill > 64 || sc.inner < 1 || sc.inner > 4096 ||
+      sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16)
+    return fail(HVF_E_INPUT, "schedule field out of range");
+  return HVF_OK;
+}
+}  // namespace
+
+hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule* sched,
+                           void* stream) {
   if (!v) return fail(HVF_E_INPUT, "null volume");
+  const hvf_schedule sc = sched ? *sched : v->sched;
+  hvf_status st = check_sched(sc);
+  if (st != HVF_OK) return st;
   if (n == 0) return HVF_OK;
   if (!d_rays || !d_hits) return fail(HVF_E_INPUT, "null ray or hit buffer");
-  hvf_status st = hvf_upload(v, stream);
+  st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
   const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
-  return hvf::launch_trace(F, d_rays, n, d_hits, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* counter = nullptr;
+  if (sc.persistent || sc.sort) {
+    if (!v->dcounters) {
+      hipError_t e = hipMalloc(&v->dcounters, HVF_NUM_COUNTERS * 2 * sizeof(uint32_t));
+      if (e != hipSuccess) {
+        v->dcounters = nullptr;
+        return hip_fail(e, "hipMalloc of ray counters");
+      }
+    }
+    counter = v->dcounters + 2 * (v->counter_next++ % HVF_NUM_COUNTERS);
+  }
+  if (sc.sort) return hvf::trace_sorted(F, d_rays, n, d_hits, sc, counter, s);
+  if (!sc.persistent) return hvf::launch_trace(F, d_rays, n, d_hits, s);
+  unsigned grid = 0;
+  st = hvf::persistent_grid(F, &grid);
+  if (st != HVF_OK) return st;
+  st = hvf::launch_fill_u32(counter, 0u, 1, s);
+  if (st != HVF_OK) return st;
+  return hvf::launch_trace_persistent(F, d_rays, n, d_hits, counter, (uint32_t)sc.refill, (uint32_t)sc.inner, grid, s);
+}
+
+hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits, hvf_schedule* out,
+                        void* stream) {
+  if (!v || !d_sample || !d_hits || n == 0) return fail(HVF_E_INPUT, "autotune needs a volume and a non-empty sample");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hvf_schedule> cand;
+  cand.push_back(hvf_schedule{0, 16, 8, 0, 4, {0, 0, 0}});
+  for (int refill : {8, 16, 32})
+    for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, {0, 0, 0}});
+  for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, {0, 0, 0}});
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HVF_E_DEVICE, "hipEventCreate failed");
+  }
+  float best_ms = 1e30f;
+  hvf_schedule best = cand[0];
+  hvf_status st = HVF_OK;
+  for (const hvf_schedule& c : cand) {
+    st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);  // warm-up (uploads on first use)
+    if (st != HVF_OK) break;
+    float tot = 0.0f;
+    const int reps = 3;
+    bool ok = hipEventRecord(e0, s) == hipSuccess;
+    for (int r = 0; r < reps && st == HVF_OK; ++r) st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&tot, e0, e1) == hipSuccess;
+    if (st != HVF_OK) break;
+    if (!ok) {
+      st = fail(HVF_E_DEVICE, "event timing failed during autotune");
+      break;
+    }
+    if (tot / reps < best_ms) {
+      best_ms = tot / reps;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HVF_OK) return st;
+  v->sched = best;
+  if (out) *out = best;
+  return HVF_OK;
+}
+
+hvf_status hvf_trace(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* stream) {
+  return hvf_trace_sched(v, d_rays, n, d_hits, nullptr, stream);
+}
+
+hvf_status hvf_get_schedule(const hvf_volume* v, hvf_schedule* out) {
+  if (!v || !out) return fail(HVF_E_INPUT, "null argument");
+  *out = v->sched;
+  return HVF_OK;
+}
+
+hvf_status hvf_set_schedule(hvf_volume* v, const hvf_schedule* sched) {
+  if (!v || !sched) return fail(HVF_E_INPUT, "null argument");
+  hvf_status st = check_sched(*sched);
+  if (st != HVF_OK) return st;
+  v->sched = *sched;
+  return HVF_OK;
 }
 
 hvf_status hvf_trace_count(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
-                           uint32_t cap, uint32_t* d_count, void* stream) {
+                           uint32_t cap, uint32_t* d_count, uint32_t* d_steps, void* stream) {
   if (!v) return fail(HVF_E_INPUT, "null volume");
   if (n == 0) return HVF_OK;
   if (!d_rays || !d_hits || !d_count || (cap && !d_log)) return fail(HVF_E_INPUT, "null buffer");
   hvf_status st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
   const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
-  return hvf::launch_trace_count(F, d_rays, n, d_hits, d_log, cap, d_count, (hipStream_t)stream);
+  return hvf::launch_trace_count(F, d_rays, n, d_hits, d_log, cap, d_count, d_steps, (hipStream_t)stream);
 }
 
 hvf_status hvf_trace_host(hvf_volume* v, const hvf_ray* rays, size_t n, hvf_hit* hits) {
@@ -284,15 +386,13 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
 
 void hvf_free(hvf_volume* v) {
   if (!v) return;
-  if (v->dbuf) {
+  if (v->dbuf || v->dcounters) {
     int cur = 0;
-    if (hipGetDevice(&cur) == hipSuccess && cur != v->device) {
-      (void)hipSetDevice(v->device);
-      (void)hipFree(v->dbuf);
-      (void)hipSetDevice(cur);
-    } else {
-      (void)hipFree(v->dbuf);
-    }
+    const bool other = hipGetDevice(&cur) == hipSuccess && v->device >= 0 && cur != v->device;
+    if (other) (void)hipSetDevice(v->device);
+    if (v->dbuf) (void)hipFree(v->dbuf);
+    if (v->dcounters) (void)hipFree(v->dcounters);
+    if (other) (void)hipSetDevice(cur);
   }
   delete v;
 }

@@ -8,8 +8,9 @@
 // (Sec. 4.3). The memory layout follows Sec. 3.3 with these deviations, none of which
 // changes which voxels are occupied:
 //  * the input is binary occupancy, so the last level carries no RGBA words: a last Raw
-//    level is a bit brick (Morton bit order inside cubic bricks), and the deepest octree
-//    depth of a last SVO/SVDAG level is its valid mask;
+//    level is a bit brick, stored as 4x4x4-voxel blocks of one 64-bit mask each (blocks
+//    x-fastest, bits x-fastest inside a block), and the deepest octree depth of a last
+//    SVO/SVDAG level is its valid mask;
 //  * a terminating integer below an SVDAG node is stored in the parent's pointer slot
 //    instead of a separate one-word leaf node; an SVO node just above the next level
 //    points to a packed array of those pointers instead of two-word leaf nodes;
@@ -156,6 +157,7 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
   for (int k = n - 1; k >= 1; --k) s.sub[k] = s.sub[k + 1] + s.lv[k].e[0];
   int depths = 0;
   for (int k = 0; k < n; ++k) depths += (s.lv[k].kind == LK_RAW) ? 1 : s.lv[k].e[0];
+  if (s.lv[n - 1].kind == LK_RAW) depths += 1;  // a last Raw level is walked as blocks + voxels
   for (int a = 0; a < 3; ++a) {
     s.ext[a] = s.sub[1] + s.lv[0].e[a];
     if (s.ext[a] > 16) {
@@ -179,15 +181,48 @@ Layout make_layout(const Spec& s) {
     const LevelSpec& lv = s.lv[k];
     const bool last = (k == n - 1);
     const int cs_level = s.sub[k + 1];
-    if (lv.kind == LK_RAW) {
+    if (lv.kind == LK_RAW && !last) {
       DepthInfo d{};
       d.level = k;
-      d.j = 0;
-      d.nk = last ? NK_RAW_BITS : NK_RAW_PTR;
+      d.nk = NK_RAW_PTR;
       d.hk = HK_RAW;
       d.cs = cs_level;
-      d.w = lv.e[0];
+      for (int a = 0; a < 3; ++a) d.w[a] = lv.e[a];
+      d.arena = true;
       L.d.push_back(d);
+    } else if (lv.kind == LK_RAW) {
+      // Brick of blocks of side 2^b (b = 2 unless an exponent is smaller).
+      const int b = std::min(2, std::min(lv.e[0], std::min(lv.e[1], lv.e[2])));
+      L.brick_b = b;
+      const int blk[3] = {lv.e[0] - b, lv.e[1] - b, lv.e[2] - b};
+      if (blk[0] + blk[1] + blk[2] > 0) {
+        DepthInfo d{};
+        d.level = k;
+        d.nk = NK_BLOCKS;
+        d.hk = HK_RAW;
+        d.cs = b;
+        for (int a = 0; a < 3; ++a) d.w[a] = blk[a];
+        d.arena = true;
+        L.d.push_back(d);
+        DepthInfo c{};
+        c.level = k;
+        c.j = 1;
+        c.nk = NK_CELLS;
+        c.hk = HK_MASK;
+        c.cs = 0;
+        c.w[0] = c.w[1] = c.w[2] = b;
+        c.arena = false;
+        L.d.push_back(c);
+      } else {
+        DepthInfo c{};
+        c.level = k;
+        c.nk = NK_CELLS;
+        c.hk = HK_MASKLOAD;
+        c.cs = 0;
+        c.w[0] = c.w[1] = c.w[2] = b;
+        c.arena = true;
+        L.d.push_back(c);
+      }
     } else {
       const int D = lv.e[0];
       for (int j = 0; j < D; ++j) {
@@ -195,36 +230,37 @@ Layout make_layout(const Spec& s) {
         d.level = k;
         d.j = j;
         d.cs = cs_level + (D - 1 - j);
-        d.w = 1;
+        d.w[0] = d.w[1] = d.w[2] = 1;
         d.hk = (lv.kind == LK_SVO) ? HK_SVO : HK_DAG;
         if (j < D - 1)
           d.nk = (lv.kind == LK_SVO) ? NK_SVO_INNER : NK_OCT_PTR;
         else
           d.nk = last ? NK_OCT_FINAL : NK_OCT_PTR;
+        d.arena = true;
         L.d.push_back(d);
       }
     }
   }
-  for (int a = 0; a < 3; ++a) L.top_w[a] = (s.lv[0].kind == LK_RAW) ? s.lv[0].e[a] : 1;
-  L.bits_linear = (n == 1 && s.lv[0].kind == LK_RAW &&
-                   !(s.lv[0].e[0] == s.lv[0].e[1] && s.lv[0].e[0] == s.lv[0].e[2]));
   return L;
 }
 
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf) {
   DevFormat f{};
   f.buf = dbuf;
-  for (int a = 0; a < 3; ++a) {
-    f.ext[a] = s.ext[a];
-    f.top_w[a] = L.top_w[a];
-  }
+  for (int a = 0; a < 3; ++a) f.ext[a] = s.ext[a];
   f.ndepth = (int)L.d.size();
-  f.bits_linear = L.bits_linear ? 1 : 0;
-  for (size_t i = 0; i < L.d.size(); ++i) {
-    f.cs_tab |= (uint64_t)(L.d[i].cs & 15) << (4 * i);
-    f.w_tab |= (uint64_t)(L.d[i].w & 15) << (4 * i);
-    f.nk_tab |= (uint64_t)(L.d[i].nk & 15) << (4 * i);
-    f.hk_tab |= (uint64_t)(L.d[i].hk & 15) << (4 * i);
+  for (size_t i = 0; i < L.d.size() && i < HVF_MAX_DEPTH; ++i) {
+    const DepthInfo& d = L.d[i];
+    f.dinfo[i] = (uint32_t)(d.nk & 15) | ((uint32_t)(d.hk & 15) << 4) | ((uint32_t)(d.cs & 15) << 8) |
+                 ((uint32_t)(d.w[0] & 15) << 12) | ((uint32_t)(d.w[1] & 15) << 16) | ((uint32_t)(d.w[2] & 15) << 20);
+  }
+  // Depth to return to when the cell position changes in bit h: the deepest depth >= 1
+  // whose node side 2^(cs + w) exceeds 2^h, else the root (depth 0).
+  for (int h = 0; h < 16; ++h) {
+    uint64_t nd = 0;
+    for (size_t i = 1; i < L.d.size(); ++i)
+      if (L.d[i].cs + L.d[i].w[0] > h) nd = i;
+    f.pop_lut |= (nd & 15) << (4 * h);
   }
   return f;
 }
@@ -303,31 +339,27 @@ struct Builder {
     const LevelSpec& lv = S.lv[di.level];
     const int cs = di.cs;
     std::vector<uint32_t>& A = arena[d];
-    if (di.nk == NK_RAW_BITS) {
-      const int wx = (d == 0) ? L.top_w[0] : di.w, wy = (d == 0) ? L.top_w[1] : di.w,
-                wz = (d == 0) ? L.top_w[2] : di.w;
-      const uint64_t bits = 1ull << (wx + wy + wz);
-      if ((bits >> 5) >= (1ull << 31)) throw Overflow();
-      const uint64_t nw = std::max<uint64_t>(2, bits / 32);
+    if (di.nk == NK_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD)) {
+      // A brick of the last Raw level: blocks of side 2^b, one 64-bit mask each.
+      const int b = L.brick_b;
+      const int wx = lv.e[0] - b, wy = lv.e[1] - b;
+      const int wz = lv.e[2] - b;
+      const uint64_t nblocks = 1ull << (wx + wy + wz);
+      if (nblocks >= (1ull << 30)) throw Overflow();
       const uint32_t id = (uint32_t)A.size();
-      A.resize(A.size() + nw, 0u);
-      const uint64_t base = morton(x, y, z);
+      A.resize(A.size() + 2 * nblocks, 0u);
+      const uint64_t m = (1ull << b) - 1;
       for (size_t i = lo; i < hi; ++i) {
-        uint64_t bit;
-        if (L.bits_linear) {
-          uint64_t vx = compact3(codes[i]) - x, vy = compact3(codes[i] >> 1) - y, vz = compact3(codes[i] >> 2) - z;
-          bit = vx | (vy << wx) | (vz << (wx + wy));
-        } else {
-          bit = codes[i] - base;  // Morton index inside an aligned cubic brick
-        }
-        A[id + (bit >> 5)] |= 1u << (bit & 31);
+        const uint64_t vx = compact3(codes[i]) - x, vy = compact3(codes[i] >> 1) - y, vz = compact3(codes[i] >> 2) - z;
+        const uint64_t blk = (vx >> b) | ((vy >> b) << wx) | ((vz >> b) << (wx + wy));
+        const uint64_t bit = (vx & m) | ((vy & m) << b) | ((vz & m) << (2 * b));
+        A[id + 2 * blk + (bit >> 5)] |= 1u << (bit & 31);
       }
       ++nodes[d];
       return id;
     }
     if (di.nk == NK_RAW_PTR) {
-      const int wx = (d == 0) ? L.top_w[0] : di.w, wy = (d == 0) ? L.top_w[1] : di.w,
-                wz = (d == 0) ? L.top_w[2] : di.w;
+      const int wx = di.w[0], wy = di.w[1], wz = di.w[2];
       const uint64_t cells = 1ull << (wx + wy + wz);
       if (cells >= (1ull << 31)) throw Overflow();
       std::vector<uint32_t> arr(cells, 0u);

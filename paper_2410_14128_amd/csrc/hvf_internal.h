@@ -29,35 +29,41 @@ struct Spec {
 hvf_status parse_spec(const char* s, Spec& out, std::string& err);
 
 // ------------------------------------------------------------------ traversal layout
-// The traversal walks "node depths": a Raw level is one depth, an SVO/SVDAG level of
-// depth L is L depths. Each depth has one node kind (how a child cell is tested and its
-// pointer found) and one header kind (how a node at that depth is entered).
+// The traversal walks "node depths": a Raw level above the last is one depth, an
+// SVO/SVDAG level of depth L is L depths, and the last level, if Raw, is a brick of
+// 4x4x4-voxel blocks (one 64-bit occupancy mask each) walked as two depths: the blocks,
+// then the voxels of one block (whose mask is held in registers). Each depth has one
+// node kind (how a child cell is tested and its pointer found) and one header kind (how
+// a node at that depth is entered).
 enum NodeKind : int {
   NK_RAW_PTR = 0,    // Raw level above the last: one pointer word per cell, 0 = empty
-  NK_RAW_BITS = 1,   // last Raw level: one occupancy bit per voxel
-  NK_SVO_INNER = 2,  // SVO node whose children are SVO nodes: child = first + 2 * rank
-  NK_OCT_PTR = 3,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
+  NK_BLOCKS = 1,     // last Raw level, block depth: one 64-bit mask per block, 0 = empty
+  NK_CELLS = 2,      // last Raw level, voxel depth: a bit of the block mask (registers)
+  NK_SVO_INNER = 3,  // SVO node whose children are SVO nodes: child = first + 2 * rank
+  NK_OCT_PTR = 4,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
                      // deepest octree depth above the last level)
-  NK_OCT_FINAL = 4   // deepest octree depth of the last level: valid mask = occupancy
+  NK_OCT_FINAL = 5   // deepest octree depth of the last level: valid mask = occupancy
 };
 enum HeaderKind : int {
-  HK_RAW = 0,  // base = pointer
-  HK_SVO = 1,  // {first child / pointer array, masks}
-  HK_DAG = 2   // {masks, child pointers...}: base = pointer + 1
+  HK_RAW = 0,       // base = pointer
+  HK_SVO = 1,       // {first child / pointer array, masks}
+  HK_DAG = 2,       // {masks, child pointers...}: base = pointer + 1
+  HK_MASK = 3,      // a block entered from its brick: the mask was read by the test
+  HK_MASKLOAD = 4   // a one-block brick: load its 64-bit mask at the pointer
 };
 
 struct DepthInfo {
-  int level;  // level index
-  int j;      // depth inside the level (0 for Raw)
+  int level;   // level index
+  int j;       // depth inside the level (0 for Raw)
   int nk, hk;
-  int cs;     // log2 side (voxels) of this depth's child cells
-  int w;      // log2 children per axis (1 for octree nodes; Raw: the level exponent)
+  int cs;      // log2 side (voxels) of this depth's child cells
+  int w[3];    // log2 children per axis (octree nodes: 1)
+  bool arena;  // nodes of this depth are stored (false for the voxel depth of a brick)
 };
 
 struct Layout {
   std::vector<DepthInfo> d;
-  int top_w[3] = {0, 0, 0};  // per-axis log2 children of the depth-0 node
-  bool bits_linear = false;  // final Raw level stored x-fastest (only a non-cubic single level)
+  int brick_b = 2;  // log2 side of a brick block (2 unless a Raw exponent of the last level is < 2)
 };
 
 Layout make_layout(const Spec& s);
@@ -73,14 +79,16 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
                        std::string& err);
 
 // ------------------------------------------------------------------ device descriptor
-// Per-depth tables packed 4 bits per depth so that a lane reads its entry with one shift.
+// One packed word per depth: nk | hk << 4 | cs << 8 | wx << 12 | wy << 16 | wz << 20.
+// pop_lut: 4 bits per h in [0, 16): the deepest depth whose node side exceeds 2^h, i.e.
+// the depth a walk returns to when its position changes in bit h (node sides shrink
+// strictly with depth, and every depth below the root is cubic).
 struct DevFormat {
   const uint32_t* buf;
   int32_t ext[3];
-  int32_t top_w[3];
   int32_t ndepth;
-  int32_t bits_linear;
-  uint64_t cs_tab, w_tab, nk_tab, hk_tab;
+  uint64_t pop_lut;
+  uint32_t dinfo[HVF_MAX_DEPTH];
 };
 
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf);
@@ -94,7 +102,12 @@ struct hvf_volume {
   hvf::Built built;
   uint32_t* dbuf = nullptr;  // device copy of built.words
   int device = -1;
+  hvf_schedule sched{0, 16, 8, 0, 4, {0, 0, 0}};
+  uint32_t* dcounters = nullptr;  // device ray counters for persistent launches
+  unsigned counter_next = 0;
 };
+
+constexpr int HVF_NUM_COUNTERS = 64;
 
 // Thread-local error text.
 void hvf_set_error(const std::string& s);

@@ -3,22 +3,29 @@
 // The paper's per-level intersection functions (Sec. 4.2: Raw levels by DDA, SVO and SVDAG
 // levels by pre-order traversal with a per-thread stack, visiting non-empty hit children
 // in order of hit time and handing each to the next level) are folded into one flat loop
-// over "node depths". Every iteration a lane does exactly one of:
+// over "node depths". Every step a lane does exactly one of:
 //   * test the child cell of its current node that holds the ray at time t;
-//   * descend into it (push the node on the lane's stack, enter the child, refine the
+//   * descend into it (push the node on the lane's stack, enter the child, narrow the
 //     cell position by comparing mid-plane crossing times with t);
 //   * report the hit (last level, occupied voxel);
-//   * advance to the next cell at the current scale (least far-plane time, all axes
-//     crossing at that time step together) and pop every node the new cell left.
+//   * advance to the next cell at the current scale (least far-plane time, every axis
+//     crossing at that time steps together) and pop every node the new cell left.
 // Because the crossing time of a plane depends only on the plane coordinate, a coarse
 // cell's visit interval is exactly the union of its children's, so this walk visits the
 // same voxels, in the same order, as a flat DDA over the finest grid.
 //
-// Memory: the format is one uint32 buffer in HBM; per-depth tables live in scalar
-// registers as 4-bit fields; the node stack is in LDS, one 8-byte slot per depth per lane.
+// Memory: the format is one uint32 buffer in HBM; a per-depth descriptor table and the
+// node stack (one 8-byte slot per depth per lane) live in LDS; the current depth's
+// descriptor, node header and, inside a brick, the 64-bit block mask live in registers.
+//
+// Kernels: trace_kernel (one ray per lane), trace_persistent_kernel (a fixed grid whose
+// waves refill idle lanes from a global ray counter when a ballot shows enough idle
+// lanes), trace_count_kernel (trace_kernel plus a log of every format word read).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <hipcub/hipcub.hpp>
+#include <mutex>
 #include <string>
 
 #include "hvf_internal.h"
@@ -27,74 +34,365 @@ namespace hvf {
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr uint32_t MAX_ITERS = 1u << 22;  // guard; a correct walk needs far fewer
-
-struct Lane {
-  float o[3], inv[3];
-  bool par[3], neg[3];
-  int vo[3];
-  float t0, t1;
-};
+constexpr uint32_t MAX_STEPS = 1u << 22;  // guard; a correct walk needs far fewer
 
 __device__ __forceinline__ float fmax_fx(float a, float b) { return a < b ? b : a; }
 __device__ __forceinline__ float fmin_fx(float a, float b) { return b < a ? b : a; }
 
-// Crossing time of the integer plane p on axis a: two rounded fp32 ops, never fused.
-__device__ __forceinline__ float plane_t(const Lane& L, int a, int p) { return ((float)p - L.o[a]) * L.inv[a]; }
+__device__ __forceinline__ uint32_t bf(uint32_t v, uint32_t off, uint32_t w) {
+  return __builtin_amdgcn_ubfe(v, off, w);
+}
+__device__ __forceinline__ uint32_t di_nk(uint32_t i) { return i & 15u; }
+__device__ __forceinline__ uint32_t di_hk(uint32_t i) { return bf(i, 4, 4); }
+__device__ __forceinline__ int di_cs(uint32_t i) { return (int)bf(i, 8, 4); }
+__device__ __forceinline__ int di_w(uint32_t i, int a) { return (int)bf(i, 12 + 4 * a, 4); }
+
+struct Ray {
+  float o[3], inv[3];
+  uint32_t neg, par;  // bit a set: d_a < 0 / axis a parallel
+  int vo[3];          // floor(o_a) on parallel axes
+  float t0, t1;
+  __device__ __forceinline__ bool is_par(int a) const { return (par >> a) & 1u; }
+  __device__ __forceinline__ bool is_neg(int a) const { return (neg >> a) & 1u; }
+  // Crossing time of the integer plane p on axis a: two rounded fp32 ops, never fused.
+  __device__ __forceinline__ float T(int a, int p) const { return ((float)p - o[a]) * inv[a]; }
+};
 
 // Ray setup and clip against [0, 2^ext) (the root volume). False on a miss.
-__device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const int32_t ext[3], Lane& L) {
+__device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const int32_t ext[3], Ray& R) {
   const float o[3] = {r0.x, r0.y, r0.z}, d[3] = {r1.x, r1.y, r1.z};
-  bool ok = true, anyn = false;
+  bool ok = true;
+  R.neg = R.par = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     ok = ok && isfinite(o[a]) && isfinite(d[a]);
-    L.o[a] = o[a];
-    L.inv[a] = 1.0f / d[a];
-    L.par[a] = !isfinite(L.inv[a]);
-    L.neg[a] = d[a] < 0.0f;
-    L.vo[a] = 0;
-    if (L.par[a]) {
+    R.o[a] = o[a];
+    R.inv[a] = 1.0f / d[a];
+    const bool par = !isfinite(R.inv[a]);
+    R.par |= (uint32_t)par << a;
+    R.neg |= (uint32_t)(d[a] < 0.0f) << a;
+    R.vo[a] = 0;
+    if (par) {
       const bool in = (o[a] >= 0.0f) && (o[a] < (float)(1 << ext[a]));
       ok = ok && in;
-      if (in) L.vo[a] = (int)floorf(o[a]);
-    } else {
-      anyn = true;
+      if (in) R.vo[a] = (int)floorf(o[a]);
     }
   }
-  if (!(ok && anyn)) return false;
+  if (!ok || R.par == 7u) return false;
   bool first = true;
   float tn = 0.0f, tf = 0.0f;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (L.par[a]) continue;
+    if (R.is_par(a)) continue;
     const int N = 1 << ext[a];
-    const float ne = plane_t(L, a, L.neg[a] ? N : 0);
-    const float fa = plane_t(L, a, L.neg[a] ? 0 : N);
+    const float ne = R.T(a, R.is_neg(a) ? N : 0);
+    const float fa = R.T(a, R.is_neg(a) ? 0 : N);
     tn = first ? ne : fmax_fx(tn, ne);
     tf = first ? fa : fmin_fx(tf, fa);
     first = false;
   }
-  L.t0 = fmax_fx(r0.w, tn);
-  L.t1 = fmin_fx(r1.w, tf);
-  return L.t0 < L.t1;
+  R.t0 = fmax_fx(r0.w, tn);
+  R.t1 = fmin_fx(r1.w, tf);
+  return R.t0 < R.t1;
 }
 
-// Narrow coordinate p (aligned to 2^hi) to the 2^lo-aligned cell that holds the ray at
-// time t on axis a: one mid-plane comparison per bit.
-__device__ __forceinline__ int refine(const Lane& L, int a, int p, int hi, int lo, float t) {
+// Narrow the cell position p (aligned to 2^hi on every axis) to the 2^lo-aligned cell
+// that holds the ray at time t: one mid-plane comparison per bit and axis. For d > 0 the
+// upper half holds the ray iff T(mid) <= t; for d < 0 iff t < T(mid); a parallel axis
+// compares floor(o) with mid. Plane times are never NaN once setup has passed.
+__device__ __forceinline__ void refine3(const Ray& R, int p[3], int hi, int lo, float t) {
   for (int b = hi - 1; b >= lo; --b) {
-    const int mid = p + (1 << b);
-    bool up;
-    if (L.par[a]) {
-      up = L.vo[a] >= mid;
-    } else {
-      const float tm = plane_t(L, a, mid);
-      up = L.neg[a] ? (t < tm) : (tm <= t);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int mid = p[a] + (1 << b);
+      const float tm = R.T(a, mid);
+      const bool up = R.is_par(a) ? (R.vo[a] >= mid) : ((tm <= t) != R.is_neg(a));
+      p[a] = up ? mid : p[a];
     }
-    p = up ? mid : p;
   }
-  return p;
+}
+
+// Memory policies. Plain: just load. Counting: also log every word index a lane reads
+// (the byte accounting of the roofline counts distinct words / 64-byte sectors per ray).
+struct Plain {
+  __device__ __forceinline__ void note(uint32_t, uint32_t) {}
+};
+struct Counting {
+  uint32_t* log;  // this lane's log: cap entries
+  uint32_t cap;
+  uint32_t k;
+  __device__ __forceinline__ void note(uint32_t idx, uint32_t nwords) {
+    for (uint32_t w = 0; w < nwords; ++w) {
+      if (k < cap) log[k] = idx + w;
+      ++k;
+    }
+  }
+};
+
+__device__ __forceinline__ uint2 ld2(const uint32_t* buf, uint32_t ix) {
+  return *reinterpret_cast<const uint2*>(buf + ix);
+}
+
+enum : int { RUN = 0, DONE = 1 };
+
+// The per-lane walk state.
+struct Walk {
+  Ray R;
+  float t;
+  int p[3];
+  int d;
+  uint32_t info;  // descriptor of depth d
+  uint32_t base, valid;
+  uint32_t steps;
+
+  // Enter the node at pointer ptr whose depth descriptor is nd: returns its header
+  // (base, valid). m: the 64-bit block mask the parent's test read (used by HK_MASK).
+  template <class Mem>
+  __device__ __forceinline__ static uint2 enter(const uint32_t* __restrict__ buf, uint32_t nd, uint32_t ptr, uint2 m,
+                                                Mem& mem) {
+    const uint32_t hk = di_hk(nd);
+    if (hk == HK_RAW) return make_uint2(ptr, 0u);
+    if (hk == HK_MASK) return m;
+    if (hk == HK_DAG) {
+      mem.note(ptr, 1);
+      return make_uint2(ptr + 1u, buf[ptr] & 0xFFu);
+    }
+    // HK_SVO (first, masks) or HK_MASKLOAD (lo, hi)
+    const uint2 h = ld2(buf, ptr);
+    mem.note(ptr, 2);
+    return make_uint2(h.x, (hk == HK_SVO) ? (h.y & 0xFFu) : h.y);
+  }
+
+  // Start the walk of a ray that passed setup. Returns DONE if the volume is empty.
+  template <class Mem>
+  __device__ __forceinline__ int start(const DevFormat& F, const uint32_t* dtab, Mem& mem) {
+    const uint32_t* __restrict__ buf = F.buf;
+    const uint32_t root = buf[0];  // word 0: pointer to the root sub-volume; 0 = empty
+    mem.note(0, 1);
+    if (root == 0u) return DONE;
+    d = 0;
+    info = dtab[0];
+    const int cs = di_cs(info);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = 0;
+    // The root node may be non-cubic: narrow each axis from its own extent.
+    for (int b = max(F.ext[0], max(F.ext[1], F.ext[2])) - 1; b >= cs; --b) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (b >= F.ext[a]) continue;
+        const int mid = p[a] + (1 << b);
+        const float tm = R.T(a, mid);
+        const bool up = R.is_par(a) ? (R.vo[a] >= mid) : ((tm <= R.t0) != R.is_neg(a));
+        p[a] = up ? mid : p[a];
+      }
+    }
+    const uint2 h = enter(buf, info, root, make_uint2(0u, 0u), mem);
+    base = h.x;
+    valid = h.y;
+    t = R.t0;
+    steps = 0;
+    return RUN;
+  }
+
+  // One step. On DONE, out holds the result (a miss leaves it untouched).
+  template <class Mem>
+  __device__ __forceinline__ int step(const DevFormat& F, const uint32_t* dtab, uint2* stk, int4& out, Mem& mem) {
+    const uint32_t* __restrict__ buf = F.buf;
+    if (++steps > MAX_STEPS) {
+      out = make_int4(-2, -2, -2, 0);  // guard tripped: reported, never silent
+      return DONE;
+    }
+    const uint32_t nk = di_nk(info);
+    const int cs = di_cs(info);
+    const uint32_t wx = bf(info, 12, 4), wy = bf(info, 16, 4), wz = bf(info, 20, 4);
+    // Child cell of the current node holding the ray (octree nodes: w = 1, the octant).
+    const uint32_t lin = bf((uint32_t)p[0], cs, wx) | (bf((uint32_t)p[1], cs, wy) << wx) |
+                         (bf((uint32_t)p[2], cs, wz) << (wx + wy));
+    bool occ;
+    uint32_t child = 0u;
+    uint2 cm = make_uint2(0u, 0u);
+    if (nk == NK_RAW_PTR) {
+      child = buf[base + lin];
+      mem.note(base + lin, 1);
+      occ = child != 0u;
+    } else if (nk == NK_BLOCKS) {
+      cm = ld2(buf, base + 2u * lin);
+      mem.note(base + 2u * lin, 2);
+      occ = (cm.x | cm.y) != 0u;
+    } else {
+      // A voxel's bit in the block mask (base:valid), or an octree child's valid bit.
+      const uint32_t word = (nk == NK_CELLS && lin < 32u) ? base : valid;
+      occ = ((word >> (lin & 31u)) & 1u) != 0u;
+    }
+    const bool fin = (nk == NK_CELLS) || (nk == NK_OCT_FINAL);
+    if (occ && !fin) {
+      if (nk >= NK_SVO_INNER) {
+        const uint32_t rank = __popc(valid & ((1u << lin) - 1u));
+        if (nk == NK_SVO_INNER) {
+          child = base + 2u * rank;
+        } else {
+          child = buf[base + rank];
+          mem.note(base + rank, 1);
+        }
+      }
+      stk[d * BLOCK] = make_uint2(base, valid);
+      ++d;
+      info = dtab[d];
+      const uint2 h = enter(buf, info, child, cm, mem);
+      base = h.x;
+      valid = h.y;
+      refine3(R, p, cs, di_cs(info), t);
+      return RUN;
+    }
+    if (occ) {
+      // An occupied single voxel: report it if the ray really spends time in it.
+      float e = R.t0, x = R.t1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const bool par = R.is_par(a), ng = R.is_neg(a);
+        const float tn = R.T(a, ng ? p[a] + 1 : p[a]), tx = R.T(a, ng ? p[a] : p[a] + 1);
+        e = fmax_fx(e, par ? -INFINITY : tn);
+        x = fmin_fx(x, par ? INFINITY : tx);
+      }
+      if (e < x) {
+        out = make_int4(p[0], p[1], p[2], __float_as_int(e));
+        return DONE;
+      }
+    }
+    // Advance to the next cell of side 2^cs: the least far-plane time; every axis that
+    // crosses at that time steps.
+    const int stepv = 1 << cs;
+    float tf[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
+      tf[a] = R.is_par(a) ? INFINITY : tt;
+    }
+    const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
+    if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
+    t = m;
+    uint32_t dd = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
+      const bool mv = (tf[a] == m);
+      dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
+      p[a] = mv ? np : p[a];
+    }
+    // Pop to the deepest node that still contains the new cell (the root always does).
+    if (d > 0) {
+      const int hb = 31 - __clz(dd);
+      const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
+      if (nd != d) {
+        d = nd;
+        info = dtab[d];
+        const uint2 sv = stk[d * BLOCK];
+        base = sv.x;
+        valid = sv.y;
+        const int mask = ~((1 << di_cs(info)) - 1);
+        p[0] &= mask;
+        p[1] &= mask;
+        p[2] &= mask;
+      }
+    }
+    return RUN;
+  }
+};
+
+__device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
+  if (threadIdx.x < HVF_MAX_DEPTH) dtab[threadIdx.x] = F.dinfo[threadIdx.x];
+  __syncthreads();
+}
+
+__device__ __forceinline__ int4 miss_hit() { return make_int4(-1, -1, -1, __float_as_int(INFINITY)); }
+
+__global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                      int4* __restrict__ hits, uint32_t n) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  load_dtab(F, dtab);
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  int4 out = miss_hit();
+  Walk w;
+  Plain mem;
+  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
+    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+    }
+  hits[i] = out;
+}
+
+// Persistent variant: a grid sized to the device; each wave keeps its lanes busy by
+// fetching a new ray for every idle lane from a global counter whenever at least
+// `refill` lanes are idle (or the whole wave is). *counter must be 0 at launch.
+__global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                                 int4* __restrict__ hits, uint32_t n,
+                                                                 uint32_t* __restrict__ counter, uint32_t refill,
+                                                                 uint32_t inner) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  load_dtab(F, dtab);
+  uint2* stk = stk_all + threadIdx.x;
+  const uint32_t lane = __lane_id();
+  Walk w;
+  Plain mem;
+  bool active = false;
+  uint32_t ray = 0;
+  int4 out = miss_hit();
+  bool drained = false;
+  for (;;) {
+    const uint64_t idle = __ballot(!active);
+    const uint32_t nidle = (uint32_t)__popcll(idle);
+    if (!drained && (nidle >= refill || nidle == 64u)) {
+      uint32_t first = 0;
+      if (lane == (uint32_t)(__ffsll((unsigned long long)idle) - 1)) first = atomicAdd(counter, nidle);
+      first = __shfl(first, __ffsll((unsigned long long)idle) - 1);
+      if (first >= n) drained = true;
+      if (!active) {
+        const uint32_t rank = (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+        const uint32_t id = first + rank;
+        if (id < n) {
+          ray = id;
+          out = miss_hit();
+          const float4 r0 = rays[2 * (size_t)id], r1 = rays[2 * (size_t)id + 1];
+          active = setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN;
+          if (!active) hits[id] = out;
+        }
+      }
+    }
+    if (drained && __ballot(active) == 0ull) break;
+    if (active) {
+      for (uint32_t k = 0; k < inner; ++k) {
+        if (w.step(F, dtab, stk, out, mem) == DONE) {
+          hits[ray] = out;
+          active = false;
+          break;
+        }
+      }
+    }
+  }
+}
+
+// One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
+__global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                              int4* __restrict__ hits, uint32_t n,
+                                                              const uint32_t* __restrict__ perm,
+                                                              const uint32_t* __restrict__ key) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  load_dtab(F, dtab);
+  const uint32_t k = blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= n || key[k] == 0xFFFFFFFFu) return;  // rays that miss the root box were answered
+  const uint32_t i = perm[k];
+  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  int4 out = miss_hit();
+  Walk w;
+  Plain mem;
+  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
+    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+    }
+  hits[i] = out;
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
@@ -106,217 +404,82 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t tab(uint64_t t, int d) { return (uint32_t)(t >> (4 * d)) & 15u; }
-
-// Memory policies. Plain: just load. Counting: also log every word index a lane reads
-// (the byte accounting of the roofline counts distinct words / 64-byte sectors per ray).
-struct Plain {
-  __device__ __forceinline__ void note(uint32_t, uint32_t) {}
-};
-struct Counting {
-  uint32_t* log;  // this lane's log: cap entries
-  uint32_t cap;
-  uint32_t k = 0;
-  __device__ __forceinline__ void note(uint32_t idx, uint32_t nwords) {
-    for (uint32_t w = 0; w < nwords; ++w) {
-      if (k < cap) log[k] = idx + w;
-      ++k;
-    }
-  }
-};
-
-// Trace one lane's ray; writes the result to *out.
-template <class Mem>
-__device__ __forceinline__ void walk(const DevFormat& F, const Lane& L, uint2* stk, int4& out, Mem& mem) {
-  const uint32_t* __restrict__ buf = F.buf;
-  const uint32_t root = buf[0];  // word 0: pointer to the root sub-volume; 0 = empty
-  mem.note(0, 1);
-  if (root == 0) return;
-  int p[3];
-  const int cs0 = (int)tab(F.cs_tab, 0);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) p[a] = refine(L, a, 0, F.ext[a], cs0, L.t0);
-  int d = 0;
-  uint32_t base = root, valid = 0xFFu;
-  {
-    const uint32_t hk = tab(F.hk_tab, 0);
-    if (hk == HK_SVO) {
-      const uint2 h = *reinterpret_cast<const uint2*>(buf + root);
-      mem.note(root, 2);
-      base = h.x;
-      valid = h.y & 0xFFu;
-    } else if (hk == HK_DAG) {
-      valid = buf[root] & 0xFFu;
-      mem.note(root, 1);
-      base = root + 1;
-    }
-  }
-  float t = L.t0;
-  for (uint32_t it = 0; it < MAX_ITERS; ++it) {
-    const uint32_t nk = tab(F.nk_tab, d);
-    const int cs = (int)tab(F.cs_tab, d);
-    bool occ;
-    uint32_t child = 0;
-    if (nk <= NK_RAW_BITS) {
-      int wx, wy, wz;
-      if (d == 0) {
-        wx = F.top_w[0];
-        wy = F.top_w[1];
-        wz = F.top_w[2];
-      } else {
-        wx = wy = wz = (int)tab(F.w_tab, d);
-      }
-      const uint32_t cx = ((uint32_t)p[0] >> cs) & ((1u << wx) - 1u);
-      const uint32_t cy = ((uint32_t)p[1] >> cs) & ((1u << wy) - 1u);
-      const uint32_t cz = ((uint32_t)p[2] >> cs) & ((1u << wz) - 1u);
-      if (nk == NK_RAW_PTR) {
-        const uint32_t ix = base + (cx | (cy << wx) | (cz << (wx + wy)));
-        child = buf[ix];
-        mem.note(ix, 1);
-        occ = child != 0u;
-      } else {
-        uint32_t word_ix, bit;
-        if (F.bits_linear) {
-          const uint64_t b64 = (uint64_t)cx | ((uint64_t)cy << wx) | ((uint64_t)cz << (wx + wy));
-          word_ix = (uint32_t)(b64 >> 5);
-          bit = (uint32_t)b64 & 31u;
-        } else if (wx <= 10) {
-          const uint32_t m = spread10(cx) | (spread10(cy) << 1) | (spread10(cz) << 2);
-          word_ix = m >> 5;
-          bit = m & 31u;
-        } else {
-          const uint64_t m = (uint64_t)(spread10(cx) | (spread10(cy) << 1) | (spread10(cz) << 2)) |
-                             ((uint64_t)(spread10(cx >> 10) | (spread10(cy >> 10) << 1) | (spread10(cz >> 10) << 2)) << 30);
-          word_ix = (uint32_t)(m >> 5);
-          bit = (uint32_t)m & 31u;
-        }
-        occ = (buf[base + word_ix] >> bit) & 1u;
-        mem.note(base + word_ix, 1);
-      }
-    } else {
-      const uint32_t oct = (((uint32_t)p[0] >> cs) & 1u) | ((((uint32_t)p[1] >> cs) & 1u) << 1) |
-                           ((((uint32_t)p[2] >> cs) & 1u) << 2);
-      occ = (valid >> oct) & 1u;
-      if (occ && nk != NK_OCT_FINAL) {
-        const uint32_t rank = __popc(valid & ((1u << oct) - 1u));
-        if (nk == NK_SVO_INNER) {
-          child = base + 2u * rank;
-        } else {
-          child = buf[base + rank];
-          mem.note(base + rank, 1);
-        }
-      }
-    }
-    if (occ) {
-      if (nk == NK_RAW_BITS || nk == NK_OCT_FINAL) {
-        // An occupied single voxel: report it if the ray really spends time in it.
-        float e = L.t0, x = L.t1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (L.par[a]) continue;
-          e = fmax_fx(e, plane_t(L, a, L.neg[a] ? p[a] + 1 : p[a]));
-          x = fmin_fx(x, plane_t(L, a, L.neg[a] ? p[a] : p[a] + 1));
-        }
-        if (e < x) {
-          out = make_int4(p[0], p[1], p[2], __float_as_int(e));
-          return;
-        }
-      } else {
-        stk[d * BLOCK] = make_uint2(base, valid);
-        ++d;
-        const uint32_t hk = tab(F.hk_tab, d);
-        if (hk == HK_RAW) {
-          base = child;
-        } else if (hk == HK_SVO) {
-          const uint2 h = *reinterpret_cast<const uint2*>(buf + child);
-          mem.note(child, 2);
-          base = h.x;
-          valid = h.y & 0xFFu;
-        } else {
-          valid = buf[child] & 0xFFu;
-          mem.note(child, 1);
-          base = child + 1u;
-        }
-        const int ncs = (int)tab(F.cs_tab, d);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) p[a] = refine(L, a, p[a], cs, ncs, t);
-        continue;
-      }
-    }
-    // Advance to the next cell of side 2^cs.
-    const int step = 1 << cs;
-    float tf[3];
-    float m = 0.0f;
-    bool first = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      tf[a] = 0.0f;
-      if (L.par[a]) continue;
-      tf[a] = plane_t(L, a, L.neg[a] ? p[a] : p[a] + step);
-      m = first ? tf[a] : fmin_fx(m, tf[a]);
-      first = false;
-    }
-    if (!(m < L.t1)) return;  // leaves the clipped ray interval: miss
-    t = m;
-    int diff = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (L.par[a] || tf[a] != m) continue;
-      const int np = p[a] + (L.neg[a] ? -step : step);
-      diff |= np ^ p[a];
-      p[a] = np;
-    }
-    if (d > 0) {
-      const int h = 31 - __clz(diff);
-      int nd = d;
-      while (nd > 0 && h >= (int)(tab(F.cs_tab, nd) + tab(F.w_tab, nd))) --nd;
-      if (nd != d) {
-        d = nd;
-        const uint2 s = stk[d * BLOCK];
-        base = s.x;
-        valid = s.y;
-        const int mask = ~((1 << (int)tab(F.cs_tab, d)) - 1);
-        p[0] &= mask;
-        p[1] &= mask;
-        p[2] &= mask;
-      }
-    }
-  }
-  out = make_int4(-2, -2, -2, 0);  // iteration guard tripped: reported, never silent
-}
-
-__global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
-                                                      int4* __restrict__ hits, uint32_t n) {
-  extern __shared__ uint2 stk_all[];
+// Coherence key of each ray: direction octant (3 high bits), then the Morton code of
+// the cell of side 2^cell_bits holding the ray's entry point into the volume (29 bits,
+// coarsest first). Rays that miss the root box get the key 0xFFFFFFFF and their miss is
+// written here.
+__global__ __launch_bounds__(BLOCK) void ray_key_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                        int4* __restrict__ hits, uint32_t n, int cell_bits,
+                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ idx) {
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  int4 out = make_int4(-1, -1, -1, __float_as_int(INFINITY));
-  Lane L;
-  Plain mem;
-  if (setup(r0, r1, F.ext, L)) walk(F, L, stk_all + threadIdx.x, out, mem);
-  hits[i] = out;
+  Ray R;
+  uint32_t k = 0xFFFFFFFFu;
+  if (setup(r0, r1, F.ext, R)) {
+    const float d[3] = {r1.x, r1.y, r1.z};
+    uint32_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float q = R.o[a] + R.t0 * d[a];  // approximate entry point: only orders rays
+      const int N = 1 << F.ext[a];
+      const int v = (int)fminf(fmaxf(floorf(q), 0.0f), (float)(N - 1));
+      c[a] = (uint32_t)v >> cell_bits;
+    }
+    const uint32_t m = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);  // up to 30 bits
+    k = (R.neg << 29) | (m >> 1);
+    if (k == 0xFFFFFFFFu) k = 0xFFFFFFFEu;
+  } else {
+    hits[i] = miss_hit();
+  }
+  key[i] = k;
+  idx[i] = i;
 }
 
-// Same traversal, logging the word index of every format load: log[i * cap + k] for the
-// first cap loads of ray i; count[i] = number of loads (may exceed cap).
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Same traversal as trace_kernel, logging the word index of every format load:
+// log[i * cap + k] for the first cap loads of ray i; count[i] = number of loads.
 __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n,
                                                             uint32_t* __restrict__ log, uint32_t cap,
-                                                            uint32_t* __restrict__ count) {
+                                                            uint32_t* __restrict__ count,
+                                                            uint32_t* __restrict__ nsteps) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
+  load_dtab(F, dtab);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  int4 out = make_int4(-1, -1, -1, __float_as_int(INFINITY));
-  Lane L;
-  Counting mem{log + (size_t)i * cap, cap};
-  if (setup(r0, r1, F.ext, L)) walk(F, L, stk_all + threadIdx.x, out, mem);
+  int4 out = miss_hit();
+  Walk w;
+  Counting mem{log + (size_t)i * cap, cap, 0u};
+  w.steps = 0;
+  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
+    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+    }
   hits[i] = out;
   count[i] = mem.k;
+  if (nsteps) nsteps[i] = w.steps;
 }
 
+hvf_status launch_check(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    hvf_set_error(std::string(what) + " launch failed: " + hipGetErrorString(e));
+    return HVF_E_DEVICE;
+  }
+  return HVF_OK;
+}
+
+int g_cu_count = -1;
+
 }  // namespace
+
+size_t stack_lds_bytes(const DevFormat& F) { return (size_t)F.ndepth * BLOCK * sizeof(uint2); }
 
 hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s) {
   if (n == 0) return HVF_OK;
@@ -325,34 +488,123 @@ hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf
     return HVF_E_INPUT;
   }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-  const size_t lds = (size_t)F.ndepth * BLOCK * sizeof(uint2);
-  hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(BLOCK), lds, s, F, reinterpret_cast<const float4*>(d_rays),
-                     reinterpret_cast<int4*>(d_hits), (uint32_t)n);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    hvf_set_error(std::string("trace launch failed: ") + hipGetErrorString(e));
-    return HVF_E_DEVICE;
+  hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n);
+  return launch_check("trace");
+}
+
+// Blocks of the persistent kernel that fit on the device at once.
+hvf_status persistent_grid(const DevFormat& F, unsigned* grid) {
+  if (g_cu_count < 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      hvf_set_error("hipGetDeviceProperties failed");
+      return HVF_E_DEVICE;
+    }
+    g_cu_count = prop.multiProcessorCount;
   }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent_kernel, BLOCK, stack_lds_bytes(F)) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  *grid = (unsigned)(g_cu_count * per_cu);
   return HVF_OK;
 }
 
+hvf_status launch_trace_persistent(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                                   uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s) {
+  if (n == 0) return HVF_OK;
+  if (n >= (1ull << 31)) {
+    hvf_set_error("at most 2^31 - 1 rays per persistent call");
+    return HVF_E_INPUT;
+  }
+  hipLaunchKernelGGL(trace_persistent_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_counter,
+                     refill, inner);
+  return launch_check("persistent trace");
+}
+
+hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
+  if (n == 0) return HVF_OK;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
+  return launch_check("fill");
+}
+
+namespace {
+// Device scratch for ray sorting, grown on demand and reused (one sorted trace at a time
+// per process; calls are serialised by this lock on the host side).
+struct SortScratch {
+  std::mutex mu;
+  void* buf = nullptr;
+  size_t bytes = 0;
+};
+SortScratch g_sort;
+}  // namespace
+
+hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule& sc,
+                        uint32_t* d_counter, hipStream_t s) {
+  (void)d_counter;
+  if (n >= (1ull << 31)) {
+    hvf_set_error("at most 2^31 - 1 rays per sorted call");
+    return HVF_E_INPUT;
+  }
+  std::lock_guard<std::mutex> lock(g_sort.mu);
+  const size_t arr = ((n * sizeof(uint32_t) + 255) / 256) * 256;
+  size_t temp = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, temp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                         (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)n, 0, 32, s) !=
+      hipSuccess) {
+    hvf_set_error("radix sort size query failed");
+    return HVF_E_DEVICE;
+  }
+  const size_t need = 4 * arr + temp;
+  if (need > g_sort.bytes) {
+    if (g_sort.buf) (void)hipFree(g_sort.buf);
+    g_sort.buf = nullptr;
+    g_sort.bytes = 0;
+    const hipError_t e = hipMalloc(&g_sort.buf, need);
+    if (e != hipSuccess) {
+      hvf_set_error(std::string("hipMalloc of sort scratch: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE;
+    }
+    g_sort.bytes = need;
+  }
+  char* base = (char*)g_sort.buf;
+  uint32_t* key_in = (uint32_t*)base;
+  uint32_t* idx_in = (uint32_t*)(base + arr);
+  uint32_t* key_out = (uint32_t*)(base + 2 * arr);
+  uint32_t* idx_out = (uint32_t*)(base + 3 * arr);
+  void* tmp = base + 4 * arr;
+  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(ray_key_kernel, dim3(grid), dim3(BLOCK), 0, s, F, reinterpret_cast<const float4*>(d_rays),
+                     reinterpret_cast<int4*>(d_hits), (uint32_t)n, sc.sort_bits, key_in, idx_in);
+  hvf_status st = launch_check("ray key");
+  if (st != HVF_OK) return st;
+  if (hipcub::DeviceRadixSort::SortPairs(tmp, temp, key_in, key_out, idx_in, idx_out, (int)n, 0, 32, s) !=
+      hipSuccess) {
+    hvf_set_error("radix sort failed");
+    return HVF_E_DEVICE;
+  }
+  hipLaunchKernelGGL(trace_indexed_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, idx_out,
+                     key_out);
+  return launch_check("sorted trace");
+}
+
 hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
-                              uint32_t cap, uint32_t* d_count, hipStream_t s) {
+                              uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32)) {
     hvf_set_error("at most 2^32 - 1 rays per call");
     return HVF_E_INPUT;
   }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-  const size_t lds = (size_t)F.ndepth * BLOCK * sizeof(uint2);
-  hipLaunchKernelGGL(trace_count_kernel, dim3(grid), dim3(BLOCK), lds, s, F, reinterpret_cast<const float4*>(d_rays),
-                     reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log, cap, d_count);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    hvf_set_error(std::string("counting trace launch failed: ") + hipGetErrorString(e));
-    return HVF_E_DEVICE;
-  }
-  return HVF_OK;
+  hipLaunchKernelGGL(trace_count_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log, cap,
+                     d_count, d_steps);
+  return launch_check("counting trace");
 }
 
 }  // namespace hvf

@@ -17,22 +17,15 @@ def _depths(info):
         sub[k] = sub[k + 1] + exps[k][0]
     out = []
     for k in range(n):
-        if kinds[k] == "R":
+        if kinds[k] == "R" and k < n - 1:
             out.append((k, "R", 0, 1, sub[k + 1], exps[k]))
+        elif kinds[k] == "R":
+            out.append((k, "B", 0, 1, 0, exps[k]))  # last Raw level: a brick of 64-bit block masks
         else:
             L = exps[k][0]
             for j in range(L):
                 out.append((k, kinds[k], j, L, sub[k + 1] + (L - 1 - j), (1, 1, 1)))
     return out, n
-
-
-def _morton_cell(idx, w):
-    x = y = z = 0
-    for b in range(w):
-        x |= ((idx >> (3 * b)) & 1) << b
-        y |= ((idx >> (3 * b + 1)) & 1) << b
-        z |= ((idx >> (3 * b + 2)) & 1) << b
-    return x, y, z
 
 
 def decode(info, words):
@@ -46,7 +39,7 @@ def decode(info, words):
 
     def enter(d, ptr):
         k, kind, j, L, cs, w = D[d]
-        if kind == "R":
+        if kind in ("R", "B"):
             return ptr, 0xFF
         if kind == "S":
             return int(W[ptr]), int(W[ptr + 1]) & 0xFF
@@ -56,24 +49,28 @@ def decode(info, words):
         k, kind, j, L, cs, w = D[d]
         last_level = (k == nlev - 1)
         base, valid = enter(d, ptr)
+        if kind == "B":
+            # blocks of side 2^b (b = min(2, smallest exponent)), blocks x-fastest, one
+            # 64-bit mask per block with bits x-fastest inside the block
+            b = min(2, min(w))
+            bx, by, bz = w[0] - b, w[1] - b, w[2] - b
+            for blk in range(1 << (bx + by + bz)):
+                m = int(W[ptr + 2 * blk]) | (int(W[ptr + 2 * blk + 1]) << 32)
+                ox, oy, oz = blk & ((1 << bx) - 1), (blk >> bx) & ((1 << by) - 1), blk >> (bx + by)
+                for bit in range(64):
+                    if (m >> bit) & 1:
+                        cx, cy, cz = bit & ((1 << b) - 1), (bit >> b) & ((1 << b) - 1), bit >> (2 * b)
+                        assert cz < (1 << b), "bit beyond the block"
+                        out.append((corner[0] + (ox << b) + cx, corner[1] + (oy << b) + cy, corner[2] + (oz << b) + cz))
+            return
         if kind == "R":
             wx, wy, wz = w
             ncell = 1 << (wx + wy + wz)
-            if last_level:
-                cubic = (wx == wy == wz)
-                for bit in range(ncell):
-                    if (int(W[base + (bit >> 5)]) >> (bit & 31)) & 1:
-                        if cubic:
-                            cx, cy, cz = _morton_cell(bit, wx)
-                        else:
-                            cx, cy, cz = bit & ((1 << wx) - 1), (bit >> wx) & ((1 << wy) - 1), bit >> (wx + wy)
-                        out.append((corner[0] + cx, corner[1] + cy, corner[2] + cz))
-            else:
-                for idx in range(ncell):
-                    p = int(W[base + idx])
-                    if p:
-                        cx, cy, cz = idx & ((1 << wx) - 1), (idx >> wx) & ((1 << wy) - 1), idx >> (wx + wy)
-                        walk(d + 1, p, (corner[0] + (cx << cs), corner[1] + (cy << cs), corner[2] + (cz << cs)))
+            for idx in range(ncell):
+                p = int(W[base + idx])
+                if p:
+                    cx, cy, cz = idx & ((1 << wx) - 1), (idx >> wx) & ((1 << wy) - 1), idx >> (wx + wy)
+                    walk(d + 1, p, (corner[0] + (cx << cs), corner[1] + (cy << cs), corner[2] + (cz << cs)))
             return
         deepest = (j == L - 1)
         for o in range(8):

@@ -86,3 +86,43 @@ def test_deterministic(H):
     assert np.array_equal(a, b)
     ref = oracle.Volume("G(4) R(3,3,3) --whole-level-dedup", codes).trace(rays, nthreads=8)
     assert compare(a, ref, "shell 128") == 0
+
+
+SCHEDULES = [dict(persistent=1, refill=1, inner=1), dict(persistent=1, refill=16, inner=8),
+             dict(persistent=1, refill=64, inner=64), dict(sort=1, sort_bits=0), dict(sort=1, sort_bits=4),
+             dict(sort=1, sort_bits=9)]
+
+
+@pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
+def test_schedules_give_identical_results(H, sd):
+    import torch
+    sc = H.schedule(**sd)
+    cases = [("R(2,2,2) S(2) R(2,2,2)", W.scene_solid_noise(1), (64,) * 3),
+             ("G(4) R(3,3,3) --whole-level-dedup", W.scene_shell(3, 7, 8, 4, 1.4), (128,) * 3),
+             ("S(1) G(1) R(1,1,1)", W.scene_bernoulli(2, 3, 3, 3, 0.1), (8,) * 3)]
+    for spec, codes, ext in cases:
+        rays = np.concatenate([W.camera_rays(3, 0, ext, 160, 120), W.random_rays(3, ext, 30000),
+                               np.concatenate([r for r, _ in EDGE_CASES])])
+        v = H.Volume(spec, codes)
+        d = torch.from_numpy(rays).cuda()
+        plain = v.trace(d).cpu().numpy()
+        got = v.trace(d, sched=sc)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        assert np.array_equal(got, plain), f"{spec} {sd}"
+        ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
+        assert compare(got, ref, f"{spec} {sd}") == 0
+
+
+def test_autotune_keeps_results(H):
+    import torch
+    codes = W.scene_shell(3, 7, 8, 4, 1.4)
+    spec = "R(3,3,3) G(4) --whole-level-dedup"
+    v = H.Volume(spec, codes)
+    sample = torch.from_numpy(W.camera_rays(9, 1, (128,) * 3, 320, 240)).cuda()
+    sc = v.autotune(sample)
+    assert H.schedule_dict(v.get_schedule()) == H.schedule_dict(sc)
+    rays = np.concatenate([W.camera_rays(9, 0, (128,) * 3, 320, 240), W.random_rays(9, (128,) * 3, 20000)])
+    got = gpu_trace(v, rays)
+    ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
+    assert compare(got, ref, f"autotuned {H.schedule_dict(sc)}") == 0
