@@ -251,6 +251,44 @@ def run_surface2048(args, torch, H, W, C):
     return {"occupancy": len(codes) / n ** 3, "formats": out}
 
 
+def run_batched(args, torch, H, W, C):
+    """64 volumes of random hybrid formats, 64 ray batches of uneven size: one graph-captured
+    persistent launch versus one hvf_trace launch per volume on the same stream."""
+    cfg = C.BATCHED
+    t0 = time.time()
+    vols, d_rays, specs, ns = [], [], [], []
+    for i in range(cfg["nvol"]):
+        spec, k, codes, rays = C.batched_case(cfg, i)
+        v = H.Volume(spec, codes)
+        v.upload()
+        vols.append(v)
+        d_rays.append(torch.from_numpy(rays).cuda())
+        specs.append(spec)
+        ns.append(len(rays))
+    total = int(sum(ns))
+    log(f"[bench] batched: {len(vols)} volumes, {total} rays, built in {time.time() - t0:.1f}s")
+    hits_plain = [torch.empty((n, 4), dtype=torch.int32, device="cuda") for n in ns]
+    plain = H.schedule()
+    fns = [lambda v=v, r=r, h=h: v.trace(r, h, sched=plain) for v, r, h in zip(vols, d_rays, hits_plain)]
+    ms_plain, _ = time_launches(fns, args.steps, args.warmup)
+    b = H.Batch(vols, d_rays)
+    opts = b.autotune() if not args.no_tune else H.batch_opts()
+    ms_b, _ = time_launches([b.run], args.steps, args.warmup)
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(b.hits, hits_plain))
+    b.close()
+    rec = {"volumes": len(vols), "rays": total, "ms_batched": round(ms_b, 3), "ms_per_volume_launches": round(ms_plain, 3),
+           "mrays_s_batched": round(total / ms_b / 1e3, 1), "mrays_s_per_volume": round(total / ms_plain / 1e3, 1),
+           "speedup": round(ms_plain / ms_b, 3), "identical_hits": bool(same),
+           "opts": {"refill": opts.refill, "inner": opts.inner, "blocks_per_cu": opts.blocks_per_cu,
+                    "use_graph": opts.use_graph}}
+    log(f"[bench] batched: graph {rec['mrays_s_batched']} Mrays/s vs per-volume {rec['mrays_s_per_volume']} Mrays/s "
+        f"(x{rec['speedup']}), identical={same}, {rec['opts']}")
+    for v in vols:
+        v.close()
+    return rec
+
+
 def cpu_baseline(res512, C, budget_rays):
     """The oracle, as it stands, on a bounded sample of the 512^3 workload."""
     import oracle
@@ -289,7 +327,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2048", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
-    ap.add_argument("--only", choices=["surface512", "surface2048"], default=None,
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only", choices=["surface512", "surface2048", "batched"], default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -308,12 +347,18 @@ def main():
     if args.only == "surface2048":
         run_surface2048(args, torch, H, W, C)
         return
+    if args.only == "batched":
+        run_batched(args, torch, H, W, C)
+        return
     res = run_surface512(args, torch, H, W, C)
     if args.only == "surface512":
         return
     extra = None
     if not args.no_2048:
         extra = run_surface2048(args, torch, H, W, C)
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args, torch, H, W, C)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(res, C, args.cpu_rays)
@@ -329,6 +374,7 @@ def main():
         "cpu_baseline": cpu,
         "per_format": res["per_format"],
         "surface_2048": extra,
+        "batched": batched,
         "kernel_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

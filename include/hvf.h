@@ -133,6 +133,39 @@ hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
 hvf_status hvf_autotune(hvf_volume* vol, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits_scratch,
                         hvf_schedule* out, void* hip_stream);
 
+/* ---------------------------------------------------------------- batching
+ * Many volumes (any formats and sizes) with ray batches of uneven size traced in one
+ * persistent launch: a global counter hands out indices of the concatenated ray space,
+ * idle lanes pick up the next rays (from whichever batch they fall in) whenever at least
+ * `refill` of a wave's 64 lanes are idle. The launch (counter reset + kernel) is captured
+ * once in a hipGraph and replayed by every hvf_batch_run. Each batch's hits are identical
+ * to hvf_trace of that batch alone. */
+typedef struct hvf_batch hvf_batch;
+
+typedef struct hvf_batch_opts {
+  int32_t refill;        /* 1..64 */
+  int32_t inner;         /* traversal steps between refill checks, 1..4096 */
+  int32_t blocks_per_cu; /* 0: as many as fit; else at most this many 256-thread blocks per CU */
+  int32_t use_graph;     /* 1: capture and replay a hipGraph; 0: plain launches */
+} hvf_batch_opts;
+
+/* Describe a batched launch over m batches (1 <= m <= 256; total rays < 2^31): volume
+ * vols[i] traces d_rays[i][0..n[i]) into d_hits[i]. The pointers are captured: the same
+ * device buffers are read and written by every hvf_batch_run. Uploads the volumes.
+ * Volumes must outlive the batch. opts may be NULL (defaults). */
+hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_rays, const size_t* n,
+                            hvf_hit* const* d_hits, size_t m, const hvf_batch_opts* opts, hvf_batch** out);
+
+/* Run (replay) the batched launch on hip_stream; asynchronous. */
+hvf_status hvf_batch_run(hvf_batch* b, void* hip_stream);
+
+/* Time candidate refill/inner/occupancy settings on the batch itself, keep the fastest
+ * (re-capturing the graph) and copy it to *out (may be NULL). Synchronises hip_stream. */
+hvf_status hvf_batch_autotune(hvf_batch* b, void* hip_stream, hvf_batch_opts* out);
+
+/* Release a batch (waits for its device work to finish). NULL is ignored. */
+void hvf_batch_free(hvf_batch* b);
+
 /* Counting variant of hvf_trace, for byte accounting: the same traversal and results,
  * and for ray i the word index of each format load it makes, in order, in
  * d_log[i * cap + k] for k < cap, with the total number of loads in d_count[i] (it may

@@ -62,6 +62,15 @@ def schedule_dict(s: hvf_schedule) -> dict:
     return {"persistent": s.persistent, "refill": s.refill, "inner": s.inner, "sort": s.sort, "sort_bits": s.sort_bits}
 
 
+class hvf_batch_opts(ctypes.Structure):
+    _fields_ = [("refill", ctypes.c_int32), ("inner", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+def batch_opts(refill: int = 16, inner: int = 8, blocks_per_cu: int = 0, use_graph: int = 1) -> hvf_batch_opts:
+    return hvf_batch_opts(refill, inner, blocks_per_cu, use_graph)
+
+
 _lib = None
 
 
@@ -88,6 +97,14 @@ def lib():
         L.hvf_set_schedule.argtypes = [vp, ctypes.POINTER(hvf_schedule)]
         L.hvf_autotune.restype = i32
         L.hvf_autotune.argtypes = [vp, vp, sz, vp, ctypes.POINTER(hvf_schedule), vp]
+        L.hvf_batch_create.restype = i32
+        L.hvf_batch_create.argtypes = [vp, vp, vp, vp, sz, ctypes.POINTER(hvf_batch_opts), ctypes.POINTER(vp)]
+        L.hvf_batch_run.restype = i32
+        L.hvf_batch_run.argtypes = [vp, vp]
+        L.hvf_batch_autotune.restype = i32
+        L.hvf_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(hvf_batch_opts)]
+        L.hvf_batch_free.restype = None
+        L.hvf_batch_free.argtypes = [vp]
         L.hvf_trace_count.restype = i32
         L.hvf_trace_count.argtypes = [vp, vp, sz, vp, vp, ctypes.c_uint32, vp, vp, vp]
         L.hvf_trace_host.restype = i32
@@ -251,6 +268,56 @@ class Volume:
         out = np.empty((len(r), 4), dtype=np.int32)
         _check(lib().hvf_trace_host(self._h, r.ctypes.data, len(r), out.ctypes.data))
         return out
+
+
+class Batch:
+    """Many volumes and ray batches traced in one persistent, graph-captured launch.
+
+    ``vols``: Volume objects; ``rays``: device float32 [n_i, 8] tensors; ``hits``: device
+    int32 [n_i, 4] tensors (allocated if None). The buffers are bound at creation.
+    """
+
+    def __init__(self, vols, rays, hits=None, opts: hvf_batch_opts | None = None):
+        import torch
+        m = len(vols)
+        assert m == len(rays) and m >= 1
+        if hits is None:
+            hits = [torch.empty((r.shape[0], 4), dtype=torch.int32, device=r.device) for r in rays]
+        for r, h in zip(rays, hits):
+            assert r.is_cuda and r.dtype == torch.float32 and r.is_contiguous() and r.shape[-1] == 8
+            assert h.is_cuda and h.dtype == torch.int32 and h.is_contiguous() and h.shape == (r.shape[0], 4)
+        self.vols, self.rays, self.hits = list(vols), list(rays), list(hits)
+        VP = ctypes.c_void_p * m
+        SZ = ctypes.c_size_t * m
+        hv = VP(*[v.handle for v in vols])
+        rv = VP(*[r.data_ptr() for r in rays])
+        nv = SZ(*[r.shape[0] for r in rays])
+        ov = VP(*[h.data_ptr() for h in hits])
+        out = ctypes.c_void_p()
+        _check(lib().hvf_batch_create(ctypes.cast(hv, ctypes.c_void_p), ctypes.cast(rv, ctypes.c_void_p),
+                                      ctypes.cast(nv, ctypes.c_void_p), ctypes.cast(ov, ctypes.c_void_p), m,
+                                      ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+        self._h = out.value
+
+    def run(self, stream=None):
+        _check(lib().hvf_batch_run(self._h, _stream_ptr(stream)))
+        return self.hits
+
+    def autotune(self, stream=None) -> hvf_batch_opts:
+        o = hvf_batch_opts()
+        _check(lib().hvf_batch_autotune(self._h, _stream_ptr(stream), ctypes.byref(o)))
+        return o
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hvf_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols() -> list[str]:

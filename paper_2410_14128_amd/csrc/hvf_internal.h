@@ -93,6 +93,20 @@ struct DevFormat {
 
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf);
 
+// One batch of the batched launch: a volume and its ray / hit arrays. Rays of all
+// batches form one index space; batch b owns indices [first, first + n).
+struct BatchItem {
+  const uint32_t* buf;
+  const void* rays;  // float4 pairs
+  void* hits;        // int4
+  uint64_t pop_lut;
+  uint32_t first;
+  uint32_t n;
+  int32_t ext[3];
+  int32_t ndepth;
+};
+constexpr int HVF_BATCH_MAX_ITEMS = 256;
+
 }  // namespace hvf
 
 // The opaque handle.

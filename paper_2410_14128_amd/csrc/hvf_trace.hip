@@ -135,6 +135,27 @@ __device__ __forceinline__ uint2 ld2(const uint32_t* buf, uint32_t ix) {
 
 enum : int { RUN = 0, DONE = 1 };
 
+// The format a lane walks: word buffer, pop table, per-axis extents and the per-depth
+// descriptor table (in LDS). Uniform across a launch for single-volume kernels; per lane
+// in the batched kernel.
+struct Fmt {
+  const uint32_t* buf;
+  uint64_t pop_lut;
+  const uint32_t* dtab;
+  int ext[3];
+};
+
+__device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab) {
+  Fmt f;
+  f.buf = F.buf;
+  f.pop_lut = F.pop_lut;
+  f.dtab = dtab;
+  f.ext[0] = F.ext[0];
+  f.ext[1] = F.ext[1];
+  f.ext[2] = F.ext[2];
+  return f;
+}
+
 // The per-lane walk state.
 struct Walk {
   Ray R;
@@ -165,8 +186,9 @@ struct Walk {
 
   // Start the walk of a ray that passed setup. Returns DONE if the volume is empty.
   template <class Mem>
-  __device__ __forceinline__ int start(const DevFormat& F, const uint32_t* dtab, Mem& mem) {
+  __device__ __forceinline__ int start(const Fmt& F, Mem& mem) {
     const uint32_t* __restrict__ buf = F.buf;
+    const uint32_t* dtab = F.dtab;
     const uint32_t root = buf[0];  // word 0: pointer to the root sub-volume; 0 = empty
     mem.note(0, 1);
     if (root == 0u) return DONE;
@@ -196,8 +218,9 @@ struct Walk {
 
   // One step. On DONE, out holds the result (a miss leaves it untouched).
   template <class Mem>
-  __device__ __forceinline__ int step(const DevFormat& F, const uint32_t* dtab, uint2* stk, int4& out, Mem& mem) {
+  __device__ __forceinline__ int step(const Fmt& F, uint2* stk, int4& out, Mem& mem) {
     const uint32_t* __restrict__ buf = F.buf;
+    const uint32_t* dtab = F.dtab;
     if (++steps > MAX_STEPS) {
       out = make_int4(-2, -2, -2, 0);  // guard tripped: reported, never silent
       return DONE;
@@ -311,14 +334,15 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
   load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
   int4 out = miss_hit();
   Walk w;
   Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
-    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
+    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
 }
@@ -333,6 +357,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
   load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab);
   uint2* stk = stk_all + threadIdx.x;
   const uint32_t lane = __lane_id();
   Walk w;
@@ -356,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
           ray = id;
           out = miss_hit();
           const float4 r0 = rays[2 * (size_t)id], r1 = rays[2 * (size_t)id + 1];
-          active = setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN;
+          active = setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN;
           if (!active) hits[id] = out;
         }
       }
@@ -364,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
     if (drained && __ballot(active) == 0ull) break;
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
-        if (w.step(F, dtab, stk, out, mem) == DONE) {
+        if (w.step(fm, stk, out, mem) == DONE) {
           hits[ray] = out;
           active = false;
           break;
@@ -382,6 +407,7 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
   load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab);
   const uint32_t k = blockIdx.x * BLOCK + threadIdx.x;
   if (k >= n || key[k] == 0xFFFFFFFFu) return;  // rays that miss the root box were answered
   const uint32_t i = perm[k];
@@ -389,8 +415,8 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   int4 out = miss_hit();
   Walk w;
   Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
-    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
+    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
 }
@@ -441,6 +467,86 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, size_t n) 
   if (i < n) p[i] = v;
 }
 
+// Batched persistent kernel: many volumes (formats, sizes) and ray batches in one launch.
+// A global counter hands out indices of the concatenated ray space; an idle lane finds
+// its batch by binary search over the batch start table, and walks that batch's volume.
+// Per-depth descriptor tables of every batch and the start table live in LDS.
+// LDS layout: dtab[items * 16] | start[items + 1] | stack[max_depth * BLOCK] (uint2).
+__global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __restrict__ items,
+                                                            const uint32_t* __restrict__ dinfo_all, uint32_t nitems,
+                                                            uint32_t total, uint32_t* __restrict__ counter,
+                                                            uint32_t refill, uint32_t inner) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* dt = smem;
+  uint32_t* start = smem + nitems * HVF_MAX_DEPTH;
+  const uint32_t stk_off = (nitems * HVF_MAX_DEPTH + nitems + 1 + 1) & ~1u;
+  uint2* stk = reinterpret_cast<uint2*>(smem + stk_off) + threadIdx.x;
+  for (uint32_t i = threadIdx.x; i < nitems * HVF_MAX_DEPTH; i += BLOCK) dt[i] = dinfo_all[i];
+  for (uint32_t i = threadIdx.x; i < nitems; i += BLOCK) start[i] = items[i].first;
+  if (threadIdx.x == 0) start[nitems] = total;
+  __syncthreads();
+  const uint32_t lane = __lane_id();
+  Walk w;
+  Plain mem;
+  Fmt fm;
+  fm.buf = nullptr;
+  fm.pop_lut = 0;
+  fm.dtab = dt;
+  fm.ext[0] = fm.ext[1] = fm.ext[2] = 0;
+  int4* hits = nullptr;
+  bool active = false;
+  uint32_t ray = 0;
+  int4 out = miss_hit();
+  bool drained = false;
+  for (;;) {
+    const uint64_t idle = __ballot(!active);
+    const uint32_t nidle = (uint32_t)__popcll(idle);
+    if (!drained && (nidle >= refill || nidle == 64u)) {
+      const int leader = __ffsll((unsigned long long)idle) - 1;
+      uint32_t first = 0;
+      if ((int)lane == leader) first = atomicAdd(counter, nidle);
+      first = __shfl(first, leader);
+      if (first >= total) drained = true;
+      if (!active) {
+        const uint32_t id = first + (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+        if (id < total) {
+          // batch b: the last with start[b] <= id
+          uint32_t lo = 0, hi = nitems;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (start[mid] <= id) lo = mid;
+            else hi = mid;
+          }
+          const BatchItem& it = items[lo];
+          fm.buf = it.buf;
+          fm.pop_lut = it.pop_lut;
+          fm.dtab = dt + lo * HVF_MAX_DEPTH;
+          fm.ext[0] = it.ext[0];
+          fm.ext[1] = it.ext[1];
+          fm.ext[2] = it.ext[2];
+          hits = reinterpret_cast<int4*>(it.hits);
+          ray = id - it.first;
+          const float4* rays = reinterpret_cast<const float4*>(it.rays);
+          const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
+          out = miss_hit();
+          active = setup(r0, r1, fm.ext, w.R) && w.start(fm, mem) == RUN;
+          if (!active) hits[ray] = out;
+        }
+      }
+    }
+    if (drained && __ballot(active) == 0ull) break;
+    if (active) {
+      for (uint32_t k = 0; k < inner; ++k) {
+        if (w.step(fm, stk, out, mem) == DONE) {
+          hits[ray] = out;
+          active = false;
+          break;
+        }
+      }
+    }
+  }
+}
+
 // Same traversal as trace_kernel, logging the word index of every format load:
 // log[i * cap + k] for the first cap loads of ray i; count[i] = number of loads.
 __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, const float4* __restrict__ rays,
@@ -451,6 +557,7 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
   load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
@@ -458,8 +565,8 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   Walk w;
   Counting mem{log + (size_t)i * cap, cap, 0u};
   w.steps = 0;
-  if (setup(r0, r1, F.ext, w.R) && w.start(F, dtab, mem) == RUN)
-    while (w.step(F, dtab, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
+    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
   count[i] = mem.k;
@@ -524,6 +631,42 @@ hvf_status launch_trace_persistent(const DevFormat& F, const hvf_ray* d_rays, si
                      reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_counter,
                      refill, inner);
   return launch_check("persistent trace");
+}
+
+size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
+  const size_t words = ((size_t)nitems * HVF_MAX_DEPTH + nitems + 1 + 1) & ~(size_t)1;
+  return words * 4 + (size_t)max_depth * BLOCK * sizeof(uint2);
+}
+
+hvf_status batch_grid(uint32_t nitems, int max_depth, int blocks_per_cu, unsigned* grid) {
+  if (g_cu_count < 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      hvf_set_error("hipGetDeviceProperties failed");
+      return HVF_E_DEVICE;
+    }
+    g_cu_count = prop.multiProcessorCount;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel, BLOCK,
+                                                   batch_lds_bytes(nitems, max_depth)) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
+  *grid = (unsigned)(g_cu_count * per_cu);
+  return HVF_OK;
+}
+
+hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo, uint32_t nitems, uint32_t total,
+                              int max_depth, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, d_counter, 0u, (size_t)1);
+  hvf_status st = launch_check("fill");
+  if (st != HVF_OK) return st;
+  hipLaunchKernelGGL(trace_batch_kernel, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s, d_items,
+                     d_dinfo, nitems, total, d_counter, refill, inner);
+  return launch_check("batched trace");
 }
 
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {

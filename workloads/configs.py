@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import camera_rays, scene_shell, scene_solid_noise
+from . import camera_rays, random_rays, scene_shell, scene_solid_noise
 
 # Small case: 64^3 solid spheres (radii U[4,16]) OR 5% Bernoulli noise; 256x256 pinhole.
 SMALL = dict(name="small-64", log2n=6, seed=1, spec="R(2,2,2) S(2) R(2,2,2)", width=256, height=256, views=1)
@@ -44,3 +44,44 @@ def scene(cfg: dict) -> np.ndarray:
 def primary_rays(cfg: dict, view: int, width: int | None = None, height: int | None = None) -> np.ndarray:
     n = 1 << cfg["log2n"]
     return camera_rays(cfg["seed"], view, (n, n, n), width or cfg["width"], height or cfg["height"])
+
+
+# Batched: 64 volumes, side 2^k with k ~ U{6..10}; shell scenes with max(4, N/16)
+# primitives; each a seeded random hybrid format of 2 or 3 levels with kinds uniform over
+# {R, S, G} (k split into positive parts, Raw exponents <= 5); 64 ray batches of size
+# round(exp(U[ln 4096, ln 2^21])), half pinhole rays, half random origins and directions.
+BATCHED = dict(name="batched-64", seed=4, nvol=64, kmin=6, kmax=10, nmin=4096, nmax=1 << 21)
+
+
+def batched_format(rng: np.random.Generator, k: int) -> str:
+    while True:
+        nlev = int(rng.integers(2, 4))
+        kinds = [str(rng.choice(["R", "S", "G"])) for _ in range(nlev)]
+        cuts = np.sort(rng.choice(np.arange(1, k), size=nlev - 1, replace=False)) if k > nlev - 1 else None
+        if cuts is None:
+            continue
+        parts = np.diff(np.concatenate([[0], cuts, [k]])).tolist()
+        if any(kd == "R" and p > 5 for kd, p in zip(kinds, parts)):
+            continue
+        spec = " ".join(f"R({p},{p},{p})" if kd == "R" else f"{kd}({p})" for kd, p in zip(kinds, parts))
+        if "G" in kinds and rng.random() < 0.5:
+            spec += " --whole-level-dedup"
+        return spec
+
+
+def batched_case(cfg: dict, i: int, scale_rays: float = 1.0):
+    """Volume i of the batched workload: (spec, log2 side, Morton codes, rays)."""
+    rng = np.random.default_rng([cfg["seed"], i])
+    k = int(rng.integers(cfg["kmin"], cfg["kmax"] + 1))
+    spec = batched_format(rng, k)
+    n_side = 1 << k
+    prims = max(4, n_side // 16)
+    codes = scene_shell(cfg["seed"] * 1000 + i, k, prims - prims // 4, prims // 4, 1.4)
+    n = int(round(np.exp(rng.uniform(np.log(cfg["nmin"]), np.log(cfg["nmax"])))) * scale_rays)
+    n = max(64, n)
+    half = n // 2
+    w = max(1, int(round(np.sqrt(half * 16 / 9))))
+    h = (half + w - 1) // w
+    cam = camera_rays(cfg["seed"] * 1000 + i, 0, (n_side,) * 3, w, h)[:half]
+    rnd = random_rays(cfg["seed"] * 1000 + i, (n_side,) * 3, n - half)
+    return spec, k, codes, np.ascontiguousarray(np.concatenate([cam, rnd]))
