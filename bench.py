@@ -289,6 +289,111 @@ def run_batched(args, torch, H, W, C):
     return rec
 
 
+def run_served(args, torch, H, W, C):
+    """Poisson request streams against the server; p50/p99 latency and Mrays/s at 0.5, 0.8
+    and 0.95 of the closed-loop saturation rate, plus a one-request-at-a-time baseline."""
+    cfg = C.SERVED
+    t0 = time.time()
+    vols, pools = [], []
+    for i in range(len(cfg["sides"])):
+        spec, k, codes = C.served_volume(cfg, i)
+        v = H.Volume(spec, codes)
+        v.upload()
+        vols.append(v)
+        del codes
+        n = 1 << k
+        per = []
+
+        def pinned(a):
+            p = torch.empty(a.shape, dtype=torch.float32, pin_memory=True).numpy()
+            p[...] = a
+            return p
+
+        for j, (w, h) in enumerate(cfg["resolutions"]):
+            prim = W.camera_rays(cfg["seed"] * 100 + i, j, (n, n, n), w, h)
+            hp = v.trace(torch.from_numpy(prim).cuda()).cpu().numpy()
+            b, _ = W.bounce_rays(cfg["seed"] * 100 + i + 7, prim, hp)
+            per.append((pinned(prim), pinned(np.ascontiguousarray(b))))
+        pools.append(per)
+    torch.cuda.synchronize()
+    log(f"[bench] served: {len(vols)} volumes resident "
+        f"({sum(v.info()['bytes'] for v in vols) / 2 ** 30:.2f} GiB), ray pools ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(cfg["seed"])
+    nreq = args.serve_requests + args.serve_warmup
+    plan = [(int(rng.integers(0, len(vols))), int(rng.integers(0, 4)), bool(rng.random() < cfg["bounce_p"]))
+            for _ in range(nreq)]
+
+    def run(arrivals, slots, steps):
+        srv = H.Server(args.serve_budget << 20, max_slots=slots, max_steps=steps)
+        ids = [srv.add_volume(v) for v in vols]
+        start = time.perf_counter()
+        pending = {}  # primary request id -> plan index
+        follow = {}   # bounce request id -> plan index
+        t_sub = {}
+        lat = {}
+        rays_total = 0
+        k = 0
+        while k < nreq or pending or follow:
+            now = time.perf_counter() - start
+            while k < nreq and arrivals[k] <= now:
+                vi, ri, bounce = plan[k]
+                prim = pools[vi][ri][0]
+                rid = srv.submit(ids[vi], prim, hold=True)
+                pending[rid] = k
+                t_sub[k] = start + arrivals[k]
+                rays_total += len(prim)
+                k += 1
+            for rid in list(pending):
+                done, _ = srv.poll(rid)
+                if done:
+                    j = pending.pop(rid)
+                    srv.release(rid)
+                    vi, ri, bounce = plan[j]
+                    if bounce and len(pools[vi][ri][1]):
+                        b = pools[vi][ri][1]
+                        follow[srv.submit(ids[vi], b, hold=True)] = j
+                        rays_total += len(b)
+                    else:
+                        lat[j] = (time.perf_counter() - t_sub[j]) * 1e3
+            for rid in list(follow):
+                done, _ = srv.poll(rid)
+                if done:
+                    j = follow.pop(rid)
+                    srv.release(rid)
+                    lat[j] = (time.perf_counter() - t_sub[j]) * 1e3
+            if k < nreq and not pending and not follow:
+                time.sleep(max(0.0, min(0.0005, arrivals[k] - (time.perf_counter() - start))))
+        span = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        L = np.array([lat[j] for j in range(args.serve_warmup, nreq)])
+        return {"p50_ms": round(float(np.percentile(L, 50)), 3), "p99_ms": round(float(np.percentile(L, 99)), 3),
+                "mean_ms": round(float(L.mean()), 3), "mrays_s": round(rays_total / span / 1e6, 1),
+                "requests_per_s": round(nreq / span, 1), "steps": int(st["steps"]),
+                "max_step_requests": int(st["max_step_requests"]), "admission_waits": int(st["admission_waits"]),
+                "peak_mib": round(st["peak_bytes"] / 2 ** 20, 1)}
+
+    burst = run(np.zeros(nreq), args.serve_slots, 3)
+    sat = burst["requests_per_s"]
+    log(f"[bench] served: closed-loop saturation {sat:.0f} requests/s, {burst['mrays_s']} Mrays/s")
+    levels = {}
+    for frac in (0.5, 0.8, 0.95):
+        gaps = rng.exponential(1.0 / (frac * sat), size=nreq)
+        arr = np.cumsum(gaps) - gaps[0]
+        levels[str(frac)] = run(arr, args.serve_slots, 3)
+        log(f"[bench] served @ {frac:.2f} S: p50 {levels[str(frac)]['p50_ms']} ms, p99 {levels[str(frac)]['p99_ms']} ms, "
+            f"{levels[str(frac)]['mrays_s']} Mrays/s")
+    gaps = rng.exponential(1.0 / (0.8 * sat), size=nreq)
+    arr = np.cumsum(gaps) - gaps[0]
+    fifo = run(arr, 1, 1)
+    log(f"[bench] served FIFO one-at-a-time @ 0.80 S: p50 {fifo['p50_ms']} ms, p99 {fifo['p99_ms']} ms, "
+        f"{fifo['mrays_s']} Mrays/s")
+    for v in vols:
+        v.close()
+    return {"volumes": len(vols), "saturation_requests_per_s": sat, "closed_loop": burst, "poisson": levels,
+            "fifo_at_0.8": fifo, "budget_mib": args.serve_budget, "slots": args.serve_slots}
+
+
 def cpu_baseline(res512, C, budget_rays):
     """The oracle, as it stands, on a bounded sample of the 512^3 workload."""
     import oracle
@@ -328,7 +433,12 @@ def main():
     ap.add_argument("--no-2048", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--only", choices=["surface512", "surface2048", "batched"], default=None,
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=60)
+    ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--only", choices=["surface512", "surface2048", "batched", "served"], default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -350,6 +460,9 @@ def main():
     if args.only == "batched":
         run_batched(args, torch, H, W, C)
         return
+    if args.only == "served":
+        print(json.dumps(run_served(args, torch, H, W, C)))
+        return
     res = run_surface512(args, torch, H, W, C)
     if args.only == "surface512":
         return
@@ -359,6 +472,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = run_batched(args, torch, H, W, C)
+    served = None
+    if not args.no_served:
+        served = run_served(args, torch, H, W, C)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(res, C, args.cpu_rays)
@@ -375,6 +491,7 @@ def main():
         "per_format": res["per_format"],
         "surface_2048": extra,
         "batched": batched,
+        "served": served,
         "kernel_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

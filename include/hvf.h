@@ -166,6 +166,59 @@ hvf_status hvf_batch_autotune(hvf_batch* b, void* hip_stream, hvf_batch_opts* ou
 /* Release a batch (waits for its device work to finish). NULL is ignored. */
 void hvf_batch_free(hvf_batch* b);
 
+/* ---------------------------------------------------------------- serving
+ * A server keeps volumes resident in device memory and serves trace requests as they
+ * arrive. Requests queue in arrival order and are admitted while fewer than max_slots are
+ * in flight and the request's device footprint (48 bytes per ray, 256-byte granules) fits
+ * in the free part of the memory budget; the rest wait. An engine thread packs every
+ * admitted request into the next step (one batched persistent launch, with the ray upload
+ * and hit download) on one of max_steps streams, so requests that arrive while others run
+ * are admitted and overlap on the device. Each request's hits are identical to hvf_trace
+ * of that request alone. Latency = submission to hits available in the caller's array. */
+typedef struct hvf_server hvf_server;
+
+#define HVF_SERVER_MAX_VOLUMES 1024
+
+typedef struct hvf_serve_stats {
+  uint64_t completed;
+  double p50_ms, p99_ms, mean_ms, max_ms;
+  uint64_t rays;
+  double span_ms;  /* first submission to last completion */
+  double mrays_s;  /* rays / span */
+  uint64_t steps;
+  uint64_t admission_waits;
+  uint64_t peak_bytes, budget_bytes;
+  uint64_t max_step_requests;
+} hvf_serve_stats;
+
+/* mem_budget_bytes: device (and pinned host staging) memory for in-flight requests.
+ * max_slots: requests in flight at once (>= 1). max_steps: batched launches in flight at
+ * once, each on its own stream (1..8). opts: kernel schedule (NULL: defaults; use_graph is
+ * ignored). max_slots = max_steps = 1 serves one request at a time in arrival order. */
+hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_steps, const hvf_batch_opts* opts,
+                             hvf_server** out);
+/* Make a volume resident (uploads it); it must outlive the server. */
+hvf_status hvf_server_add_volume(hvf_server* s, hvf_volume* vol, int* vol_id);
+/* Queue a request: n host rays, results into n host hits. Non-blocking. Both arrays must
+ * stay valid until the request completes. Rays in pinned host memory are copied to the
+ * device directly; others are first copied into the server's pinned staging. hits may be
+ * NULL: the results then stay in the server's staging (read them with
+ * hvf_server_result) and keep their memory until hvf_server_release. HVF_E_NOMEM if the
+ * request can never fit the budget. */
+hvf_status hvf_server_submit(hvf_server* s, int vol_id, const hvf_ray* rays, size_t n, hvf_hit* hits,
+                             uint64_t* req_id);
+hvf_status hvf_server_poll(hvf_server* s, uint64_t req_id, int* done, double* latency_ms);
+/* Results of a completed request submitted with hits == NULL (valid until released). */
+hvf_status hvf_server_result(hvf_server* s, uint64_t req_id, const hvf_hit** hits);
+/* Forget a completed request; frees its memory if the server held its results. */
+hvf_status hvf_server_release(hvf_server* s, uint64_t req_id);
+hvf_status hvf_server_wait(hvf_server* s, uint64_t req_id, double* latency_ms);
+/* Wait until every submitted request has completed. */
+hvf_status hvf_server_drain(hvf_server* s);
+hvf_status hvf_server_stats(hvf_server* s, hvf_serve_stats* out);
+/* Finish queued work, then release the server (not the volumes). NULL is ignored. */
+void hvf_server_destroy(hvf_server* s);
+
 /* Counting variant of hvf_trace, for byte accounting: the same traversal and results,
  * and for ray i the word index of each format load it makes, in order, in
  * d_log[i * cap + k] for k < cap, with the total number of loads in d_count[i] (it may

@@ -71,6 +71,14 @@ def batch_opts(refill: int = 16, inner: int = 8, blocks_per_cu: int = 0, use_gra
     return hvf_batch_opts(refill, inner, blocks_per_cu, use_graph)
 
 
+class hvf_serve_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("rays", ctypes.c_uint64),
+                ("span_ms", ctypes.c_double), ("mrays_s", ctypes.c_double), ("steps", ctypes.c_uint64),
+                ("admission_waits", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("max_step_requests", ctypes.c_uint64)]
+
+
 _lib = None
 
 
@@ -105,6 +113,26 @@ def lib():
         L.hvf_batch_autotune.argtypes = [vp, vp, ctypes.POINTER(hvf_batch_opts)]
         L.hvf_batch_free.restype = None
         L.hvf_batch_free.argtypes = [vp]
+        L.hvf_server_create.restype = i32
+        L.hvf_server_create.argtypes = [sz, i32, i32, ctypes.POINTER(hvf_batch_opts), ctypes.POINTER(vp)]
+        L.hvf_server_add_volume.restype = i32
+        L.hvf_server_add_volume.argtypes = [vp, vp, ctypes.POINTER(i32)]
+        L.hvf_server_submit.restype = i32
+        L.hvf_server_submit.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.hvf_server_poll.restype = i32
+        L.hvf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+        L.hvf_server_wait.restype = i32
+        L.hvf_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+        L.hvf_server_result.restype = i32
+        L.hvf_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.hvf_server_release.restype = i32
+        L.hvf_server_release.argtypes = [vp, ctypes.c_uint64]
+        L.hvf_server_drain.restype = i32
+        L.hvf_server_drain.argtypes = [vp]
+        L.hvf_server_stats.restype = i32
+        L.hvf_server_stats.argtypes = [vp, ctypes.POINTER(hvf_serve_stats)]
+        L.hvf_server_destroy.restype = None
+        L.hvf_server_destroy.argtypes = [vp]
         L.hvf_trace_count.restype = i32
         L.hvf_trace_count.argtypes = [vp, vp, sz, vp, vp, ctypes.c_uint32, vp, vp, vp]
         L.hvf_trace_host.restype = i32
@@ -312,6 +340,86 @@ class Batch:
         if getattr(self, "_h", None):
             lib().hvf_batch_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Resident volumes, memory-gated admission, continuous batching (see include/hvf.h)."""
+
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 64, max_steps: int = 3,
+                 opts: hvf_batch_opts | None = None):
+        out = ctypes.c_void_p()
+        _check(lib().hvf_server_create(mem_budget_bytes, max_slots, max_steps,
+                                       ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
+        self._h = out.value
+        self._keep = {}  # request id -> (rays, hits) host arrays kept alive until completion
+
+    def add_volume(self, vol: "Volume") -> int:
+        vid = ctypes.c_int()
+        _check(lib().hvf_server_add_volume(self._h, vol.handle, ctypes.byref(vid)))
+        return vid.value
+
+    def submit(self, vol_id: int, rays: np.ndarray, hits: np.ndarray | None = None, hold: bool = False) -> int:
+        """Queue a request. hold=True: results stay in server staging (see result/release)."""
+        r = np.ascontiguousarray(rays, dtype=np.float32)
+        assert r.ndim == 2 and r.shape[1] == 8
+        if hits is None and not hold:
+            hits = np.empty((len(r), 4), dtype=np.int32)
+        if hits is not None:
+            assert hits.dtype == np.int32 and hits.shape == (len(r), 4) and hits.flags.c_contiguous
+        rid = ctypes.c_uint64()
+        _check(lib().hvf_server_submit(self._h, vol_id, r.ctypes.data if len(r) else None, len(r),
+                                       hits.ctypes.data if (hits is not None and len(r)) else None,
+                                       ctypes.byref(rid)))
+        self._keep[rid.value] = (r, hits)
+        return rid.value
+
+    def result(self, req_id: int) -> np.ndarray:
+        """View of a held request's hits in server staging (valid until release)."""
+        p = ctypes.c_void_p()
+        _check(lib().hvf_server_result(self._h, req_id, ctypes.byref(p)))
+        n = len(self._keep[req_id][0])
+        if n == 0:
+            return np.zeros((0, 4), np.int32)
+        buf = (ctypes.c_int32 * (4 * n)).from_address(p.value)
+        return np.frombuffer(buf, dtype=np.int32).reshape(n, 4)
+
+    def release(self, req_id: int):
+        _check(lib().hvf_server_release(self._h, req_id))
+        self._keep.pop(req_id, None)
+
+    def poll(self, req_id: int):
+        done, lat = ctypes.c_int(), ctypes.c_double()
+        _check(lib().hvf_server_poll(self._h, req_id, ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def wait(self, req_id: int):
+        """Block until done; returns (hits, latency_ms). Held requests: (None, latency)."""
+        lat = ctypes.c_double()
+        _check(lib().hvf_server_wait(self._h, req_id, ctypes.byref(lat)))
+        r, h = self._keep[req_id]
+        if h is not None:
+            self._keep.pop(req_id)
+        return h, lat.value
+
+    def drain(self):
+        _check(lib().hvf_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = hvf_serve_stats()
+        _check(lib().hvf_server_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in hvf_serve_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hvf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

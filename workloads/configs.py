@@ -85,3 +85,19 @@ def batched_case(cfg: dict, i: int, scale_rays: float = 1.0):
     cam = camera_rays(cfg["seed"] * 1000 + i, 0, (n_side,) * 3, w, h)[:half]
     rnd = random_rays(cfg["seed"] * 1000 + i, (n_side,) * 3, n - half)
     return spec, k, codes, np.ascontiguousarray(np.concatenate([cam, rnd]))
+
+
+# Served: 16 resident volumes -- 4 each at 256^3, 512^3, 1024^3 and 2 each at 2048^3,
+# 4096^3 -- shells of 32*N/512 primitives in the format G(k-4) R(4,4,4) with whole-level
+# de-duplication; requests are seeded cameras at a resolution uniform over
+# {256x256, 512x512, 1280x720, 1920x1080}, half of them followed by one bounce per hit.
+SERVED = dict(name="served-16", seed=5, sides=[8, 8, 8, 8, 9, 9, 9, 9, 10, 10, 10, 10, 11, 11, 12, 12],
+              resolutions=[(256, 256), (512, 512), (1280, 720), (1920, 1080)], bounce_p=0.5)
+
+
+def served_volume(cfg: dict, i: int):
+    k = cfg["sides"][i]
+    n = 1 << k
+    prims = 32 * n // 512
+    codes = scene_shell(cfg["seed"] * 100 + i, k, prims - prims // 4, prims // 4, 1.2)
+    return f"G({k - 4}) R(4,4,4) --whole-level-dedup", k, codes
