@@ -6,7 +6,10 @@
 //
 // What it computes (Hybrid Voxel Formats, Sec. 3 and Sec. 4):
 //   * build: a hybrid format is a list of levels, each a base format -- Raw R(W,H,D),
-//     SVO S(L) or SVDAG G(L) (Table "Description of Implemented Formats"). Construction
+//     distance field D(W,H,D,M), SVO S(L) or SVDAG G(L) (Table "Description of
+//     Implemented Formats"). A DF level is built like a Raw level, then each cell gets the
+//     L1 distance to the nearest non-empty cell of its grid, capped at M, interleaved with
+//     the cell's terminating integer (Sec. 3.3, Sec. 4.1). Construction
 //     follows Sec. 4.1 and the construct() pseudo-code: each level visits its child
 //     sub-volumes in Morton order (Sec. 5), writes every non-empty child sub-volume to the
 //     word buffer ("disk") and records its pointer; empty children are 0. SVO nodes are two
@@ -20,7 +23,9 @@
 //     each level visits its non-empty hit children in order of hit time and calls the
 //     next level on them, returning at the first single voxel hit (Sec. 4.2 and the
 //     intersect() pseudo-code). Raw levels walk their grid with a DDA (Amanatides & Woo);
-//     SVO/SVDAG levels recurse over octants in entry-time order.
+//     DF levels walk the same DDA but do not check occupancy while the walk stays within
+//     the stored distance of the last empty cell they read (Sec. 4.2); SVO/SVDAG levels
+//     recurse over octants in entry-time order.
 //   * flat_dda: the same first-hit query on a dense occupancy bitset (a single Raw level).
 //   * brute: the plain definition -- among all occupied voxels, the visited one with the
 //     smallest entry time.
@@ -46,8 +51,9 @@ namespace {
 
 // ------------------------------------------------------------------ format description
 struct Level {
-  char kind;  // 'R', 'S', 'G'
+  char kind;  // 'R', 'D', 'S', 'G'
   int e[3];   // log2 of the number of cells per axis (S/G: depth L on every axis)
+  int M = 0;  // DF: maximum stored L1 distance
 };
 
 struct Format {
@@ -87,6 +93,8 @@ bool parse_spec(const char* spec, Format& f) {
       std::string flag = s.substr(i, j - i);
       if (flag == "--whole-level-dedup" || flag == "-whole-level-dedup" || flag == "--wld")
         f.wld = true;
+      else if (flag == "--restart-sv" || flag == "-restart-sv")
+        ;  // restarting intersection (Sec. 4.3) changes how a tracer revisits nodes, not the result
       else {
         g_err = "unknown flag " + flag;
         return false;
@@ -94,7 +102,7 @@ bool parse_spec(const char* spec, Format& f) {
       i = j;
       continue;
     }
-    if (c != 'R' && c != 'S' && c != 'G') {
+    if (c != 'R' && c != 'D' && c != 'S' && c != 'G') {
       g_err = std::string("unknown level kind '") + c + "'";
       return false;
     }
@@ -142,6 +150,13 @@ bool parse_spec(const char* spec, Format& f) {
         return false;
       }
       for (int a = 0; a < 3; ++a) L.e[a] = args[a];
+    } else if (c == 'D') {
+      if (args.size() != 4 || args[3] < 1) {
+        g_err = "D needs 3 exponents and a maximum distance >= 1";
+        return false;
+      }
+      for (int a = 0; a < 3; ++a) L.e[a] = args[a];
+      L.M = args[3];
     } else {
       if (args.size() != 1 || args[0] < 1) {
         g_err = "S/G need one depth >= 1";
@@ -253,7 +268,7 @@ struct Builder {
       empty = true;
       return {};
     }
-    if (L.kind == 'R') {
+    if (L.kind == 'R' || L.kind == 'D') {
       int64_t nx = 1 << L.e[0], ny = 1 << L.e[1], nz = 1 << L.e[2];
       std::vector<uint32_t> arr((size_t)(nx * ny * nz), 0u);
       empty = true;
@@ -270,11 +285,45 @@ struct Builder {
         if (t) empty = false;
       }
       V.node_count[k] += empty ? 0 : 1;
+      if (L.kind == 'D') return with_distances(arr, nx, ny, nz, L.M);
       return arr;
     }
     DedupMap local;
     DedupMap& map = V.f.wld ? level_maps[k] : local;
     return node(k, 0, x, y, z, lo, hi, map, empty);
+  }
+
+  // DF sub-volume: per cell the L1 distance to the nearest non-empty cell of this grid,
+  // capped at M, interleaved with the cell's terminating integer. The L1 distance
+  // transform is separable: relax d[i] = min(d[i], d[i-1] + 1) forwards then backwards
+  // along x, then along y, then along z.
+  static std::vector<uint32_t> with_distances(const std::vector<uint32_t>& t, int64_t nx, int64_t ny, int64_t nz,
+                                              int M) {
+    const int64_t big = nx + ny + nz + 1;
+    std::vector<int64_t> d(t.size());
+    for (size_t i = 0; i < t.size(); ++i) d[i] = t[i] ? 0 : big;
+    auto idx = [&](int64_t x, int64_t y, int64_t z) { return (size_t)(x + nx * (y + ny * z)); };
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t y = 0; y < ny; ++y) {
+        for (int64_t x = 1; x < nx; ++x) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x - 1, y, z)] + 1);
+        for (int64_t x = nx - 2; x >= 0; --x) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x + 1, y, z)] + 1);
+      }
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t x = 0; x < nx; ++x) {
+        for (int64_t y = 1; y < ny; ++y) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x, y - 1, z)] + 1);
+        for (int64_t y = ny - 2; y >= 0; --y) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x, y + 1, z)] + 1);
+      }
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        for (int64_t z = 1; z < nz; ++z) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x, y, z - 1)] + 1);
+        for (int64_t z = nz - 2; z >= 0; --z) d[idx(x, y, z)] = std::min(d[idx(x, y, z)], d[idx(x, y, z + 1)] + 1);
+      }
+    std::vector<uint32_t> out(2 * t.size());
+    for (size_t i = 0; i < t.size(); ++i) {
+      out[2 * i] = t[i];
+      out[2 * i + 1] = (uint32_t)std::min<int64_t>(d[i], M);
+    }
+    return out;
   }
 
   // SVO / SVDAG node at depth j (0 = root) of level k covering a cube of side 2^(L-j) cells.
@@ -440,7 +489,7 @@ struct Tracer {
   // Level k, sub-volume at pointer p with lower corner lo, entered on [te, tx).
   bool intersect(int k, uint32_t p, const int64_t lo[3], float te, float tx, Hit& h) const {
     const Level& L = V.f.lv[k];
-    if (L.kind == 'R') return raw(k, p, lo, te, tx, h);
+    if (L.kind == 'R' || L.kind == 'D') return raw(k, p, lo, te, tx, h);
     return octree(k, 0, p, lo, te, tx, h);
   }
 
@@ -478,11 +527,21 @@ struct Tracer {
       }
       if (cell[a] < 0) return false;  // te outside this sub-volume along a (empty interval)
     }
+    const bool df = (L.kind == 'D');
+    const size_t stride = df ? 2 : 1;
+    int64_t anchor[3] = {0, 0, 0}, reach = 0;  // DF: cells at L1 distance < reach from anchor are empty
     for (;;) {
       int64_t clo[3] = {lo[0] + (cell[0] << cs), lo[1] + (cell[1] << cs), lo[2] + (cell[2] << cs)};
+      const int64_t l1 = std::abs(cell[0] - anchor[0]) + std::abs(cell[1] - anchor[1]) + std::abs(cell[2] - anchor[2]);
+      const bool known_empty = df && l1 < reach;
       float e, x;
-      if (interval(c, clo, cs, te, tx, e, x) && e < x) {
-        uint32_t term = V.words[(size_t)p + (size_t)(cell[0] + n[0] * (cell[1] + n[1] * cell[2]))];
+      if (!known_empty && interval(c, clo, cs, te, tx, e, x) && e < x) {
+        const size_t at = (size_t)p + stride * (size_t)(cell[0] + n[0] * (cell[1] + n[1] * cell[2]));
+        uint32_t term = V.words[at];
+        if (df && term == 0) {  // march up to this many cells before checking again
+          reach = V.words[at + 1];
+          for (int a = 0; a < 3; ++a) anchor[a] = cell[a];
+        }
         if (visit_child(k, term, clo, e, x, h)) return true;
       }
       // Next cell: the least far-plane time among non-parallel axes.
@@ -569,12 +628,13 @@ struct Decoder {
   void level(int k, uint32_t p, const int64_t lo[3]) {
     const Level& L = V.f.lv[k];
     int cs = V.f.sub[k + 1];
-    if (L.kind == 'R') {
+    if (L.kind == 'R' || L.kind == 'D') {
       int64_t n[3] = {1 << L.e[0], 1 << L.e[1], 1 << L.e[2]};
+      const size_t stride = (L.kind == 'D') ? 2 : 1;
       for (int64_t z = 0; z < n[2]; ++z)
         for (int64_t y = 0; y < n[1]; ++y)
           for (int64_t x = 0; x < n[0]; ++x) {
-            uint32_t t = V.words[(size_t)p + (size_t)(x + n[0] * (y + n[1] * z))];
+            uint32_t t = V.words[(size_t)p + stride * (size_t)(x + n[0] * (y + n[1] * z))];
             int64_t clo[3] = {lo[0] + (x << cs), lo[1] + (y << cs), lo[2] + (z << cs)};
             term(k, t, clo);
           }

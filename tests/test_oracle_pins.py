@@ -77,15 +77,11 @@ def test_table_of_formats_extents():
             continue
         label, side, spec = line.split(maxsplit=2)
         spec = spec.strip()
-        if "D(" in spec:  # distance-field levels are not built by this oracle
-            with pytest.raises(oracle.OracleError):
-                oracle.parse(spec)
-            continue
         nlev, ext = oracle.parse(spec)
         assert ext == (int(side).bit_length() - 1,) * 3, (label, spec, ext)
         assert nlev == spec.count("(")
         n += 1
-    assert n == 27  # 13 of the 40 use distance-field levels
+    assert n == 40
 
 
 def test_composition_example_extents():
@@ -355,3 +351,95 @@ def test_multithreaded_trace_matches_single():
     vol = oracle.Volume("R(2,2,2) S(2) R(2,2,2)", codes)
     rays = W.camera_rays(1, 0, (64, 64, 64), 64, 48)
     assert np.array_equal(vol.trace(rays, 1), vol.trace(rays, 4))
+
+
+# ------------------------------------------------------------------ distance-field levels
+def _l1_brute(occ, cap):
+    """Capped L1 distance from every cell to the nearest occupied cell, by exhaustive search."""
+    nz, ny, nx = occ.shape
+    pts = np.argwhere(occ)  # (z, y, x)
+    out = np.full(occ.shape, cap, np.int64)
+    if len(pts) == 0:
+        return out
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                d = np.abs(pts - np.array([z, y, x])).sum(axis=1).min()
+                out[z, y, x] = min(cap, d)
+    return out
+
+
+@pytest.mark.parametrize("p,cap", [(0.02, 6), (0.1, 2), (0.004, 100), (0.3, 1)])
+def test_df_distances_brute_force(p, cap):
+    """A one-level DF grid stores (terminating integer, capped L1 distance) per cell (Sec. 3.3)."""
+    codes = W.scene_bernoulli(int(p * 1000) + cap, 3, 2, 4, p)
+    occ = dense_of([tuple(v) for v in W.morton_decode(codes)], (3, 2, 4))
+    w = oracle.Volume("D(3,2,4,%d)" % cap, codes).words()
+    assert w[0] == 1 and len(w) == 1 + 2 * occ.size
+    term = w[1::2].reshape(occ.shape)
+    dist = w[2::2].reshape(occ.shape)
+    assert np.array_equal(term != 0, occ.astype(bool))
+    assert np.array_equal(dist, _l1_brute(occ, cap))
+
+
+def test_df_distances_two_levels():
+    """Above a lower level, the distance counts non-empty sub-volumes of the DF grid (Sec. 4.1)."""
+    codes = W.scene_bernoulli(21, 4, 4, 4, 0.004)
+    sub = np.zeros((4, 4, 4), np.uint8)  # occupancy of the 4x4x4 grid of 4^3 sub-volumes
+    for x, y, z in W.morton_decode(codes):
+        sub[z >> 2, y >> 2, x >> 2] = 1
+    w = oracle.Volume("D(2,2,2,5) R(2,2,2)", codes).words()
+    root = int(w[0])  # children are written before the grid that points at them
+    dist = w[root + 1:root + 2 * 64:2].reshape(4, 4, 4)
+    assert np.array_equal(dist, _l1_brute(sub, 5))
+
+
+def test_df_full_and_single_voxel():
+    full = oracle.Volume("D(2,2,2,6)", np.arange(64, dtype=np.uint64)).words()
+    assert np.all(full[2::2] == 0)
+    one = oracle.Volume("D(3,3,3,30)", codes_of([(0, 0, 0)])).words()
+    d = one[2::2].reshape(8, 8, 8)
+    z, y, x = np.mgrid[0:8, 0:8, 0:8]
+    assert np.array_equal(d, x + y + z)  # closed form: distance to the corner voxel
+
+
+DF_SPECS = ["D(3,3,3,6)", "D(3,3,3,1)", "D(1,1,1,2) R(2,2,2)", "R(1,1,1) D(2,2,2,3)", "D(2,2,2,6) S(1)",
+            "G(1) D(2,2,2,4)", "D(1,1,1,3) D(1,1,1,3) D(1,1,1,3)", "S(1) D(1,1,1,1) G(1)",
+            "D(2,2,2,6) G(1) --whole-level-dedup"]
+
+
+@pytest.mark.parametrize("spec", DF_SPECS)
+def test_df_decode_is_lossless(spec):
+    codes = W.scene_bernoulli(7, 3, 3, 3, 0.2)
+    assert np.array_equal(oracle.Volume(spec, codes).decode(), codes)
+
+
+@pytest.mark.parametrize("seed,p", [(1, 0.01), (2, 0.03), (3, 0.12)])
+def test_df_formats_match_flat_dda(seed, p):
+    """Skipping by the stored distance never skips an occupied cell: hits equal the flat DDA."""
+    codes = W.scene_bernoulli(seed + 40, 3, 3, 3, p)
+    occ = dense_of([tuple(v) for v in W.morton_decode(codes)], (3, 3, 3))
+    rays = np.concatenate([W.random_rays(seed, (8, 8, 8), 600), W.camera_rays(seed, 0, (8, 8, 8), 24, 16)])
+    flat = oracle.flat_dda(occ, (3, 3, 3), rays)
+    for spec in DF_SPECS:
+        assert np.array_equal(oracle.Volume(spec, codes).trace(rays), flat), spec
+
+
+@pytest.mark.parametrize("spec", ["D(3,3,3,6)", "D(1,1,1,3) R(2,2,2)", "S(1) D(2,2,2,6)"])
+def test_df_edge_suite(spec):
+    codes = codes_of(EDGE_VOX)
+    got = oracle.Volume(spec, codes).trace(np.concatenate([r for r, _ in EDGE_CASES]))
+    for i, ((r, e), g) in enumerate(zip(EDGE_CASES, got)):
+        if e is None:
+            assert g[0] == -1, (i, g)
+        else:
+            assert as_tuple(g) == e, (i, as_tuple(g), e)
+
+
+def test_df_shell_scene():
+    codes = W.scene_shell(4, 6, 8, 4, 1.4)
+    occ = dense_of([tuple(v) for v in W.morton_decode(codes)], (6, 6, 6))
+    rays = np.concatenate([W.camera_rays(4, 0, (64, 64, 64), 48, 32), W.random_rays(4, (64, 64, 64), 1500)])
+    flat = oracle.flat_dda(occ, (6, 6, 6), rays)
+    for spec in ["D(6,6,6,6)", "D(4,4,4,6) R(2,2,2)", "D(3,3,3,6) D(3,3,3,6)", "D(2,2,2,6) G(4) --wld"]:
+        assert np.array_equal(oracle.Volume(spec, codes).trace(rays), flat), spec
