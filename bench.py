@@ -40,7 +40,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("hvf_trace.hip", "hvf_build.cpp"):
+    for f in ("hvf_trace.hip", "hvf_build.cpp", "hvf_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2410_14128_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -72,7 +72,9 @@ def byte_model(vol, rays_sample, cap=4096):
 
 
 def traffic_from_profile(name: str):
-    """HBM bytes per ray from a committed rocprofv3 PMC summary, if it matches this kernel."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
+    reading for a plain 1 GiB copy) from the committed rocprofv3 PMC summary, or None when
+    absent or taken with a different kernel source."""
     p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(p):
         return None
@@ -82,7 +84,8 @@ def traffic_from_profile(name: str):
         return None
     if d.get("kernel_hash") != kernel_source_hash():
         return None
-    return d.get("workloads", {}).get(name)
+    w = d.get("workloads", {}).get(name)
+    return None if w is None else round(float(w["bytes_per_launch"]))
 
 
 def time_launches(fn_list, steps, warmup):
@@ -432,6 +435,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2048", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (PMC calibration of FETCH/WRITE_SIZE)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -447,6 +452,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        x = torch.ones(256 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3}))
+        return
     import paper_2410_14128_amd as H
     import workloads as W
     from workloads import configs as C

@@ -82,9 +82,10 @@ typedef struct hvf_info {
 
 /* How a trace is scheduled on the device. Results never depend on it.
  * persistent = 0: one lane per ray, one launch-sized grid.
- * persistent = 1: a grid sized to the device; each wave refills its idle lanes from a
- *   global ray counter whenever at least `refill` of its 64 lanes are idle, checking after
- *   every `inner` traversal steps.
+ * persistent = 1: a grid sized to the device (at most blocks_per_cu 256-thread blocks per
+ *   CU when blocks_per_cu > 0); each wave refills its idle lanes from a global ray counter
+ *   whenever at least `refill` of its 64 lanes are idle, checking after every `inner`
+ *   traversal steps.
  * sort = 1: trace rays in the order of a coherence key (origin cell of side 2^sort_bits
  *   voxels in Morton order, then direction octant) computed and sorted on the device;
  *   results are still written at each ray's own index. */
@@ -94,11 +95,18 @@ typedef struct hvf_schedule {
   int32_t inner;
   int32_t sort;
   int32_t sort_bits;
-  int32_t reserved[3];
+  int32_t blocks_per_cu;
+  int32_t stack_depth; /* > 0: keep node-stack slots only for depths < stack_depth and
+                          re-descend from the deepest kept ancestor on a deeper pop */
+  int32_t reserved;
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).
  * format_spec: e.g. "G(7) R(4,4,4) --whole-level-dedup"; R(k^3) means R(k,k,k).
+ *   --whole-level-dedup: one de-duplication map per SVDAG level (Sec. 4.3).
+ *   --restart-sv: restarting sparse-voxel intersection (Sec. 4.3): inside SVO/SVDAG levels
+ *   no per-lane node stack is kept; after leaving a node the walk descends again from the
+ *   level's root along the current position. Results are unchanged.
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
  *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
  * out: receives a new handle owned by the caller (release with hvf_free).
@@ -125,9 +133,9 @@ hvf_status hvf_trace_sched(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf
 hvf_status hvf_get_schedule(const hvf_volume* vol, hvf_schedule* out);
 hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
 
-/* Autotune: time candidate schedules (one lane per ray; persistent with refill
- * thresholds 8/16/32 and 4 or 16 steps between checks; sorted with cell sides 2^2, 2^4,
- * 2^6) on the caller's device ray sample, pick the fastest, store it as the volume's
+/* Autotune: time candidate schedules (one lane per ray; persistent at full, 2 or 4
+ * blocks per CU with refill thresholds 8/32 and 4 or 16 steps between checks; sorted
+ * with cell sides 2^2, 2^4, 2^6) on the caller's device ray sample, pick the fastest, store it as the volume's
  * schedule and copy it to *out (may be NULL). d_hits_scratch: n device hits, overwritten.
  * Synchronises hip_stream. Results never depend on the schedule chosen. */
 hvf_status hvf_autotune(hvf_volume* vol, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits_scratch,

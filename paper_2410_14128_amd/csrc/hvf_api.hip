@@ -10,12 +10,13 @@
 #include "hvf_internal.h"
 
 namespace hvf {
-hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s);
+hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                        hipStream_t s);
 hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
                               uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s);
-hvf_status launch_trace_persistent(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
-hvf_status persistent_grid(const DevFormat& F, unsigned* grid);
+hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule& sc,
                         uint32_t* d_counter, hipStream_t s);
@@ -106,7 +107,8 @@ hvf_status hvf_upload(hvf_volume* v, void* stream) {
 namespace {
 hvf_status check_sched(const hvf_schedule& sc) {
   if (sc.persistent < 0 || sc.persistent > 1 || sc.refill < 1 || sc.refill > 64 || sc.inner < 1 || sc.inner > 4096 ||
-      sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16)
+      sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16 || sc.blocks_per_cu < 0 ||
+      sc.blocks_per_cu > 64 || sc.stack_depth < 0 || sc.stack_depth > HVF_MAX_DEPTH)
     return fail(HVF_E_INPUT, "schedule field out of range");
   return HVF_OK;
 }
@@ -122,7 +124,8 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (!d_rays || !d_hits) return fail(HVF_E_INPUT, "null ray or hit buffer");
   st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
-  const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
   hipStream_t s = (hipStream_t)stream;
   uint32_t* counter = nullptr;
   if (sc.persistent || sc.sort) {
@@ -136,13 +139,15 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
     counter = v->dcounters + 2 * (v->counter_next++ % HVF_NUM_COUNTERS);
   }
   if (sc.sort) return hvf::trace_sorted(F, d_rays, n, d_hits, sc, counter, s);
-  if (!sc.persistent) return hvf::launch_trace(F, d_rays, n, d_hits, s);
+  const int family = hvf::family_of(v->layout);
+  if (!sc.persistent) return hvf::launch_trace(F, family, d_rays, n, d_hits, s);
   unsigned grid = 0;
-  st = hvf::persistent_grid(F, &grid);
+  st = hvf::persistent_grid(F, sc.blocks_per_cu, &grid);
   if (st != HVF_OK) return st;
   st = hvf::launch_fill_u32(counter, 0u, 1, s);
   if (st != HVF_OK) return st;
-  return hvf::launch_trace_persistent(F, d_rays, n, d_hits, counter, (uint32_t)sc.refill, (uint32_t)sc.inner, grid, s);
+  return hvf::launch_trace_persistent(F, family, d_rays, n, d_hits, counter, (uint32_t)sc.refill, (uint32_t)sc.inner,
+                                      grid, s);
 }
 
 hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits, hvf_schedule* out,
@@ -150,10 +155,14 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
   if (!v || !d_sample || !d_hits || n == 0) return fail(HVF_E_INPUT, "autotune needs a volume and a non-empty sample");
   hipStream_t s = (hipStream_t)stream;
   std::vector<hvf_schedule> cand;
-  cand.push_back(hvf_schedule{0, 16, 8, 0, 4, {0, 0, 0}});
-  for (int refill : {8, 16, 32})
-    for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, {0, 0, 0}});
-  for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, {0, 0, 0}});
+  cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0});
+  const int nd = (int)v->layout.d.size();
+  for (int sd : {2, 4})
+    if (sd < nd) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, sd, 0});
+  for (int bpc : {0, 2, 4})
+    for (int refill : {8, 32})
+      for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, bpc, 0, 0});
+  for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, 0, 0, 0});
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");
   if (hipEventCreate(&e1) != hipSuccess) {

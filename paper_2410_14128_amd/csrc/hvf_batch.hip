@@ -125,6 +125,7 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     it.n = (uint32_t)n[i];
     for (int a = 0; a < 3; ++a) it.ext[a] = F.ext[a];
     it.ndepth = F.ndepth;
+    it.stacked = F.stacked;
     b->max_depth = std::max(b->max_depth, F.ndepth);
     b->items.push_back(it);
     b->dinfo.insert(b->dinfo.end(), F.dinfo, F.dinfo + HVF_MAX_DEPTH);

@@ -14,6 +14,8 @@
 //  * a terminating integer below an SVDAG node is stored in the parent's pointer slot
 //    instead of a separate one-word leaf node; an SVO node just above the next level
 //    points to a packed array of those pointers instead of two-word leaf nodes;
+//  * an SVDAG node whose children are SVDAG nodes stores, per valid child, the child's
+//    pointer and a copy of the child's mask word, so a descent reads one 8-byte slot;
 //  * nodes are grouped by traversal depth (all depth-0 nodes, then depth 1, ...), so the
 //    upper levels form one contiguous prefix of the buffer.
 #include <algorithm>
@@ -63,8 +65,7 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
       if (flag == "--whole-level-dedup" || flag == "-whole-level-dedup" || flag == "--wld") {
         s.wld = true;
       } else if (flag == "--restart-sv" || flag == "-restart-sv") {
-        unsupported = true;
-        err = "restarting sparse-voxel intersection is not implemented";
+        s.restart_sv = true;
       } else {
         err = "unknown flag '" + flag + "'";
         return HVF_E_SPEC;
@@ -231,9 +232,10 @@ Layout make_layout(const Spec& s) {
         d.j = j;
         d.cs = cs_level + (D - 1 - j);
         d.w[0] = d.w[1] = d.w[2] = 1;
-        d.hk = (lv.kind == LK_SVO) ? HK_SVO : HK_DAG;
+        // An SVDAG node below the level's root is entered through its parent's descriptor.
+        d.hk = (lv.kind == LK_SVO) ? HK_SVO : (j == 0 ? HK_DAG : HK_MASK);
         if (j < D - 1)
-          d.nk = (lv.kind == LK_SVO) ? NK_SVO_INNER : NK_OCT_PTR;
+          d.nk = (lv.kind == LK_SVO) ? NK_SVO_INNER : NK_DAG_INNER;
         else
           d.nk = last ? NK_OCT_FINAL : NK_OCT_PTR;
         d.arena = true;
@@ -242,6 +244,33 @@ Layout make_layout(const Spec& s) {
     }
   }
   return L;
+}
+
+uint32_t stacked_mask(const Layout& L, bool restart_sv, int stack_depth) {
+  uint32_t m = 0;
+  for (size_t d = 0; d < L.d.size(); ++d) {
+    bool keep = true;
+    if (restart_sv && (L.d[d].nk == NK_SVO_INNER || L.d[d].nk == NK_DAG_INNER || L.d[d].nk == NK_OCT_PTR ||
+                       L.d[d].nk == NK_OCT_FINAL))
+      keep = (L.d[d].j == 0);  // only the root node of an SVO/SVDAG level keeps a slot
+    if (stack_depth > 0 && (int)d >= stack_depth) keep = false;
+    if (d == 0) keep = true;
+    if (keep) m |= 1u << d;
+  }
+  return m;
+}
+
+void set_stacked(DevFormat& F, uint32_t mask) {
+  F.stacked = mask;
+  F.nslots = (uint32_t)__builtin_popcount(mask);
+}
+
+int family_of(const Layout& L) {
+  uint32_t need = 0;
+  for (const DepthInfo& d : L.d) need |= fam_nk(d.nk) | fam_hk(d.hk);
+  for (int i = 0; i < NUM_FAMILIES; ++i)
+    if ((FAMILIES[i] & need) == need) return i;
+  return NUM_FAMILIES - 1;
 }
 
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf) {
@@ -254,6 +283,7 @@ DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf) {
     f.dinfo[i] = (uint32_t)(d.nk & 15) | ((uint32_t)(d.hk & 15) << 4) | ((uint32_t)(d.cs & 15) << 8) |
                  ((uint32_t)(d.w[0] & 15) << 12) | ((uint32_t)(d.w[1] & 15) << 16) | ((uint32_t)(d.w[2] & 15) << 20);
   }
+  set_stacked(f, stacked_mask(L, s.restart_sv, 0));
   // Depth to return to when the cell position changes in bit h: the deepest depth >= 1
   // whose node side 2^(cs + w) exceeds 2^h, else the root (depth 0).
   for (int h = 0; h < 16; ++h) {
@@ -389,7 +419,7 @@ struct Builder {
                      Z = z + ((uint64_t)((o >> 2) & 1) << cs);
       valid |= 1u << o;
       if (di.nk != NK_OCT_FINAL) {
-        if (di.nk == NK_SVO_INNER || (d + 1 < (int)L.d.size() && L.d[d + 1].level == di.level))
+        if (di.nk == NK_SVO_INNER || di.nk == NK_DAG_INNER)
           kids[nk++] = build(d + 1, X, Y, Z, a, b, map);
         else
           kids[nk++] = build_root_of_next(d + 1, X, Y, Z, a, b);
@@ -413,12 +443,16 @@ struct Builder {
       ++nodes[d];
       return id;
     }
-    // SVDAG: mask word then one pointer per valid child; de-duplicate (not the root of
-    // a sub-volume, which its parent level writes as is).
-    uint32_t w[9];
+    // SVDAG: mask word, then per valid child either a (pointer, child masks) descriptor
+    // (children in this level) or a pointer (children are next-level roots).
+    // De-duplicate, except the root of a sub-volume, which its parent level writes as is.
+    uint32_t w[17];
     w[0] = masks;
     size_t len = 1;
-    for (int i = 0; i < nk; ++i) w[len++] = kids[i];
+    for (int i = 0; i < nk; ++i) {
+      w[len++] = kids[i];
+      if (di.nk == NK_DAG_INNER) w[len++] = arena[d + 1][kids[i]];  // the child's mask word
+    }
     const bool root = (di.j == 0);
     uint64_t h = 0;
     if (!root && map) {
@@ -523,6 +557,13 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
         break;
       case NK_SVO_INNER:
         for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(nb + A[i]);
+        break;
+      case NK_DAG_INNER:
+        for (size_t i = 0; i < A.size();) {
+          const uint32_t cnt = (uint32_t)__builtin_popcount(A[i] & 0xFFu);
+          for (uint32_t k = 0; k < cnt; ++k) dst[i + 1 + 2 * k] = (uint32_t)(nb + A[i + 1 + 2 * k]);
+          i += 1 + 2 * cnt;
+        }
         break;
       case NK_OCT_PTR:
         if (di.hk == HK_SVO) {

@@ -19,7 +19,8 @@ struct LevelSpec {
 
 struct Spec {
   std::vector<LevelSpec> lv;
-  bool wld = false;  // whole-level de-duplication of SVDAG nodes (Sec. 4.3)
+  bool wld = false;         // whole-level de-duplication of SVDAG nodes (Sec. 4.3)
+  bool restart_sv = false;  // restarting sparse-voxel intersection (Sec. 4.3)
   int ext[3] = {0, 0, 0};
   std::vector<int> sub;  // sub[k]: log2 side (voxels) of a level-k sub-volume, k >= 1; sub[n] = 0
   std::string text;
@@ -42,13 +43,16 @@ enum NodeKind : int {
   NK_SVO_INNER = 3,  // SVO node whose children are SVO nodes: child = first + 2 * rank
   NK_OCT_PTR = 4,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
                      // deepest octree depth above the last level)
-  NK_OCT_FINAL = 5   // deepest octree depth of the last level: valid mask = occupancy
+  NK_OCT_FINAL = 5,  // deepest octree depth of the last level: valid mask = occupancy
+  NK_DAG_INNER = 6   // SVDAG node whose children are SVDAG nodes: a 2-word descriptor
+                     // (child pointer, child masks) per valid child at base + 2 * rank
 };
 enum HeaderKind : int {
   HK_RAW = 0,       // base = pointer
   HK_SVO = 1,       // {first child / pointer array, masks}
   HK_DAG = 2,       // {masks, child pointers...}: base = pointer + 1
-  HK_MASK = 3,      // a block entered from its brick: the mask was read by the test
+  HK_MASK = 3,      // header read by the parent: a brick block's mask, or the (pointer + 1,
+                    // valid) pair of an SVDAG child descriptor
   HK_MASKLOAD = 4   // a one-block brick: load its 64-bit mask at the pointer
 };
 
@@ -83,15 +87,46 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
 // pop_lut: 4 bits per h in [0, 16): the deepest depth whose node side exceeds 2^h, i.e.
 // the depth a walk returns to when its position changes in bit h (node sides shrink
 // strictly with depth, and every depth below the root is cubic).
+// stacked: bit d set = depth d keeps a node-stack slot (slot index = number of stacked
+// depths above d). A pop to a depth without a slot restores the deepest stacked ancestor
+// and descends again along the current cell position.
 struct DevFormat {
   const uint32_t* buf;
   int32_t ext[3];
   int32_t ndepth;
   uint64_t pop_lut;
+  uint32_t stacked;
+  uint32_t nslots;
   uint32_t dinfo[HVF_MAX_DEPTH];
 };
 
+// Stack-slot mask of a layout: every depth, or with restart-sv only the root depth of each
+// level; stack_depth > 0 further keeps only depths < stack_depth (depth 0 always).
+uint32_t stacked_mask(const Layout& L, bool restart_sv, int stack_depth);
+void set_stacked(DevFormat& F, uint32_t mask);
+
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf);
+
+// Compile-time format families: bit k (k < 8) = node kind k may occur, bit 8 + h = header
+// kind h may occur. Trace kernels are instantiated per family so code for absent kinds
+// is not compiled in; a volume uses the first family that covers its layout.
+constexpr uint32_t fam_nk(int k) { return 1u << k; }
+constexpr uint32_t fam_hk(int h) { return 1u << (8 + h); }
+constexpr uint32_t FAM_DAG_BRICK = fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) |
+                                   fam_hk(HK_DAG) | fam_hk(HK_MASK) | fam_hk(HK_RAW) | fam_hk(HK_MASKLOAD);
+constexpr uint32_t FAM_SVO_BRICK = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) |
+                                   fam_hk(HK_SVO) | fam_hk(HK_MASK) | fam_hk(HK_RAW) | fam_hk(HK_MASKLOAD);
+constexpr uint32_t FAM_RAW_BRICK = fam_nk(NK_RAW_PTR) | fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) | fam_hk(HK_RAW) |
+                                   fam_hk(HK_MASK) | fam_hk(HK_MASKLOAD);
+constexpr uint32_t FAM_OCTREE = fam_nk(NK_SVO_INNER) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_PTR) |
+                                fam_nk(NK_OCT_FINAL) | fam_hk(HK_SVO) | fam_hk(HK_DAG) | fam_hk(HK_MASK);
+constexpr uint32_t FAM_RAW_OCTREE = FAM_OCTREE | fam_nk(NK_RAW_PTR) | fam_hk(HK_RAW);
+constexpr uint32_t FAM_ALL = 0x7Fu | (0x1Fu << 8);
+constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE, FAM_ALL};
+constexpr int NUM_FAMILIES = 6;
+
+// Index into FAMILIES of the first family covering the layout.
+int family_of(const Layout& L);
 
 // One batch of the batched launch: a volume and its ray / hit arrays. Rays of all
 // batches form one index space; batch b owns indices [first, first + n).
@@ -104,6 +139,8 @@ struct BatchItem {
   uint32_t n;
   int32_t ext[3];
   int32_t ndepth;
+  uint32_t stacked;
+  uint32_t pad;
 };
 constexpr int HVF_BATCH_MAX_ITEMS = 256;
 
@@ -116,7 +153,7 @@ struct hvf_volume {
   hvf::Built built;
   uint32_t* dbuf = nullptr;  // device copy of built.words
   int device = -1;
-  hvf_schedule sched{0, 16, 8, 0, 4, {0, 0, 0}};
+  hvf_schedule sched{0, 16, 8, 0, 4, 0, 0, 0};
   uint32_t* dcounters = nullptr;  // device ray counters for persistent launches
   unsigned counter_next = 0;
 };

@@ -176,6 +176,7 @@ hvf_status launch_step(hvf_server* S, Step& st) {
     it.n = (uint32_t)r.n;
     for (int a = 0; a < 3; ++a) it.ext[a] = F.ext[a];
     it.ndepth = F.ndepth;
+    it.stacked = F.stacked;
     st.h_items[i] = it;
     std::memcpy(st.h_dinfo + i * HVF_MAX_DEPTH, F.dinfo, sizeof(F.dinfo));
     max_depth = std::max(max_depth, F.ndepth);

@@ -143,7 +143,11 @@ struct Fmt {
   uint64_t pop_lut;
   const uint32_t* dtab;
   int ext[3];
+  uint32_t stacked;  // depths with a node-stack slot
 };
+
+// Stack slot of depth d: the number of stacked depths above it.
+__device__ __forceinline__ uint32_t slot_of(uint32_t stacked, int d) { return __popc(stacked & ((1u << d) - 1u)); }
 
 __device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab) {
   Fmt f;
@@ -153,6 +157,7 @@ __device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab) 
   f.ext[0] = F.ext[0];
   f.ext[1] = F.ext[1];
   f.ext[2] = F.ext[2];
+  f.stacked = F.stacked;
   return f;
 }
 
@@ -168,24 +173,52 @@ struct Walk {
 
   // Enter the node at pointer ptr whose depth descriptor is nd: returns its header
   // (base, valid). m: the 64-bit block mask the parent's test read (used by HK_MASK).
-  template <class Mem>
+  template <uint32_t FAM, class Mem>
   __device__ __forceinline__ static uint2 enter(const uint32_t* __restrict__ buf, uint32_t nd, uint32_t ptr, uint2 m,
                                                 Mem& mem) {
     const uint32_t hk = di_hk(nd);
-    if (hk == HK_RAW) return make_uint2(ptr, 0u);
-    if (hk == HK_MASK) return m;
-    if (hk == HK_DAG) {
+    if ((FAM & fam_hk(HK_RAW)) && hk == HK_RAW) return make_uint2(ptr, 0u);
+    if ((FAM & fam_hk(HK_MASK)) && hk == HK_MASK) return m;
+    if ((FAM & fam_hk(HK_DAG)) && hk == HK_DAG) {
       mem.note(ptr, 1);
       return make_uint2(ptr + 1u, buf[ptr] & 0xFFu);
     }
     // HK_SVO (first, masks) or HK_MASKLOAD (lo, hi)
     const uint2 h = ld2(buf, ptr);
     mem.note(ptr, 2);
+    if (!(FAM & fam_hk(HK_SVO))) return h;
+    if (!(FAM & fam_hk(HK_MASKLOAD))) return make_uint2(h.x, h.y & 0xFFu);
     return make_uint2(h.x, (hk == HK_SVO) ? (h.y & 0xFFu) : h.y);
   }
 
+  // Pointer (and, for SVDAG descriptors, the child's header) of the occupied child `lin`
+  // of an octree node with header (base, valid).
+  template <uint32_t FAM, class Mem>
+  __device__ __forceinline__ static void octree_child(const uint32_t* __restrict__ buf, uint32_t nk, uint32_t lin,
+                                                      uint32_t base, uint32_t valid, uint32_t& child, uint2& cm,
+                                                      Mem& mem) {
+    const uint32_t rank = __popc(valid & ((1u << lin) - 1u));
+    if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) {
+      child = base + 2u * rank;
+    } else if ((FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER) {
+      const uint2 dsc = ld2(buf, base + 2u * rank);  // (child pointer, child masks)
+      mem.note(base + 2u * rank, 2);
+      child = dsc.x;
+      cm = make_uint2(dsc.x + 1u, dsc.y & 0xFFu);
+    } else {
+      child = buf[base + rank];
+      mem.note(base + rank, 1);
+    }
+  }
+
+  __device__ __forceinline__ uint32_t cell_lin(uint32_t in) const {
+    const int c = di_cs(in);
+    const uint32_t wx = bf(in, 12, 4), wy = bf(in, 16, 4), wz = bf(in, 20, 4);
+    return bf((uint32_t)p[0], c, wx) | (bf((uint32_t)p[1], c, wy) << wx) | (bf((uint32_t)p[2], c, wz) << (wx + wy));
+  }
+
   // Start the walk of a ray that passed setup. Returns DONE if the volume is empty.
-  template <class Mem>
+  template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int start(const Fmt& F, Mem& mem) {
     const uint32_t* __restrict__ buf = F.buf;
     const uint32_t* dtab = F.dtab;
@@ -208,7 +241,7 @@ struct Walk {
         p[a] = up ? mid : p[a];
       }
     }
-    const uint2 h = enter(buf, info, root, make_uint2(0u, 0u), mem);
+    const uint2 h = enter<FAM>(buf, info, root, make_uint2(0u, 0u), mem);
     base = h.x;
     valid = h.y;
     t = R.t0;
@@ -217,7 +250,7 @@ struct Walk {
   }
 
   // One step. On DONE, out holds the result (a miss leaves it untouched).
-  template <class Mem>
+  template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int step(const Fmt& F, uint2* stk, int4& out, Mem& mem) {
     const uint32_t* __restrict__ buf = F.buf;
     const uint32_t* dtab = F.dtab;
@@ -227,41 +260,31 @@ struct Walk {
     }
     const uint32_t nk = di_nk(info);
     const int cs = di_cs(info);
-    const uint32_t wx = bf(info, 12, 4), wy = bf(info, 16, 4), wz = bf(info, 20, 4);
     // Child cell of the current node holding the ray (octree nodes: w = 1, the octant).
-    const uint32_t lin = bf((uint32_t)p[0], cs, wx) | (bf((uint32_t)p[1], cs, wy) << wx) |
-                         (bf((uint32_t)p[2], cs, wz) << (wx + wy));
+    const uint32_t lin = cell_lin(info);
     bool occ;
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
-    if (nk == NK_RAW_PTR) {
+    if ((FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR) {
       child = buf[base + lin];
       mem.note(base + lin, 1);
       occ = child != 0u;
-    } else if (nk == NK_BLOCKS) {
+    } else if ((FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS) {
       cm = ld2(buf, base + 2u * lin);
       mem.note(base + 2u * lin, 2);
       occ = (cm.x | cm.y) != 0u;
     } else {
       // A voxel's bit in the block mask (base:valid), or an octree child's valid bit.
-      const uint32_t word = (nk == NK_CELLS && lin < 32u) ? base : valid;
+      const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && lin < 32u) ? base : valid;
       occ = ((word >> (lin & 31u)) & 1u) != 0u;
     }
-    const bool fin = (nk == NK_CELLS) || (nk == NK_OCT_FINAL);
+    const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL);
     if (occ && !fin) {
-      if (nk >= NK_SVO_INNER) {
-        const uint32_t rank = __popc(valid & ((1u << lin) - 1u));
-        if (nk == NK_SVO_INNER) {
-          child = base + 2u * rank;
-        } else {
-          child = buf[base + rank];
-          mem.note(base + rank, 1);
-        }
-      }
-      stk[d * BLOCK] = make_uint2(base, valid);
+      if (nk >= NK_SVO_INNER) octree_child<FAM>(buf, nk, lin, base, valid, child, cm, mem);
+      if ((F.stacked >> d) & 1u) stk[slot_of(F.stacked, d) * BLOCK] = make_uint2(base, valid);
       ++d;
       info = dtab[d];
-      const uint2 h = enter(buf, info, child, cm, mem);
+      const uint2 h = enter<FAM>(buf, info, child, cm, mem);
       base = h.x;
       valid = h.y;
       refine3(R, p, cs, di_cs(info), t);
@@ -307,11 +330,32 @@ struct Walk {
       const int hb = 31 - __clz(dd);
       const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
       if (nd != d) {
-        d = nd;
-        info = dtab[d];
-        const uint2 sv = stk[d * BLOCK];
+        // Restore the deepest stacked ancestor r <= nd, then descend again along p (every
+        // ancestor of the current cell exists, so each child on the way is occupied).
+        const int r = 31 - __clz(F.stacked & ((2u << nd) - 1u));
+        const uint2 sv = stk[slot_of(F.stacked, r) * BLOCK];
         base = sv.x;
         valid = sv.y;
+        info = dtab[r];
+        for (int k = r; k < nd; ++k) {
+          const uint32_t knk = di_nk(info), kl = cell_lin(info);
+          uint32_t child = 0u;
+          uint2 cm = make_uint2(0u, 0u);
+          if ((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) {
+            child = buf[base + kl];
+            mem.note(base + kl, 1);
+          } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
+            cm = ld2(buf, base + 2u * kl);
+            mem.note(base + 2u * kl, 2);
+          } else {
+            octree_child<FAM>(buf, knk, kl, base, valid, child, cm, mem);
+          }
+          info = dtab[k + 1];
+          const uint2 h = enter<FAM>(buf, info, child, cm, mem);
+          base = h.x;
+          valid = h.y;
+        }
+        d = nd;
         const int mask = ~((1 << di_cs(info)) - 1);
         p[0] &= mask;
         p[1] &= mask;
@@ -329,6 +373,7 @@ __device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
 
 __device__ __forceinline__ int4 miss_hit() { return make_int4(-1, -1, -1, __float_as_int(INFINITY)); }
 
+template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                       int4* __restrict__ hits, uint32_t n) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
@@ -341,8 +386,8 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   int4 out = miss_hit();
   Walk w;
   Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
-    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
+    while (w.template step<FAM>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
 }
@@ -350,6 +395,7 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
 // Persistent variant: a grid sized to the device; each wave keeps its lanes busy by
 // fetching a new ray for every idle lane from a global counter whenever at least
 // `refill` lanes are idle (or the whole wave is). *counter must be 0 at launch.
+template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                                  int4* __restrict__ hits, uint32_t n,
                                                                  uint32_t* __restrict__ counter, uint32_t refill,
@@ -381,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
           ray = id;
           out = miss_hit();
           const float4 r0 = rays[2 * (size_t)id], r1 = rays[2 * (size_t)id + 1];
-          active = setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN;
+          active = setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
           if (!active) hits[id] = out;
         }
       }
@@ -389,7 +435,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
     if (drained && __ballot(active) == 0ull) break;
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
-        if (w.step(fm, stk, out, mem) == DONE) {
+        if (w.template step<FAM>(fm, stk, out, mem) == DONE) {
           hits[ray] = out;
           active = false;
           break;
@@ -415,8 +461,8 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   int4 out = miss_hit();
   Walk w;
   Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
-    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN)
+    while (w.template step<FAM_ALL>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
 }
@@ -493,6 +539,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
   fm.pop_lut = 0;
   fm.dtab = dt;
   fm.ext[0] = fm.ext[1] = fm.ext[2] = 0;
+  fm.stacked = 1u;
   int4* hits = nullptr;
   bool active = false;
   uint32_t ray = 0;
@@ -524,12 +571,13 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
           fm.ext[0] = it.ext[0];
           fm.ext[1] = it.ext[1];
           fm.ext[2] = it.ext[2];
+          fm.stacked = it.stacked;
           hits = reinterpret_cast<int4*>(it.hits);
           ray = id - it.first;
           const float4* rays = reinterpret_cast<const float4*>(it.rays);
           const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
           out = miss_hit();
-          active = setup(r0, r1, fm.ext, w.R) && w.start(fm, mem) == RUN;
+          active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN;
           if (!active) hits[ray] = out;
         }
       }
@@ -537,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
     if (drained && __ballot(active) == 0ull) break;
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
-        if (w.step(fm, stk, out, mem) == DONE) {
+        if (w.template step<FAM_ALL>(fm, stk, out, mem) == DONE) {
           hits[ray] = out;
           active = false;
           break;
@@ -565,8 +613,8 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   Walk w;
   Counting mem{log + (size_t)i * cap, cap, 0u};
   w.steps = 0;
-  if (setup(r0, r1, F.ext, w.R) && w.start(fm, mem) == RUN)
-    while (w.step(fm, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN)
+    while (w.template step<FAM_ALL>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
   count[i] = mem.k;
@@ -586,22 +634,37 @@ int g_cu_count = -1;
 
 }  // namespace
 
-size_t stack_lds_bytes(const DevFormat& F) { return (size_t)F.ndepth * BLOCK * sizeof(uint2); }
+size_t stack_lds_bytes(const DevFormat& F) { return (size_t)(F.nslots ? F.nslots : 1) * BLOCK * sizeof(uint2); }
 
-hvf_status launch_trace(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, hipStream_t s) {
+#define HVF_FAMILY_SWITCH(family, LAUNCH) \
+  switch (family) {                          \
+    case 0: LAUNCH(FAM_DAG_BRICK); break;    \
+    case 1: LAUNCH(FAM_SVO_BRICK); break;    \
+    case 2: LAUNCH(FAM_RAW_BRICK); break;    \
+    case 3: LAUNCH(FAM_OCTREE); break;       \
+    case 4: LAUNCH(FAM_RAW_OCTREE); break;   \
+    default: LAUNCH(FAM_ALL); break;         \
+  }
+
+hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                        hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32)) {
     hvf_set_error("at most 2^32 - 1 rays per call");
     return HVF_E_INPUT;
   }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-  hipLaunchKernelGGL(trace_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
-                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n);
+  const float4* r = reinterpret_cast<const float4*>(d_rays);
+  int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_TRACE(FAMV) \
+  hipLaunchKernelGGL(trace_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_TRACE)
+#undef HVF_LAUNCH_TRACE
   return launch_check("trace");
 }
 
-// Blocks of the persistent kernel that fit on the device at once.
-hvf_status persistent_grid(const DevFormat& F, unsigned* grid) {
+// Blocks of the persistent kernel per CU (at most blocks_per_cu if > 0) times CUs.
+hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid) {
   if (g_cu_count < 0) {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -612,24 +675,29 @@ hvf_status persistent_grid(const DevFormat& F, unsigned* grid) {
     g_cu_count = prop.multiProcessorCount;
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent_kernel, BLOCK, stack_lds_bytes(F)) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_persistent_kernel<FAM_ALL>, BLOCK,
+                                                   stack_lds_bytes(F)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
+  if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
   *grid = (unsigned)(g_cu_count * per_cu);
   return HVF_OK;
 }
 
-hvf_status launch_trace_persistent(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 31)) {
     hvf_set_error("at most 2^31 - 1 rays per persistent call");
     return HVF_E_INPUT;
   }
-  hipLaunchKernelGGL(trace_persistent_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
-                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_counter,
-                     refill, inner);
+  const float4* r = reinterpret_cast<const float4*>(d_rays);
+  int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_PERSISTENT(FAMV)                                                                                  \
+  hipLaunchKernelGGL(trace_persistent_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, \
+                     (uint32_t)n, d_counter, refill, inner)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_PERSISTENT)
+#undef HVF_LAUNCH_PERSISTENT
   return launch_check("persistent trace");
 }
 

@@ -82,6 +82,11 @@ def decode(info, words):
                 out.append(c)
             elif kind == "S" and not deepest:
                 walk(d + 1, base + 2 * rank, c)
+            elif kind == "G" and not deepest:
+                # descriptor: (child pointer, copy of the child's mask word)
+                child = int(W[base + 2 * rank])
+                assert int(W[base + 2 * rank + 1]) == int(W[child]), "descriptor mask differs from the child's"
+                walk(d + 1, child, c)
             else:
                 walk(d + 1, int(W[base + rank]), c)
 

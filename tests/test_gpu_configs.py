@@ -92,7 +92,7 @@ def surf2048():
     return cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r
 
 
-@pytest.mark.parametrize("spec", C.SURF2048["specs"])
+@pytest.mark.parametrize("spec", C.SURF2048["specs"] + ["G(7) R(4,4,4) --whole-level-dedup --restart-sv"])
 def test_surface2048(H, surf2048, spec):
     cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
     vol = H.Volume(spec, codes)

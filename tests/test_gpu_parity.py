@@ -88,7 +88,9 @@ def test_deterministic(H):
     assert compare(a, ref, "shell 128") == 0
 
 
-SCHEDULES = [dict(persistent=1, refill=1, inner=1), dict(persistent=1, refill=16, inner=8),
+SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persistent=1, refill=8),
+             dict(persistent=1, refill=1, inner=1), dict(persistent=1, refill=16, inner=8),
+             dict(persistent=1, refill=8, inner=4, blocks_per_cu=1), dict(persistent=1, refill=32, inner=16, blocks_per_cu=2),
              dict(persistent=1, refill=64, inner=64), dict(sort=1, sort_bits=0), dict(sort=1, sort_bits=4),
              dict(sort=1, sort_bits=9)]
 
@@ -126,3 +128,20 @@ def test_autotune_keeps_results(H):
     got = gpu_trace(v, rays)
     ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
     assert compare(got, ref, f"autotuned {H.schedule_dict(sc)}") == 0
+
+
+@pytest.mark.parametrize("spec", [sp + " --restart-sv" for sp in SPECS_8 if "--" not in sp] +
+                         ["G(4) R(3,3,3) --whole-level-dedup --restart-sv", "S(2) G(2) R(2,2,2) --restart-sv"])
+def test_restart_sv(H, spec):
+    """Restarting sparse-voxel intersection (no stack inside SVO/SVDAG levels) gives the
+    same hits as the oracle."""
+    for seed in (1, 2):
+        codes = W.scene_bernoulli(seed, 3, 3, 3, 0.06 * seed) if "R(3,3,3)" not in spec else W.scene_shell(seed, 7, 8, 4, 1.4)
+        ext = (8,) * 3 if "R(3,3,3)" not in spec else (128,) * 3
+        if "S(2) G(2)" in spec:
+            codes, ext = W.scene_solid_noise(seed), (64,) * 3
+        rays = np.concatenate([W.random_rays(seed, ext, 3000), W.camera_rays(seed, 0, ext, 64, 48),
+                               np.concatenate([r for r, _ in EDGE_CASES])])
+        got = gpu_trace(H.Volume(spec, codes), rays)
+        ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
+        assert compare(got, ref, f"{spec} seed {seed}") == 0

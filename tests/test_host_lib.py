@@ -115,7 +115,7 @@ def test_table_of_formats():
 @pytest.mark.parametrize("spec,status", [
     ("R(2,2,2) S(1,1,1)", "HVF_E_SPEC"), ("S(2) R(1,0,2)", "HVF_E_SPEC"), ("Q(3)", "HVF_E_SPEC"),
     ("R(3,3)", "HVF_E_SPEC"), ("S(0)", "HVF_E_SPEC"), ("", "HVF_E_SPEC"), ("R(3,3,3) --bogus", "HVF_E_SPEC"),
-    ("G(9) G(9)", "HVF_E_SPEC"), ("D(4,4,4,6) G(5)", "HVF_E_UNSUPPORTED"), ("R(4,4,4) G(5) --restart-sv", "HVF_E_UNSUPPORTED"),
+    ("G(9) G(9)", "HVF_E_SPEC"), ("D(4,4,4,6) G(5)", "HVF_E_UNSUPPORTED"), ("R(4,4,4) G(5) --bogus-flag", "HVF_E_SPEC"),
 ])
 def test_spec_errors(spec, status):
     with pytest.raises(H.HvfError) as e:
@@ -163,3 +163,10 @@ def test_gpu_calls_without_device_fail_loudly():
     with pytest.raises(H.HvfError) as e:
         v.upload(0)
     assert e.value.name in ("HVF_E_DEVICE", "HVF_E_NOMEM")
+
+
+def test_restart_sv_is_accepted_and_keeps_the_layout():
+    codes = W.scene_bernoulli(4, 4, 4, 4, 0.05)
+    a = H.Volume("R(2,2,2) G(2) --whole-level-dedup", codes)
+    b = H.Volume("R(2,2,2) G(2) --whole-level-dedup --restart-sv", codes)
+    assert np.array_equal(a.words(), b.words())  # an intersection option, not a format change
