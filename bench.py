@@ -197,6 +197,40 @@ def run_surface512(args, torch, H, W, C):
     }
 
 
+def raw_twin(spec):
+    """The same hierarchy with every distance-field level D(W,H,D,M) replaced by Raw R(W,H,D)."""
+    import re
+    return re.sub(r"D\((\d+),(\d+),(\d+),\d+\)", r"R(\1,\2,\3)", spec)
+
+
+def run_df512(args, torch, H, C, res):
+    """Distance-field formats of the table at 512^3, each beside its Raw twin (same levels,
+    no distances), autotuned like the nine headline formats and timed over the 4 views."""
+    cfg = C.SURF512
+    codes, views = res["codes"], res["views"]
+    d_views = [torch.from_numpy(r).cuda() for r in views]
+    hits = [torch.empty((len(r), 4), dtype=torch.int32, device="cuda") for r in views]
+    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"], 960, 540)).cuda()
+    nrays = sum(len(r) for r in views)
+    out = []
+    for spec in C.SURF512_DF:
+        row = {"format": spec, "raw_twin": raw_twin(spec)}
+        for key, sp in (("df", spec), ("raw", row["raw_twin"])):
+            v = H.Volume(sp, codes)
+            v.upload()
+            sched = H.schedule_dict(v.get_schedule() if args.no_tune else v.autotune(tune))
+            ms, _ = time_launches([lambda v=v, j=j: v.trace(d_views[j], hits[j]) for j in range(len(views))],
+                                  args.steps, args.warmup)
+            row[key] = {"mrays_s": round(nrays / (ms * 1e-3) / 1e6, 1), "bytes": v.info()["bytes"], "schedule": sched}
+            del v
+        row["df_over_raw"] = round(row["df"]["mrays_s"] / row["raw"]["mrays_s"], 3)
+        log(f"[bench]   DF {spec:46s} {row['df']['mrays_s']:8.1f} Mrays/s  twin {row['raw_twin']:36s} "
+            f"{row['raw']['mrays_s']:8.1f}  x{row['df_over_raw']:.2f}  size {row['df']['bytes'] / 2 ** 20:.1f} MiB "
+            f"vs {row['raw']['bytes'] / 2 ** 20:.1f}")
+        out.append(row)
+    return out
+
+
 def run_surface2048(args, torch, H, W, C):
     cfg = C.SURF2048
     n = 1 << cfg["log2n"]
@@ -439,11 +473,12 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (PMC calibration of FETCH/WRITE_SIZE)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-df", action="store_true", help="skip the distance-field format leg")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "batched", "served"], default=None,
+    ap.add_argument("--only", choices=["surface512", "surface2048", "batched", "served", "df"], default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -479,6 +514,11 @@ def main():
     res = run_surface512(args, torch, H, W, C)
     if args.only == "surface512":
         return
+    df = None
+    if not args.no_df:
+        df = run_df512(args, torch, H, C, res)
+    if args.only == "df":
+        return
     extra = None
     if not args.no_2048:
         extra = run_surface2048(args, torch, H, W, C)
@@ -503,6 +543,7 @@ def main():
         "cpu_baseline": cpu,
         "per_format": res["per_format"],
         "surface_2048": extra,
+        "distance_field_512": df,
         "batched": batched,
         "served": served,
         "kernel_hash": kernel_source_hash(),

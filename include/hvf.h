@@ -56,7 +56,7 @@ typedef enum hvf_status {
   HVF_E_OVERFLOW = 3,    /* the built format would need 2^32 words or more */
   HVF_E_NOMEM = 4,       /* host or device allocation failed, or a memory budget is exceeded */
   HVF_E_DEVICE = 5,      /* a HIP runtime error; the message names it */
-  HVF_E_UNSUPPORTED = 6, /* a valid spec this build does not implement (distance-field levels) */
+  HVF_E_UNSUPPORTED = 6, /* a valid request this build does not implement */
   HVF_E_STATE = 7        /* call not valid in the object's current state */
 } hvf_status;
 
@@ -65,7 +65,7 @@ typedef struct hvf_volume hvf_volume; /* opaque; immutable once built */
 #define HVF_MAX_LEVELS 8
 #define HVF_MAX_DEPTH 16
 
-/* Summary of a built volume. Level kinds: 'R', 'S', 'G'. */
+/* Summary of a built volume. Level kinds: 'R', 'D', 'S', 'G'. */
 typedef struct hvf_info {
   int32_t num_levels;
   char kinds[HVF_MAX_LEVELS];
@@ -78,6 +78,7 @@ typedef struct hvf_info {
   uint64_t depth_nodes[HVF_MAX_DEPTH];
   uint64_t depth_offset[HVF_MAX_DEPTH]; /* first word of each depth: depths are stored in order */
   uint64_t num_voxels;                  /* occupied voxels */
+  int32_t level_maxdist[HVF_MAX_LEVELS]; /* DF levels: the maximum stored distance M; else 0 */
 } hvf_info;
 
 /* How a trace is scheduled on the device. Results never depend on it.
@@ -103,6 +104,10 @@ typedef struct hvf_schedule {
 
 /* Build a volume on the host (Sec. 4.1).
  * format_spec: e.g. "G(7) R(4,4,4) --whole-level-dedup"; R(k^3) means R(k,k,k).
+ *   Levels (table of implemented formats, Sec. 3.2): R(W,H,D) Raw grid, D(W,H,D,M) distance
+ *   field (a Raw grid whose empty cells also store their L1 distance to the nearest
+ *   non-empty cell, capped at M, 1 <= M <= 99; Sec. 3.3, 4.1, 4.2), S(L) SVO, G(L) SVDAG.
+ *   With a DF level above the last the buffer is limited to 2^31 words.
  *   --whole-level-dedup: one de-duplication map per SVDAG level (Sec. 4.3).
  *   --restart-sv: restarting sparse-voxel intersection (Sec. 4.3): inside SVO/SVDAG levels
  *   no per-lane node stack is kept; after leaving a node the walk descends again from the
@@ -110,7 +115,7 @@ typedef struct hvf_schedule {
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
  *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
  * out: receives a new handle owned by the caller (release with hvf_free).
- * Errors: HVF_E_SPEC, HVF_E_UNSUPPORTED, HVF_E_INPUT, HVF_E_OVERFLOW, HVF_E_NOMEM.
+ * Errors: HVF_E_SPEC, HVF_E_INPUT, HVF_E_OVERFLOW, HVF_E_NOMEM.
  * Makes no HIP call. */
 hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, hvf_volume** out);
 

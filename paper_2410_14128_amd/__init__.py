@@ -45,6 +45,7 @@ class hvf_info(ctypes.Structure):
         ("depth_nodes", ctypes.c_uint64 * HVF_MAX_DEPTH),
         ("depth_offset", ctypes.c_uint64 * HVF_MAX_DEPTH),
         ("num_voxels", ctypes.c_uint64),
+        ("level_maxdist", ctypes.c_int32 * HVF_MAX_LEVELS),
     ]
 
 
@@ -228,6 +229,7 @@ class Volume:
             "depth_nodes": [int(I.depth_nodes[d]) for d in range(nd)],
             "depth_offset": [int(I.depth_offset[d]) for d in range(nd)],
             "num_voxels": int(I.num_voxels),
+            "level_maxdist": [int(I.level_maxdist[k]) for k in range(n)],
         }
 
     def words(self) -> np.ndarray:

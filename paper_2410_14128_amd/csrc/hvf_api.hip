@@ -261,7 +261,8 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
   I.num_levels = (int32_t)v->spec.lv.size();
   for (int k = 0; k < I.num_levels; ++k) {
     const int kind = v->spec.lv[k].kind;
-    I.kinds[k] = kind == hvf::LK_RAW ? 'R' : kind == hvf::LK_SVO ? 'S' : 'G';
+    I.kinds[k] = kind == hvf::LK_RAW ? (v->spec.lv[k].maxd ? 'D' : 'R') : kind == hvf::LK_SVO ? 'S' : 'G';
+    I.level_maxdist[k] = v->spec.lv[k].maxd;
     for (int a = 0; a < 3; ++a) I.level_exp[k][a] = v->spec.lv[k].e[a];
     I.level_nodes[k] = v->built.level_nodes.empty() ? 0 : v->built.level_nodes[k];
   }

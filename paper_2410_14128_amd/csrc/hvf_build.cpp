@@ -17,7 +17,13 @@
 //  * an SVDAG node whose children are SVDAG nodes stores, per valid child, the child's
 //    pointer and a copy of the child's mask word, so a descent reads one 8-byte slot;
 //  * nodes are grouped by traversal depth (all depth-0 nodes, then depth 1, ...), so the
-//    upper levels form one contiguous prefix of the buffer.
+//    upper levels form one contiguous prefix of the buffer;
+//  * a DF level (Sec. 3.3) keeps one word per cell instead of an interleaved pair: a
+//    non-empty cell's word is its pointer, an empty cell's word is DF_EMPTY | distance
+//    (a non-empty cell's distance is 0 by definition, so nothing is lost). A last DF
+//    level is a brick like a last Raw level whose blocks take 4 words: the mask and the
+//    capped L1 distance, in blocks, to the nearest non-empty block -- the walk reads one
+//    block per step there, so its distances are counted in blocks.
 #include <algorithm>
 #include <cstring>
 #include <unordered_map>
@@ -51,7 +57,6 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
   s.text = text;
   const std::string str(text);
   size_t i = 0;
-  bool unsupported = false;
   while (i < str.size()) {
     char c = str[i];
     if (c == ' ' || c == '\t') {
@@ -122,14 +127,13 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
       L.kind = LK_RAW;
       for (int k = 0; k < 3; ++k) L.e[k] = a[k];
     } else if (c == 'D') {
-      if (a.size() != 4 && !(a.size() == 3)) {
-        err = "D(W,H,D,M) takes four numbers";
+      if (a.size() != 4 || a[3] < 1) {
+        err = "D(W,H,D,M) takes three exponents and a maximum distance M >= 1";
         return HVF_E_SPEC;
       }
-      unsupported = true;
-      err = "distance-field levels are not implemented";
       L.kind = LK_RAW;
       for (int k = 0; k < 3; ++k) L.e[k] = a[k];
+      L.maxd = a[3];
     } else {
       if (a.size() != 1 || a[0] < 1) {
         err = std::string(1, c) + "(L) takes one depth >= 1";
@@ -170,7 +174,6 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
     err = "more than 16 node depths";
     return HVF_E_SPEC;
   }
-  if (unsupported) return HVF_E_UNSUPPORTED;
   out = s;
   return HVF_OK;
 }
@@ -185,7 +188,7 @@ Layout make_layout(const Spec& s) {
     if (lv.kind == LK_RAW && !last) {
       DepthInfo d{};
       d.level = k;
-      d.nk = NK_RAW_PTR;
+      d.nk = lv.maxd ? NK_DF_PTR : NK_RAW_PTR;
       d.hk = HK_RAW;
       d.cs = cs_level;
       for (int a = 0; a < 3; ++a) d.w[a] = lv.e[a];
@@ -199,7 +202,7 @@ Layout make_layout(const Spec& s) {
       if (blk[0] + blk[1] + blk[2] > 0) {
         DepthInfo d{};
         d.level = k;
-        d.nk = NK_BLOCKS;
+        d.nk = lv.maxd ? NK_DF_BLOCKS : NK_BLOCKS;
         d.hk = HK_RAW;
         d.cs = b;
         for (int a = 0; a < 3; ++a) d.w[a] = blk[a];
@@ -334,6 +337,40 @@ struct NodeMap {
   }
 };
 
+// Capped L1 distance transform of a 2^wx x 2^wy x 2^wz grid (x fastest): dist[i] =
+// min(cap, L1 distance from cell i to the nearest cell with occ set). L1 distance on the
+// grid is the length of a shortest path of face-neighbour moves, so a breadth-first search
+// from every occupied cell at once, stopped at depth cap, computes it.
+void capped_l1(const std::vector<uint8_t>& occ, int wx, int wy, int wz, uint32_t cap, std::vector<uint32_t>& dist) {
+  const uint64_t nx = 1ull << wx, ny = 1ull << wy, nz = 1ull << wz, n = nx * ny * nz;
+  dist.assign(n, cap);
+  std::vector<uint64_t> frontier, next;
+  for (uint64_t i = 0; i < n; ++i)
+    if (occ[i]) {
+      dist[i] = 0;
+      frontier.push_back(i);
+    }
+  for (uint32_t r = 1; r < cap && !frontier.empty(); ++r) {
+    next.clear();
+    for (uint64_t i : frontier) {
+      const uint64_t x = i & (nx - 1), y = (i >> wx) & (ny - 1), z = i >> (wx + wy);
+      auto visit = [&](uint64_t j) {
+        if (dist[j] > r) {
+          dist[j] = r;
+          next.push_back(j);
+        }
+      };
+      if (x > 0) visit(i - 1);
+      if (x + 1 < nx) visit(i + 1);
+      if (y > 0) visit(i - nx);
+      if (y + 1 < ny) visit(i + nx);
+      if (z > 0) visit(i - nx * ny);
+      if (z + 1 < nz) visit(i + nx * ny);
+    }
+    frontier.swap(next);
+  }
+}
+
 struct Builder {
   const Spec& S;
   const Layout& L;
@@ -369,26 +406,35 @@ struct Builder {
     const LevelSpec& lv = S.lv[di.level];
     const int cs = di.cs;
     std::vector<uint32_t>& A = arena[d];
-    if (di.nk == NK_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD)) {
-      // A brick of the last Raw level: blocks of side 2^b, one 64-bit mask each.
+    if (di.nk == NK_BLOCKS || di.nk == NK_DF_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD)) {
+      // A brick of the last Raw/DF level: blocks of side 2^b, one 64-bit mask each; a DF
+      // brick adds per block the capped L1 distance to the nearest non-empty block.
       const int b = L.brick_b;
       const int wx = lv.e[0] - b, wy = lv.e[1] - b;
       const int wz = lv.e[2] - b;
       const uint64_t nblocks = 1ull << (wx + wy + wz);
-      if (nblocks >= (1ull << 30)) throw Overflow();
+      const uint64_t stride = (di.nk == NK_DF_BLOCKS) ? 4 : 2;
+      if (nblocks * stride >= (1ull << 31)) throw Overflow();
       const uint32_t id = (uint32_t)A.size();
-      A.resize(A.size() + 2 * nblocks, 0u);
+      A.resize(A.size() + stride * nblocks, 0u);
       const uint64_t m = (1ull << b) - 1;
       for (size_t i = lo; i < hi; ++i) {
         const uint64_t vx = compact3(codes[i]) - x, vy = compact3(codes[i] >> 1) - y, vz = compact3(codes[i] >> 2) - z;
         const uint64_t blk = (vx >> b) | ((vy >> b) << wx) | ((vz >> b) << (wx + wy));
         const uint64_t bit = (vx & m) | ((vy & m) << b) | ((vz & m) << (2 * b));
-        A[id + 2 * blk + (bit >> 5)] |= 1u << (bit & 31);
+        A[id + stride * blk + (bit >> 5)] |= 1u << (bit & 31);
+      }
+      if (di.nk == NK_DF_BLOCKS) {
+        std::vector<uint8_t> occ(nblocks);
+        for (uint64_t k = 0; k < nblocks; ++k) occ[k] = (A[id + 4 * k] | A[id + 4 * k + 1]) != 0u;
+        std::vector<uint32_t> dist;
+        capped_l1(occ, wx, wy, wz, (uint32_t)lv.maxd, dist);
+        for (uint64_t k = 0; k < nblocks; ++k) A[id + 4 * k + 2] = dist[k];
       }
       ++nodes[d];
       return id;
     }
-    if (di.nk == NK_RAW_PTR) {
+    if (di.nk == NK_RAW_PTR || di.nk == NK_DF_PTR) {
       const int wx = di.w[0], wy = di.w[1], wz = di.w[2];
       const uint64_t cells = 1ull << (wx + wy + wz);
       if (cells >= (1ull << 31)) throw Overflow();
@@ -401,6 +447,14 @@ struct Builder {
         uint32_t child = build_root_of_next(d + 1, x + (cx << cs), y + (cy << cs), z + (cz << cs), a, b);
         arr[cx | (cy << wx) | (cz << (wx + wy))] = child + 1;  // id + 1; 0 = empty
         a = b;
+      }
+      if (di.nk == NK_DF_PTR) {
+        std::vector<uint8_t> occ(cells);
+        for (uint64_t k = 0; k < cells; ++k) occ[k] = arr[k] != 0u;
+        std::vector<uint32_t> dist;
+        capped_l1(occ, wx, wy, wz, (uint32_t)lv.maxd, dist);
+        for (uint64_t k = 0; k < cells; ++k)
+          if (!occ[k]) arr[k] = DF_EMPTY | dist[k];
       }
       const uint32_t id = (uint32_t)A.size();
       A.insert(A.end(), arr.begin(), arr.end());
@@ -534,8 +588,11 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
     auxb[d] = cur;
     cur += b.aux[d].size();
   }
-  if (cur >= (1ull << 32)) {
-    err = "format needs " + std::to_string(cur) + " words, beyond 32-bit word offsets";
+  bool df_ptr = false;
+  for (const DepthInfo& di : L.d) df_ptr = df_ptr || di.nk == NK_DF_PTR;
+  if (cur >= (df_ptr ? (1ull << 31) : (1ull << 32))) {
+    err = "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
+          "-bit word offsets" + (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : "");
     return HVF_E_OVERFLOW;
   }
   try {
@@ -554,6 +611,9 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
     switch (di.nk) {
       case NK_RAW_PTR:
         for (size_t i = 0; i < A.size(); ++i) dst[i] = A[i] ? (uint32_t)(nb + A[i] - 1) : 0u;
+        break;
+      case NK_DF_PTR:
+        for (size_t i = 0; i < A.size(); ++i) dst[i] = (A[i] & DF_EMPTY) ? A[i] : (uint32_t)(nb + A[i] - 1);
         break;
       case NK_SVO_INNER:
         for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(nb + A[i]);

@@ -14,7 +14,10 @@ enum LevelKind : int { LK_RAW = 0, LK_SVO = 1, LK_DAG = 2 };
 
 struct LevelSpec {
   int kind;
-  int e[3];  // log2 cells per axis (SVO/SVDAG: depth L on all three)
+  int e[3];      // log2 cells per axis (SVO/SVDAG: depth L on all three)
+  int maxd = 0;  // distance-field level D(W,H,D,M): M (>= 1); 0 for a plain Raw level.
+                 // A DF level is a Raw level (kind LK_RAW) whose empty cells also carry
+                 // their L1 distance to the nearest non-empty cell, capped at M (Sec. 3.3).
 };
 
 struct Spec {
@@ -30,23 +33,28 @@ struct Spec {
 hvf_status parse_spec(const char* s, Spec& out, std::string& err);
 
 // ------------------------------------------------------------------ traversal layout
-// The traversal walks "node depths": a Raw level above the last is one depth, an
-// SVO/SVDAG level of depth L is L depths, and the last level, if Raw, is a brick of
+// The traversal walks "node depths": a Raw or DF level above the last is one depth, an
+// SVO/SVDAG level of depth L is L depths, and the last level, if Raw or DF, is a brick of
 // 4x4x4-voxel blocks (one 64-bit occupancy mask each) walked as two depths: the blocks,
 // then the voxels of one block (whose mask is held in registers). Each depth has one
 // node kind (how a child cell is tested and its pointer found) and one header kind (how
-// a node at that depth is entered).
+// a node at that depth is entered). Octree kinds are numbered last (>= NK_SVO_INNER).
 enum NodeKind : int {
   NK_RAW_PTR = 0,    // Raw level above the last: one pointer word per cell, 0 = empty
   NK_BLOCKS = 1,     // last Raw level, block depth: one 64-bit mask per block, 0 = empty
-  NK_CELLS = 2,      // last Raw level, voxel depth: a bit of the block mask (registers)
-  NK_SVO_INNER = 3,  // SVO node whose children are SVO nodes: child = first + 2 * rank
-  NK_OCT_PTR = 4,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
+  NK_CELLS = 2,      // last Raw/DF level, voxel depth: a bit of the block mask (registers)
+  NK_DF_PTR = 3,     // DF level above the last: one word per cell, a pointer (< 2^31) if
+                     // the cell is non-empty, else DF_EMPTY | capped L1 distance in cells
+  NK_DF_BLOCKS = 4,  // last DF level, block depth: 4 words per block (mask lo, mask hi,
+                     // capped L1 distance in blocks to the nearest non-empty block, 0)
+  NK_SVO_INNER = 5,  // SVO node whose children are SVO nodes: child = first + 2 * rank
+  NK_OCT_PTR = 6,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
                      // deepest octree depth above the last level)
-  NK_OCT_FINAL = 5,  // deepest octree depth of the last level: valid mask = occupancy
-  NK_DAG_INNER = 6   // SVDAG node whose children are SVDAG nodes: a 2-word descriptor
+  NK_OCT_FINAL = 7,  // deepest octree depth of the last level: valid mask = occupancy
+  NK_DAG_INNER = 8   // SVDAG node whose children are SVDAG nodes: a 2-word descriptor
                      // (child pointer, child masks) per valid child at base + 2 * rank
 };
+constexpr uint32_t DF_EMPTY = 0x80000000u;  // marks an empty cell word of a DF pointer grid
 enum HeaderKind : int {
   HK_RAW = 0,       // base = pointer
   HK_SVO = 1,       // {first child / pointer array, masks}
@@ -107,11 +115,11 @@ void set_stacked(DevFormat& F, uint32_t mask);
 
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf);
 
-// Compile-time format families: bit k (k < 8) = node kind k may occur, bit 8 + h = header
-// kind h may occur. Trace kernels are instantiated per family so code for absent kinds
-// is not compiled in; a volume uses the first family that covers its layout.
+// Compile-time format families: bit k (k < 16) = node kind k may occur, bit 16 + h =
+// header kind h may occur. Trace kernels are instantiated per family so code for absent
+// kinds is not compiled in; a volume uses the first family that covers its layout.
 constexpr uint32_t fam_nk(int k) { return 1u << k; }
-constexpr uint32_t fam_hk(int h) { return 1u << (8 + h); }
+constexpr uint32_t fam_hk(int h) { return 1u << (16 + h); }
 constexpr uint32_t FAM_DAG_BRICK = fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) |
                                    fam_hk(HK_DAG) | fam_hk(HK_MASK) | fam_hk(HK_RAW) | fam_hk(HK_MASKLOAD);
 constexpr uint32_t FAM_SVO_BRICK = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) |
@@ -121,9 +129,12 @@ constexpr uint32_t FAM_RAW_BRICK = fam_nk(NK_RAW_PTR) | fam_nk(NK_BLOCKS) | fam_
 constexpr uint32_t FAM_OCTREE = fam_nk(NK_SVO_INNER) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_PTR) |
                                 fam_nk(NK_OCT_FINAL) | fam_hk(HK_SVO) | fam_hk(HK_DAG) | fam_hk(HK_MASK);
 constexpr uint32_t FAM_RAW_OCTREE = FAM_OCTREE | fam_nk(NK_RAW_PTR) | fam_hk(HK_RAW);
-constexpr uint32_t FAM_ALL = 0x7Fu | (0x1Fu << 8);
-constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE, FAM_ALL};
-constexpr int NUM_FAMILIES = 6;
+constexpr uint32_t FAM_DF_BRICK = FAM_RAW_BRICK | fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS);
+constexpr uint32_t FAM_DF_OCTREE = FAM_RAW_OCTREE | fam_nk(NK_DF_PTR);
+constexpr uint32_t FAM_ALL = 0x1FFu | (0x1Fu << 16);
+constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE,
+                                 FAM_RAW_OCTREE, FAM_DF_BRICK, FAM_DF_OCTREE, FAM_ALL};
+constexpr int NUM_FAMILIES = 8;
 
 // Index into FAMILIES of the first family covering the layout.
 int family_of(const Layout& L);

@@ -132,6 +132,9 @@ struct Counting {
 __device__ __forceinline__ uint2 ld2(const uint32_t* buf, uint32_t ix) {
   return *reinterpret_cast<const uint2*>(buf + ix);
 }
+__device__ __forceinline__ uint4 ld4(const uint32_t* buf, uint32_t ix) {
+  return *reinterpret_cast<const uint4*>(buf + ix);
+}
 
 enum : int { RUN = 0, DONE = 1 };
 
@@ -170,6 +173,13 @@ struct Walk {
   uint32_t info;  // descriptor of depth d
   uint32_t base, valid;
   uint32_t steps;
+  // Distance-field skipping at the current depth: every cell whose L1 distance (in cells
+  // of this depth) from the anchor cell a[] is below reach is known to be empty. The
+  // anchor is the last empty cell read; any change of depth clears reach. Along a ray
+  // each axis coordinate moves monotonically away from the anchor, so once a cell is
+  // outside that ball every later cell is too.
+  int a[3];
+  uint32_t reach;
 
   // Enter the node at pointer ptr whose depth descriptor is nd: returns its header
   // (base, valid). m: the 64-bit block mask the parent's test read (used by HK_MASK).
@@ -246,6 +256,7 @@ struct Walk {
     valid = h.y;
     t = R.t0;
     steps = 0;
+    reach = 0;
     return RUN;
   }
 
@@ -273,6 +284,31 @@ struct Walk {
       cm = ld2(buf, base + 2u * lin);
       mem.note(base + 2u * lin, 2);
       occ = (cm.x | cm.y) != 0u;
+    } else if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
+      // Cell positions at this depth are multiples of 2^cs, so the shift is exact.
+      const uint32_t l1 = (uint32_t)(abs(p[0] - a[0]) + abs(p[1] - a[1]) + abs(p[2] - a[2])) >> cs;
+      occ = false;
+      if (l1 >= reach) {  // not known to be empty: read the cell
+        uint32_t dist;
+        if ((FAM & fam_nk(NK_DF_PTR)) && nk == NK_DF_PTR) {
+          child = buf[base + lin];
+          mem.note(base + lin, 1);
+          occ = (child & DF_EMPTY) == 0u;
+          dist = child & ~DF_EMPTY;
+        } else {
+          const uint4 q = ld4(buf, base + 4u * lin);
+          mem.note(base + 4u * lin, 4);
+          cm = make_uint2(q.x, q.y);
+          occ = (q.x | q.y) != 0u;
+          dist = q.z;
+        }
+        if (!occ) {
+          reach = dist;
+          a[0] = p[0];
+          a[1] = p[1];
+          a[2] = p[2];
+        }
+      }
     } else {
       // A voxel's bit in the block mask (base:valid), or an octree child's valid bit.
       const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && lin < 32u) ? base : valid;
@@ -283,6 +319,7 @@ struct Walk {
       if (nk >= NK_SVO_INNER) octree_child<FAM>(buf, nk, lin, base, valid, child, cm, mem);
       if ((F.stacked >> d) & 1u) stk[slot_of(F.stacked, d) * BLOCK] = make_uint2(base, valid);
       ++d;
+      reach = 0;
       info = dtab[d];
       const uint2 h = enter<FAM>(buf, info, child, cm, mem);
       base = h.x;
@@ -341,12 +378,15 @@ struct Walk {
           const uint32_t knk = di_nk(info), kl = cell_lin(info);
           uint32_t child = 0u;
           uint2 cm = make_uint2(0u, 0u);
-          if ((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) {
-            child = buf[base + kl];
+          if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
+            child = buf[base + kl];  // an ancestor cell: non-empty, so a plain pointer
             mem.note(base + kl, 1);
           } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
             cm = ld2(buf, base + 2u * kl);
             mem.note(base + 2u * kl, 2);
+          } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
+            cm = ld2(buf, base + 4u * kl);
+            mem.note(base + 4u * kl, 2);
           } else {
             octree_child<FAM>(buf, knk, kl, base, valid, child, cm, mem);
           }
@@ -356,6 +396,7 @@ struct Walk {
           valid = h.y;
         }
         d = nd;
+        reach = 0;
         const int mask = ~((1 << di_cs(info)) - 1);
         p[0] &= mask;
         p[1] &= mask;
@@ -643,6 +684,8 @@ size_t stack_lds_bytes(const DevFormat& F) { return (size_t)(F.nslots ? F.nslots
     case 2: LAUNCH(FAM_RAW_BRICK); break;    \
     case 3: LAUNCH(FAM_OCTREE); break;       \
     case 4: LAUNCH(FAM_RAW_OCTREE); break;   \
+    case 5: LAUNCH(FAM_DF_BRICK); break;     \
+    case 6: LAUNCH(FAM_DF_OCTREE); break;    \
     default: LAUNCH(FAM_ALL); break;         \
   }
 

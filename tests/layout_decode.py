@@ -17,10 +17,15 @@ def _depths(info):
         sub[k] = sub[k + 1] + exps[k][0]
     out = []
     for k in range(n):
-        if kinds[k] == "R" and k < n - 1:
-            out.append((k, "R", 0, 1, sub[k + 1], exps[k]))
-        elif kinds[k] == "R":
-            out.append((k, "B", 0, 1, 0, exps[k]))  # last Raw level: a brick of 64-bit block masks
+        if kinds[k] in "RD" and k < n - 1:
+            # DF pointer grid: one word per cell, top bit set = empty (low bits: distance)
+            out.append((k, kinds[k], 0, 1, sub[k + 1], exps[k]))
+        elif kinds[k] in "RD":
+            # last Raw level: a brick of 64-bit block masks; a last DF level with more than
+            # one block stores 4 words per block (mask lo, mask hi, block distance, 0)
+            b = min(2, min(exps[k]))
+            many = sum(e - b for e in exps[k]) > 0
+            out.append((k, "E" if kinds[k] == "D" and many else "B", 0, 1, 0, exps[k]))
         else:
             L = exps[k][0]
             for j in range(L):
@@ -39,7 +44,7 @@ def decode(info, words):
 
     def enter(d, ptr):
         k, kind, j, L, cs, w = D[d]
-        if kind in ("R", "B"):
+        if kind in ("R", "B", "D", "E"):
             return ptr, 0xFF
         if kind == "S":
             return int(W[ptr]), int(W[ptr + 1]) & 0xFF
@@ -49,13 +54,14 @@ def decode(info, words):
         k, kind, j, L, cs, w = D[d]
         last_level = (k == nlev - 1)
         base, valid = enter(d, ptr)
-        if kind == "B":
+        if kind in ("B", "E"):
             # blocks of side 2^b (b = min(2, smallest exponent)), blocks x-fastest, one
             # 64-bit mask per block with bits x-fastest inside the block
             b = min(2, min(w))
             bx, by, bz = w[0] - b, w[1] - b, w[2] - b
+            st = 4 if kind == "E" else 2
             for blk in range(1 << (bx + by + bz)):
-                m = int(W[ptr + 2 * blk]) | (int(W[ptr + 2 * blk + 1]) << 32)
+                m = int(W[ptr + st * blk]) | (int(W[ptr + st * blk + 1]) << 32)
                 ox, oy, oz = blk & ((1 << bx) - 1), (blk >> bx) & ((1 << by) - 1), blk >> (bx + by)
                 for bit in range(64):
                     if (m >> bit) & 1:
@@ -63,11 +69,13 @@ def decode(info, words):
                         assert cz < (1 << b), "bit beyond the block"
                         out.append((corner[0] + (ox << b) + cx, corner[1] + (oy << b) + cy, corner[2] + (oz << b) + cz))
             return
-        if kind == "R":
+        if kind in ("R", "D"):
             wx, wy, wz = w
             ncell = 1 << (wx + wy + wz)
             for idx in range(ncell):
                 p = int(W[base + idx])
+                if kind == "D" and p >> 31:
+                    continue  # empty DF cell: the low bits hold its distance
                 if p:
                     cx, cy, cz = idx & ((1 << wx) - 1), (idx >> wx) & ((1 << wy) - 1), idx >> (wx + wy)
                     walk(d + 1, p, (corner[0] + (cx << cs), corner[1] + (cy << cs), corner[2] + (cz << cs)))
@@ -93,6 +101,49 @@ def decode(info, words):
     walk(0, root, (0, 0, 0))
     out.sort(key=lambda v: (v[2], v[1], v[0]))
     return out
+
+
+def df_grids(info, words):
+    """Every DF grid of the buffer: list of (kind, dims (nx, ny, nz), occupied[z, y, x], dist[z, y, x]).
+
+    kind "D": a pointer grid (distance in cells); "E": the block grid of a last DF level
+    (distance in blocks)."""
+    W = [int(v) for v in words] if len(words) < 200000 else words
+    D, nlev = _depths(info)
+    grids = []
+    root = int(W[0])
+    if root == 0:
+        return grids
+
+    def cells(d, ptr):
+        k, kind, j, L, cs, w = D[d]
+        if kind in ("D", "R"):
+            dims = (1 << w[0], 1 << w[1], 1 << w[2])
+            vals = np.array([int(W[ptr + i]) for i in range(dims[0] * dims[1] * dims[2])], dtype=np.uint64)
+            if kind == "D":
+                occ = (vals >> np.uint64(31)) == 0
+                dist = np.where(occ, 0, vals & np.uint64(0x7FFFFFFF))
+                grids.append(("D", dims, occ.reshape(dims[::-1]), dist.reshape(dims[::-1]).astype(np.int64)))
+                kids = [int(v) for v in vals[occ]]
+            else:
+                kids = [int(v) for v in vals if v]
+            if d + 1 < len(D) and D[d + 1][1] in ("R", "D", "B", "E"):
+                for c in kids:
+                    cells(d + 1, c)
+            elif d + 1 < len(D):
+                # octree below: DF grids deeper than an octree are not listed
+                pass
+        elif kind == "E":
+            b = min(2, min(w))
+            dims = (1 << (w[0] - b), 1 << (w[1] - b), 1 << (w[2] - b))
+            nb = dims[0] * dims[1] * dims[2]
+            q = np.array([int(W[ptr + i]) for i in range(4 * nb)], dtype=np.uint64).reshape(nb, 4)
+            occ = (q[:, 0] | q[:, 1]) != 0
+            grids.append(("E", dims, occ.reshape(dims[::-1]), q[:, 2].astype(np.int64).reshape(dims[::-1])))
+            assert np.all(q[:, 3] == 0)
+
+    cells(0, root)
+    return grids
 
 
 def decode_codes(info, words, morton_encode):

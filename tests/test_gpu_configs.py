@@ -9,6 +9,8 @@
   on that sample and traced by both. The oracle traces the same volume built as G(11):
   every format of one volume has the same first hits (pinned on the CPU), and G(11) is
   the format the oracle builds in seconds at this size.
+* The distance-field formats of the table at 512^3 and one at 2048^3, the same way
+  (D(9,9,9,6) against the flat DDA, like R(9,9,9)).
 """
 import numpy as np
 import pytest
@@ -54,11 +56,11 @@ def _trace_full(vol, rays):
     return h.cpu().numpy()
 
 
-@pytest.mark.parametrize("spec", C.SURF512["specs"])
+@pytest.mark.parametrize("spec", C.SURF512["specs"] + C.SURF512_DF)
 def test_surface512(H, surf512, spec):
     cfg, codes, views = surf512
     vol = H.Volume(spec, codes)
-    if spec.startswith("R(9,9,9)"):
+    if spec.startswith("R(9,9,9)") or spec.startswith("D(9,9,9"):
         dense = _dense(codes, 9)
         ref_fn = lambda r: oracle.flat_dda(dense, (9, 9, 9), r)
     else:
@@ -92,7 +94,8 @@ def surf2048():
     return cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r
 
 
-@pytest.mark.parametrize("spec", C.SURF2048["specs"] + ["G(7) R(4,4,4) --whole-level-dedup --restart-sv"])
+@pytest.mark.parametrize("spec", C.SURF2048["specs"] + ["G(7) R(4,4,4) --whole-level-dedup --restart-sv",
+                                                        "D(4,4,4,6) G(7) --whole-level-dedup"])
 def test_surface2048(H, surf2048, spec):
     cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
     vol = H.Volume(spec, codes)

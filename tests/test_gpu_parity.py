@@ -8,7 +8,7 @@ import pytest
 import oracle
 import workloads as W
 from tests.gpu_util import compare, gpu_trace
-from tests.test_oracle_pins import EDGE_CASES, EDGE_SPECS, EDGE_VOX, SPECS_8, codes_of
+from tests.test_oracle_pins import DF_SPECS, EDGE_CASES, EDGE_SPECS, EDGE_VOX, SPECS_8, codes_of
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ def test_small_config_full_frame(H):
     assert 0.2 < (ref[:, 0] >= 0).mean() < 0.9
 
 
-@pytest.mark.parametrize("spec", SPECS_8)
+@pytest.mark.parametrize("spec", SPECS_8 + DF_SPECS)
 def test_every_type_sequence_tiny(H, spec):
     for seed in (1, 2, 3):
         codes = W.scene_bernoulli(seed, 3, 3, 3, 0.05 * seed)
@@ -44,7 +44,7 @@ def test_every_type_sequence_tiny(H, spec):
         assert compare(got, ref, f"{spec} seed {seed}") == 0
 
 
-@pytest.mark.parametrize("spec", EDGE_SPECS)
+@pytest.mark.parametrize("spec", EDGE_SPECS + ["D(3,3,3,6)", "D(1,1,1,3) R(2,2,2)", "S(1) D(2,2,2,6)"])
 def test_edge_suite(H, spec):
     codes = codes_of(EDGE_VOX)
     rays = np.concatenate([r for r, _ in EDGE_CASES])
@@ -58,7 +58,8 @@ def test_edge_suite(H, spec):
             assert (int(g[0]), int(g[1]), int(g[2]), float(np.int32(g[3]).view(np.float32))) == e
 
 
-@pytest.mark.parametrize("spec", ["R(1,0,2) R(2,2,2)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)", "R(3,2,4)"])
+@pytest.mark.parametrize("spec", ["R(1,0,2) R(2,2,2)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)", "R(3,2,4)",
+                                  "D(1,0,2,3) R(2,2,2)", "D(3,2,4,6)", "D(1,0,2,2) D(2,2,2,4)"])
 def test_noncubic_top(H, spec):
     codes = W.scene_bernoulli(3, 3, 2, 4, 0.08)
     rays = np.concatenate([W.random_rays(4, (8, 4, 16), 3000), W.camera_rays(4, 0, (8, 4, 16), 48, 32)])
@@ -101,7 +102,8 @@ def test_schedules_give_identical_results(H, sd):
     sc = H.schedule(**sd)
     cases = [("R(2,2,2) S(2) R(2,2,2)", W.scene_solid_noise(1), (64,) * 3),
              ("G(4) R(3,3,3) --whole-level-dedup", W.scene_shell(3, 7, 8, 4, 1.4), (128,) * 3),
-             ("S(1) G(1) R(1,1,1)", W.scene_bernoulli(2, 3, 3, 3, 0.1), (8,) * 3)]
+             ("S(1) G(1) R(1,1,1)", W.scene_bernoulli(2, 3, 3, 3, 0.1), (8,) * 3),
+             ("D(2,2,2,4) D(2,2,2,6) D(3,3,3,6)", W.scene_shell(3, 7, 8, 4, 1.4), (128,) * 3)]
     for spec, codes, ext in cases:
         rays = np.concatenate([W.camera_rays(3, 0, ext, 160, 120), W.random_rays(3, ext, 30000),
                                np.concatenate([r for r, _ in EDGE_CASES])])
@@ -145,3 +147,15 @@ def test_restart_sv(H, spec):
         got = gpu_trace(H.Volume(spec, codes), rays)
         ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
         assert compare(got, ref, f"{spec} seed {seed}") == 0
+
+
+@pytest.mark.parametrize("spec", ["D(6,6,6,6)", "D(4,4,4,6) R(2,2,2)", "D(3,3,3,6) D(3,3,3,6)",
+                                  "D(2,2,2,6) G(4) --whole-level-dedup", "D(3,3,3,99) S(3)", "D(2,2,2,1) D(4,4,4,1)"])
+def test_distance_field_sparse_scene(H, spec):
+    """DF levels skip cells by their stored distance (Sec. 4.2); a sparse shell scene makes
+    long skips. Hits must equal the oracle's, on primary and random rays."""
+    codes = W.scene_shell(4, 6, 8, 4, 1.4)
+    rays = np.concatenate([W.camera_rays(4, 0, (64, 64, 64), 96, 64), W.random_rays(4, (64, 64, 64), 6000)])
+    got = gpu_trace(H.Volume(spec, codes), rays)
+    ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
+    assert compare(got, ref, spec) == 0

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.layout_decode import decode_codes
+from tests.layout_decode import decode_codes, df_grids
 
 H = pytest.importorskip("paper_2410_14128_amd")
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -41,7 +41,9 @@ def test_exports_every_declared_symbol():
 
 SPECS = ["R(3,3,3)", "S(3)", "G(3)", "R(1,1,1) R(2,2,2)", "R(2,2,2) S(1)", "R(1,1,1) G(2)", "S(1) R(2,2,2)",
          "S(2) S(1)", "S(1) G(2)", "G(2) R(1,1,1)", "G(1) S(2)", "G(1) G(2)", "R(1,1,1) S(1) G(1)",
-         "S(1) G(1) R(1,1,1)", "G(1) R(1,1,1) S(1)", "G(1) G(1) G(1) --whole-level-dedup", "R(1,1,1) G(2) --wld"]
+         "S(1) G(1) R(1,1,1)", "G(1) R(1,1,1) S(1)", "G(1) G(1) G(1) --whole-level-dedup", "R(1,1,1) G(2) --wld",
+         "D(3,3,3,6)", "D(1,1,1,2) R(2,2,2)", "R(1,1,1) D(2,2,2,3)", "D(2,2,2,6) S(1)", "G(1) D(2,2,2,4)",
+         "D(1,1,1,3) D(1,1,1,3) D(1,1,1,3)", "S(1) D(1,1,1,1) G(1)", "D(1,1,1,5) D(2,2,2,5)"]
 
 
 @pytest.mark.parametrize("spec", SPECS)
@@ -103,19 +105,16 @@ def test_table_of_formats():
             continue
         label, side, spec = line.split(maxsplit=2)
         spec = spec.strip()
-        if "D(" in spec:
-            with pytest.raises(H.HvfError) as e:
-                H.Volume(spec, np.zeros(0, np.uint64))
-            assert e.value.name == "HVF_E_UNSUPPORTED"
-            continue
         info = H.Volume(spec, np.zeros(0, np.uint64)).info()
         assert info["extent_log2"] == (int(side).bit_length() - 1,) * 3, (label, spec)
+        assert info["kinds"] == "".join(c for c in spec if c in "RDSG"), (label, spec)
 
 
 @pytest.mark.parametrize("spec,status", [
     ("R(2,2,2) S(1,1,1)", "HVF_E_SPEC"), ("S(2) R(1,0,2)", "HVF_E_SPEC"), ("Q(3)", "HVF_E_SPEC"),
     ("R(3,3)", "HVF_E_SPEC"), ("S(0)", "HVF_E_SPEC"), ("", "HVF_E_SPEC"), ("R(3,3,3) --bogus", "HVF_E_SPEC"),
-    ("G(9) G(9)", "HVF_E_SPEC"), ("D(4,4,4,6) G(5)", "HVF_E_UNSUPPORTED"), ("R(4,4,4) G(5) --bogus-flag", "HVF_E_SPEC"),
+    ("G(9) G(9)", "HVF_E_SPEC"), ("D(4,4,4) G(5)", "HVF_E_SPEC"), ("D(4,4,4,0) G(5)", "HVF_E_SPEC"),
+    ("D(4^3) G(5)", "HVF_E_SPEC"), ("D(4,4,4,100)", "HVF_E_SPEC"), ("R(4,4,4) G(5) --bogus-flag", "HVF_E_SPEC"),
 ])
 def test_spec_errors(spec, status):
     with pytest.raises(H.HvfError) as e:
@@ -170,3 +169,52 @@ def test_restart_sv_is_accepted_and_keeps_the_layout():
     a = H.Volume("R(2,2,2) G(2) --whole-level-dedup", codes)
     b = H.Volume("R(2,2,2) G(2) --whole-level-dedup --restart-sv", codes)
     assert np.array_equal(a.words(), b.words())  # an intersection option, not a format change
+
+
+# ------------------------------------------------------------------ distance-field levels
+def _capped_taxicab(occ, cap):
+    """min(cap, L1 distance to the nearest occupied cell), via scipy's chamfer transform."""
+    from scipy.ndimage import distance_transform_cdt
+    if not occ.any():
+        return np.full(occ.shape, cap, np.int64)
+    return np.minimum(distance_transform_cdt(~occ, metric="taxicab").astype(np.int64), cap)
+
+
+@pytest.mark.parametrize("spec,p", [("D(3,2,4,6)", 0.02), ("D(2,2,2,3) R(2,2,2)", 0.01), ("D(4,4,4,2) R(2,2,2)", 0.003),
+                                    ("D(1,1,1,5) D(2,2,2,5)", 0.004), ("D(2,2,2,99) D(1,1,1,4) S(1)", 0.002),
+                                    ("R(1,1,1) D(4,4,4,6)", 0.01)])
+def test_df_distances(spec, p):
+    """Every stored distance is the capped L1 distance in cells (pointer grids) or in
+    4^3 blocks (the block grid of a last DF level) to the nearest non-empty cell."""
+    ext = H.Volume(spec, np.zeros(0, np.uint64)).info()["extent_log2"]
+    codes = W.scene_bernoulli(int(p * 1e4), ext[0], ext[1], ext[2], p)
+    v = H.Volume(spec, codes)
+    info = v.info()
+    assert np.array_equal(decode_codes(info, v.words(), W.morton_encode), codes)
+    grids = df_grids(info, v.words())
+    assert grids
+    # the cap of each DF grid, by (kind, dims): pointer grids have 2^e cells per axis,
+    # the block grid of a last DF level 2^(e - 2)
+    cap_of = {}
+    for k, e in enumerate(info["level_exp"]):
+        if info["kinds"][k] == "D":
+            cap_of[("D", tuple(1 << x for x in e))] = info["level_maxdist"][k]
+            if min(e) >= 2:
+                cap_of[("E", tuple(1 << (x - 2) for x in e))] = info["level_maxdist"][k]
+    for kind, dims, occ, dist in grids:
+        assert occ.any()  # a stored sub-volume is never empty
+        cap = cap_of[(kind, dims)]
+        assert np.array_equal(dist, _capped_taxicab(occ, cap)), (spec, kind, dims)
+
+
+def test_df_layout_sizes():
+    codes = np.array([0], np.uint64)
+    # one word per pointer-grid cell (like Raw); a DF block takes 16 bytes instead of 8
+    a = H.Volume("D(3,3,3,6) R(2,2,2)", codes).info()
+    b = H.Volume("R(3,3,3) R(2,2,2)", codes).info()
+    assert a["num_words"] == b["num_words"]
+    c = H.Volume("D(4,4,4,6)", codes).info()
+    d = H.Volume("R(4,4,4)", codes).info()
+    assert c["depth_offset"][0] == d["depth_offset"][0] and c["num_words"] - c["depth_offset"][0] == 4 * 64
+    assert d["num_words"] - d["depth_offset"][0] == 2 * 64
+    assert a["kinds"] == "DR" and a["level_maxdist"] == [6, 0]

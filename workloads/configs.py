@@ -29,6 +29,12 @@ SURF512 = dict(
         "S(5) R(4,4,4)",                     # table row 32
     ])
 
+# Distance-field formats of the table at 512^3 (rows 21, 22, 26, 27, 34, 35, 38), traced on
+# the same volume and views; measured beside the nine formats above, not part of them.
+SURF512_DF = ["D(3,3,3,6) D(3,3,3,6) G(3) --whole-level-dedup", "D(3,3,3,6) R(3,3,3) G(3) --whole-level-dedup",
+              "D(4,4,4,6) S(5)", "D(4,4,4,6) G(5) --whole-level-dedup", "D(5,5,5,6) D(4,4,4,6)",
+              "D(5,5,5,6) R(4,4,4)", "D(9,9,9,6)"]
+
 # 2048^3 surface volume: 96 spheres + 32 tori; SVDAG top 7 levels -> Raw 16^3 bricks, and
 # SVO -> Raw 8^3; 1080p primary rays plus one cosine-weighted bounce per primary hit.
 SURF2048 = dict(name="surface-2048", log2n=11, seed=3, n_sph=96, n_tor=32, scale=1.2, width=1920, height=1080,
