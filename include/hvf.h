@@ -99,7 +99,9 @@ typedef struct hvf_schedule {
   int32_t blocks_per_cu;
   int32_t stack_depth; /* > 0: keep node-stack slots only for depths < stack_depth and
                           re-descend from the deepest kept ancestor on a deeper pop */
-  int32_t reserved;
+  int32_t lds_depths;  /* > 0: every block first copies the nodes of the top lds_depths
+                          depths (a prefix of the buffer, at most 32 KiB) into LDS and
+                          reads them there; HVF_E_INPUT if the prefix is larger */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).

@@ -52,18 +52,18 @@ class hvf_info(ctypes.Structure):
 class hvf_schedule(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int32), ("refill", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("sort", ctypes.c_int32), ("sort_bits", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("stack_depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("stack_depth", ctypes.c_int32), ("lds_depths", ctypes.c_int32)]
 
 
 def schedule(persistent: int = 0, refill: int = 16, inner: int = 8, sort: int = 0, sort_bits: int = 4,
-             blocks_per_cu: int = 0, stack_depth: int = 0) -> hvf_schedule:
+             blocks_per_cu: int = 0, stack_depth: int = 0, lds_depths: int = 0) -> hvf_schedule:
     """A device schedule for a trace (results never depend on it)."""
-    return hvf_schedule(persistent, refill, inner, sort, sort_bits, blocks_per_cu, stack_depth)
+    return hvf_schedule(persistent, refill, inner, sort, sort_bits, blocks_per_cu, stack_depth, lds_depths)
 
 
 def schedule_dict(s: hvf_schedule) -> dict:
     return {"persistent": s.persistent, "refill": s.refill, "inner": s.inner, "sort": s.sort, "sort_bits": s.sort_bits,
-            "blocks_per_cu": s.blocks_per_cu, "stack_depth": s.stack_depth}
+            "blocks_per_cu": s.blocks_per_cu, "stack_depth": s.stack_depth, "lds_depths": s.lds_depths}
 
 
 class hvf_batch_opts(ctypes.Structure):

@@ -108,7 +108,8 @@ namespace {
 hvf_status check_sched(const hvf_schedule& sc) {
   if (sc.persistent < 0 || sc.persistent > 1 || sc.refill < 1 || sc.refill > 64 || sc.inner < 1 || sc.inner > 4096 ||
       sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16 || sc.blocks_per_cu < 0 ||
-      sc.blocks_per_cu > 64 || sc.stack_depth < 0 || sc.stack_depth > HVF_MAX_DEPTH)
+      sc.blocks_per_cu > 64 || sc.stack_depth < 0 || sc.stack_depth > HVF_MAX_DEPTH || sc.lds_depths < 0 ||
+      sc.lds_depths > HVF_MAX_DEPTH)
     return fail(HVF_E_INPUT, "schedule field out of range");
   return HVF_OK;
 }
@@ -126,6 +127,9 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (st != HVF_OK) return st;
   hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
   if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
+  if (!hvf::lds_prefix_words(v->layout, v->built, sc.lds_depths, &F.lds_words))
+    return fail(HVF_E_INPUT, "the top " + std::to_string(sc.lds_depths) + " depths exceed the LDS prefix limit of " +
+                                 std::to_string(hvf::HVF_LDS_PREFIX_MAX_WORDS) + " words");
   hipStream_t s = (hipStream_t)stream;
   uint32_t* counter = nullptr;
   if (sc.persistent || sc.sort) {
@@ -172,23 +176,43 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
   float best_ms = 1e30f;
   hvf_schedule best = cand[0];
   hvf_status st = HVF_OK;
-  for (const hvf_schedule& c : cand) {
+  auto time_one = [&](const hvf_schedule& c) {
     st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);  // warm-up (uploads on first use)
-    if (st != HVF_OK) break;
+    if (st != HVF_OK) return;
     float tot = 0.0f;
     const int reps = 3;
     bool ok = hipEventRecord(e0, s) == hipSuccess;
     for (int r = 0; r < reps && st == HVF_OK; ++r) st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);
     ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(&tot, e0, e1) == hipSuccess;
-    if (st != HVF_OK) break;
+    if (st != HVF_OK) return;
     if (!ok) {
       st = fail(HVF_E_DEVICE, "event timing failed during autotune");
-      break;
+      return;
     }
     if (tot / reps < best_ms) {
       best_ms = tot / reps;
       best = c;
+    }
+  };
+  for (const hvf_schedule& c : cand) {
+    time_one(c);
+    if (st != HVF_OK) break;
+  }
+  // Second round: stage the top depths of the buffer in LDS under the best schedule, for
+  // the three deepest prefixes that fit (distinct sizes only).
+  if (st == HVF_OK) {
+    const hvf_schedule base = best;
+    uint32_t last = 0;
+    int tried = 0;
+    for (int k = nd; k >= 1 && tried < 3 && st == HVF_OK; --k) {
+      uint32_t w = 0;
+      if (!hvf::lds_prefix_words(v->layout, v->built, k, &w) || w == 0 || w == last) continue;
+      last = w;
+      ++tried;
+      hvf_schedule c = base;
+      c.lds_depths = k;
+      time_one(c);
     }
   }
   (void)hipEventDestroy(e0);

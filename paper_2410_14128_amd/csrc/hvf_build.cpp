@@ -263,6 +263,19 @@ uint32_t stacked_mask(const Layout& L, bool restart_sv, int stack_depth) {
   return m;
 }
 
+bool lds_prefix_words(const Layout& L, const Built& B, int lds_depths, uint32_t* words) {
+  uint64_t w = 0;
+  if (lds_depths > 0 && B.words.size() > 1) {
+    if (lds_depths < (int)L.d.size() && lds_depths < (int)B.depth_offset.size())
+      w = B.depth_offset[lds_depths];
+    else
+      w = B.words.size() & ~3ull;
+  }
+  if (w > HVF_LDS_PREFIX_MAX_WORDS) return false;
+  *words = (uint32_t)w;
+  return true;
+}
+
 void set_stacked(DevFormat& F, uint32_t mask) {
   F.stacked = mask;
   F.nslots = (uint32_t)__builtin_popcount(mask);

@@ -98,6 +98,7 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
 // stacked: bit d set = depth d keeps a node-stack slot (slot index = number of stacked
 // depths above d). A pop to a depth without a slot restores the deepest stacked ancestor
 // and descends again along the current cell position.
+// lds_words: leading buffer words each block stages in LDS (0 = none); a multiple of 4.
 struct DevFormat {
   const uint32_t* buf;
   int32_t ext[3];
@@ -105,8 +106,19 @@ struct DevFormat {
   uint64_t pop_lut;
   uint32_t stacked;
   uint32_t nslots;
+  uint32_t lds_words;
+  uint32_t pad;
   uint32_t dinfo[HVF_MAX_DEPTH];
 };
+
+// Largest prefix a schedule may stage in LDS (32 KiB; the node stack takes at most 32 KiB
+// more, so a block stays within 64 KiB).
+constexpr uint32_t HVF_LDS_PREFIX_MAX_WORDS = 8192;
+
+// Words staged for lds_depths top depths: the start of depth lds_depths (depths are stored
+// in order, each 64-byte aligned), or the whole buffer rounded down to 4 words when every
+// depth is staged. Returns false if that exceeds HVF_LDS_PREFIX_MAX_WORDS.
+bool lds_prefix_words(const Layout& L, const Built& B, int lds_depths, uint32_t* words);
 
 // Stack-slot mask of a layout: every depth, or with restart-sv only the root depth of each
 // level; stack_depth > 0 further keeps only depths < stack_depth (depth 0 always).

@@ -140,20 +140,32 @@ enum : int { RUN = 0, DONE = 1 };
 
 // The format a lane walks: word buffer, pop table, per-axis extents and the per-depth
 // descriptor table (in LDS). Uniform across a launch for single-volume kernels; per lane
-// in the batched kernel.
+// in the batched kernel. The first npre words of the buffer (the top depths: nodes are
+// stored depth by depth) may be staged in LDS at pre; reads below npre go there.
 struct Fmt {
   const uint32_t* buf;
   uint64_t pop_lut;
   const uint32_t* dtab;
   int ext[3];
   uint32_t stacked;  // depths with a node-stack slot
+  const uint32_t* pre;
+  uint32_t npre;
+  __device__ __forceinline__ uint32_t w1(uint32_t ix) const { return ix < npre ? pre[ix] : buf[ix]; }
+  __device__ __forceinline__ uint2 w2(uint32_t ix) const {
+    return ix + 2u <= npre ? make_uint2(pre[ix], pre[ix + 1u]) : ld2(buf, ix);
+  }
+  __device__ __forceinline__ uint4 w4(uint32_t ix) const {
+    return ix + 4u <= npre ? make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]) : ld4(buf, ix);
+  }
 };
 
 // Stack slot of depth d: the number of stacked depths above it.
 __device__ __forceinline__ uint32_t slot_of(uint32_t stacked, int d) { return __popc(stacked & ((1u << d) - 1u)); }
 
-__device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab) {
+__device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab, const uint32_t* pre) {
   Fmt f;
+  f.pre = pre;
+  f.npre = pre ? F.lds_words : 0u;
   f.buf = F.buf;
   f.pop_lut = F.pop_lut;
   f.dtab = dtab;
@@ -184,17 +196,16 @@ struct Walk {
   // Enter the node at pointer ptr whose depth descriptor is nd: returns its header
   // (base, valid). m: the 64-bit block mask the parent's test read (used by HK_MASK).
   template <uint32_t FAM, class Mem>
-  __device__ __forceinline__ static uint2 enter(const uint32_t* __restrict__ buf, uint32_t nd, uint32_t ptr, uint2 m,
-                                                Mem& mem) {
+  __device__ __forceinline__ static uint2 enter(const Fmt& F, uint32_t nd, uint32_t ptr, uint2 m, Mem& mem) {
     const uint32_t hk = di_hk(nd);
     if ((FAM & fam_hk(HK_RAW)) && hk == HK_RAW) return make_uint2(ptr, 0u);
     if ((FAM & fam_hk(HK_MASK)) && hk == HK_MASK) return m;
     if ((FAM & fam_hk(HK_DAG)) && hk == HK_DAG) {
       mem.note(ptr, 1);
-      return make_uint2(ptr + 1u, buf[ptr] & 0xFFu);
+      return make_uint2(ptr + 1u, F.w1(ptr) & 0xFFu);
     }
     // HK_SVO (first, masks) or HK_MASKLOAD (lo, hi)
-    const uint2 h = ld2(buf, ptr);
+    const uint2 h = F.w2(ptr);
     mem.note(ptr, 2);
     if (!(FAM & fam_hk(HK_SVO))) return h;
     if (!(FAM & fam_hk(HK_MASKLOAD))) return make_uint2(h.x, h.y & 0xFFu);
@@ -204,19 +215,19 @@ struct Walk {
   // Pointer (and, for SVDAG descriptors, the child's header) of the occupied child `lin`
   // of an octree node with header (base, valid).
   template <uint32_t FAM, class Mem>
-  __device__ __forceinline__ static void octree_child(const uint32_t* __restrict__ buf, uint32_t nk, uint32_t lin,
+  __device__ __forceinline__ static void octree_child(const Fmt& F, uint32_t nk, uint32_t lin,
                                                       uint32_t base, uint32_t valid, uint32_t& child, uint2& cm,
                                                       Mem& mem) {
     const uint32_t rank = __popc(valid & ((1u << lin) - 1u));
     if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) {
       child = base + 2u * rank;
     } else if ((FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER) {
-      const uint2 dsc = ld2(buf, base + 2u * rank);  // (child pointer, child masks)
+      const uint2 dsc = F.w2(base + 2u * rank);  // (child pointer, child masks)
       mem.note(base + 2u * rank, 2);
       child = dsc.x;
       cm = make_uint2(dsc.x + 1u, dsc.y & 0xFFu);
     } else {
-      child = buf[base + rank];
+      child = F.w1(base + rank);
       mem.note(base + rank, 1);
     }
   }
@@ -230,9 +241,8 @@ struct Walk {
   // Start the walk of a ray that passed setup. Returns DONE if the volume is empty.
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int start(const Fmt& F, Mem& mem) {
-    const uint32_t* __restrict__ buf = F.buf;
     const uint32_t* dtab = F.dtab;
-    const uint32_t root = buf[0];  // word 0: pointer to the root sub-volume; 0 = empty
+    const uint32_t root = F.w1(0);  // word 0: pointer to the root sub-volume; 0 = empty
     mem.note(0, 1);
     if (root == 0u) return DONE;
     d = 0;
@@ -251,7 +261,7 @@ struct Walk {
         p[a] = up ? mid : p[a];
       }
     }
-    const uint2 h = enter<FAM>(buf, info, root, make_uint2(0u, 0u), mem);
+    const uint2 h = enter<FAM>(F, info, root, make_uint2(0u, 0u), mem);
     base = h.x;
     valid = h.y;
     t = R.t0;
@@ -263,7 +273,6 @@ struct Walk {
   // One step. On DONE, out holds the result (a miss leaves it untouched).
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int step(const Fmt& F, uint2* stk, int4& out, Mem& mem) {
-    const uint32_t* __restrict__ buf = F.buf;
     const uint32_t* dtab = F.dtab;
     if (++steps > MAX_STEPS) {
       out = make_int4(-2, -2, -2, 0);  // guard tripped: reported, never silent
@@ -277,11 +286,11 @@ struct Walk {
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
     if ((FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR) {
-      child = buf[base + lin];
+      child = F.w1(base + lin);
       mem.note(base + lin, 1);
       occ = child != 0u;
     } else if ((FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS) {
-      cm = ld2(buf, base + 2u * lin);
+      cm = F.w2(base + 2u * lin);
       mem.note(base + 2u * lin, 2);
       occ = (cm.x | cm.y) != 0u;
     } else if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
@@ -291,12 +300,12 @@ struct Walk {
       if (l1 >= reach) {  // not known to be empty: read the cell
         uint32_t dist;
         if ((FAM & fam_nk(NK_DF_PTR)) && nk == NK_DF_PTR) {
-          child = buf[base + lin];
+          child = F.w1(base + lin);
           mem.note(base + lin, 1);
           occ = (child & DF_EMPTY) == 0u;
           dist = child & ~DF_EMPTY;
         } else {
-          const uint4 q = ld4(buf, base + 4u * lin);
+          const uint4 q = F.w4(base + 4u * lin);
           mem.note(base + 4u * lin, 4);
           cm = make_uint2(q.x, q.y);
           occ = (q.x | q.y) != 0u;
@@ -316,12 +325,12 @@ struct Walk {
     }
     const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL);
     if (occ && !fin) {
-      if (nk >= NK_SVO_INNER) octree_child<FAM>(buf, nk, lin, base, valid, child, cm, mem);
+      if (nk >= NK_SVO_INNER) octree_child<FAM>(F, nk, lin, base, valid, child, cm, mem);
       if ((F.stacked >> d) & 1u) stk[slot_of(F.stacked, d) * BLOCK] = make_uint2(base, valid);
       ++d;
       reach = 0;
       info = dtab[d];
-      const uint2 h = enter<FAM>(buf, info, child, cm, mem);
+      const uint2 h = enter<FAM>(F, info, child, cm, mem);
       base = h.x;
       valid = h.y;
       refine3(R, p, cs, di_cs(info), t);
@@ -379,19 +388,19 @@ struct Walk {
           uint32_t child = 0u;
           uint2 cm = make_uint2(0u, 0u);
           if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
-            child = buf[base + kl];  // an ancestor cell: non-empty, so a plain pointer
+            child = F.w1(base + kl);  // an ancestor cell: non-empty, so a plain pointer
             mem.note(base + kl, 1);
           } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
-            cm = ld2(buf, base + 2u * kl);
+            cm = F.w2(base + 2u * kl);
             mem.note(base + 2u * kl, 2);
           } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
-            cm = ld2(buf, base + 4u * kl);
+            cm = F.w2(base + 4u * kl);
             mem.note(base + 4u * kl, 2);
           } else {
-            octree_child<FAM>(buf, knk, kl, base, valid, child, cm, mem);
+            octree_child<FAM>(F, knk, kl, base, valid, child, cm, mem);
           }
           info = dtab[k + 1];
-          const uint2 h = enter<FAM>(buf, info, child, cm, mem);
+          const uint2 h = enter<FAM>(F, info, child, cm, mem);
           base = h.x;
           valid = h.y;
         }
@@ -407,6 +416,18 @@ struct Walk {
   }
 };
 
+// Copy the first F.lds_words words of the buffer (a multiple of 4; the top depths) into
+// LDS right after the node stack; returns that LDS copy, or null when nothing is staged.
+// Must precede load_dtab, whose barrier publishes the copy.
+__device__ __forceinline__ const uint32_t* stage_prefix(const DevFormat& F, uint2* stk_all) {
+  if (F.lds_words == 0u) return nullptr;
+  uint32_t* pre = reinterpret_cast<uint32_t*>(stk_all + (size_t)(F.nslots ? F.nslots : 1u) * BLOCK);
+  const uint4* src = reinterpret_cast<const uint4*>(F.buf);
+  uint4* dst = reinterpret_cast<uint4*>(pre);
+  for (uint32_t i = threadIdx.x; i < F.lds_words / 4u; i += BLOCK) dst[i] = src[i];
+  return pre;
+}
+
 __device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
   if (threadIdx.x < HVF_MAX_DEPTH) dtab[threadIdx.x] = F.dinfo[threadIdx.x];
   __syncthreads();
@@ -419,8 +440,9 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
                                                       int4* __restrict__ hits, uint32_t n) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
-  const Fmt fm = fmt_of(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
@@ -443,8 +465,9 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
                                                                  uint32_t inner) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
-  const Fmt fm = fmt_of(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
   uint2* stk = stk_all + threadIdx.x;
   const uint32_t lane = __lane_id();
   Walk w;
@@ -493,8 +516,9 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
                                                               const uint32_t* __restrict__ key) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
-  const Fmt fm = fmt_of(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t k = blockIdx.x * BLOCK + threadIdx.x;
   if (k >= n || key[k] == 0xFFFFFFFFu) return;  // rays that miss the root box were answered
   const uint32_t i = perm[k];
@@ -581,6 +605,8 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
   fm.dtab = dt;
   fm.ext[0] = fm.ext[1] = fm.ext[2] = 0;
   fm.stacked = 1u;
+  fm.pre = nullptr;
+  fm.npre = 0u;
   int4* hits = nullptr;
   bool active = false;
   uint32_t ray = 0;
@@ -645,8 +671,9 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
                                                             uint32_t* __restrict__ nsteps) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
-  const Fmt fm = fmt_of(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
@@ -675,7 +702,10 @@ int g_cu_count = -1;
 
 }  // namespace
 
-size_t stack_lds_bytes(const DevFormat& F) { return (size_t)(F.nslots ? F.nslots : 1) * BLOCK * sizeof(uint2); }
+// Dynamic LDS of a single-volume trace kernel: the node stack, then the staged prefix.
+size_t stack_lds_bytes(const DevFormat& F) {
+  return (size_t)(F.nslots ? F.nslots : 1) * BLOCK * sizeof(uint2) + (size_t)F.lds_words * 4u;
+}
 
 #define HVF_FAMILY_SWITCH(family, LAUNCH) \
   switch (family) {                          \

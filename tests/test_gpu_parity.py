@@ -93,7 +93,9 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(persistent=1, refill=1, inner=1), dict(persistent=1, refill=16, inner=8),
              dict(persistent=1, refill=8, inner=4, blocks_per_cu=1), dict(persistent=1, refill=32, inner=16, blocks_per_cu=2),
              dict(persistent=1, refill=64, inner=64), dict(sort=1, sort_bits=0), dict(sort=1, sort_bits=4),
-             dict(sort=1, sort_bits=9)]
+             dict(sort=1, sort_bits=9), dict(lds_depths=1), dict(lds_depths=2), dict(lds_depths=16),
+             dict(lds_depths=3, persistent=1, refill=16, inner=8), dict(lds_depths=2, stack_depth=2),
+             dict(lds_depths=2, sort=1, sort_bits=4)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
@@ -110,6 +112,14 @@ def test_schedules_give_identical_results(H, sd):
         v = H.Volume(spec, codes)
         d = torch.from_numpy(rays).cuda()
         plain = v.trace(d).cpu().numpy()
+        info = v.info()
+        k = sd.get("lds_depths", 0)
+        staged = 0 if k == 0 else (info["depth_offset"][k] if k < info["num_depths"] else info["num_words"] & ~3)
+        if staged > 8192:
+            with pytest.raises(H.HvfError) as e:  # the prefix does not fit the LDS limit
+                v.trace(d, sched=sc)
+            assert e.value.name == "HVF_E_INPUT"
+            continue
         got = v.trace(d, sched=sc)
         torch.cuda.synchronize()
         got = got.cpu().numpy()
