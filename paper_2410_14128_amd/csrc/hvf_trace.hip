@@ -129,11 +129,18 @@ struct Counting {
   }
 };
 
-__device__ __forceinline__ uint2 ld2(const uint32_t* buf, uint32_t ix) {
-  return *reinterpret_cast<const uint2*>(buf + ix);
+// Format words are read through explicitly global pointers (and the staged prefix through
+// explicitly LDS ones), so the compiler emits global_load / ds_read and never merges the
+// two into a generic (flat) access.
+typedef const __attribute__((address_space(1))) uint32_t gword;
+typedef const __attribute__((address_space(3))) uint32_t lword;
+__device__ __forceinline__ gword* as_global(const uint32_t* p) { return (gword*)p; }
+__device__ __forceinline__ lword* as_lds(const uint32_t* p) { return (lword*)p; }
+__device__ __forceinline__ uint2 ld2(gword* buf, uint32_t ix) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) uint2*>(buf + ix);
 }
-__device__ __forceinline__ uint4 ld4(const uint32_t* buf, uint32_t ix) {
-  return *reinterpret_cast<const uint4*>(buf + ix);
+__device__ __forceinline__ uint4 ld4(gword* buf, uint32_t ix) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) uint4*>(buf + ix);
 }
 
 enum : int { RUN = 0, DONE = 1 };
@@ -143,19 +150,24 @@ enum : int { RUN = 0, DONE = 1 };
 // in the batched kernel. The first npre words of the buffer (the top depths: nodes are
 // stored depth by depth) may be staged in LDS at pre; reads below npre go there.
 struct Fmt {
-  const uint32_t* buf;
+  gword* buf;
   uint64_t pop_lut;
   const uint32_t* dtab;
   int ext[3];
   uint32_t stacked;  // depths with a node-stack slot
-  const uint32_t* pre;
+  lword* pre;
   uint32_t npre;
-  __device__ __forceinline__ uint32_t w1(uint32_t ix) const { return ix < npre ? pre[ix] : buf[ix]; }
+  __device__ __forceinline__ uint32_t w1(uint32_t ix) const {
+    if (ix < npre) return pre[ix];
+    return buf[ix];
+  }
   __device__ __forceinline__ uint2 w2(uint32_t ix) const {
-    return ix + 2u <= npre ? make_uint2(pre[ix], pre[ix + 1u]) : ld2(buf, ix);
+    if (ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
+    return ld2(buf, ix);
   }
   __device__ __forceinline__ uint4 w4(uint32_t ix) const {
-    return ix + 4u <= npre ? make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]) : ld4(buf, ix);
+    if (ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
+    return ld4(buf, ix);
   }
 };
 
@@ -164,9 +176,9 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t stacked, int d) { return __
 
 __device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab, const uint32_t* pre) {
   Fmt f;
-  f.pre = pre;
+  f.pre = as_lds(pre);
   f.npre = pre ? F.lds_words : 0u;
-  f.buf = F.buf;
+  f.buf = as_global(F.buf);
   f.pop_lut = F.pop_lut;
   f.dtab = dtab;
   f.ext[0] = F.ext[0];
@@ -632,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
             else hi = mid;
           }
           const BatchItem& it = items[lo];
-          fm.buf = it.buf;
+          fm.buf = as_global(it.buf);
           fm.pop_lut = it.pop_lut;
           fm.dtab = dt + lo * HVF_MAX_DEPTH;
           fm.ext[0] = it.ext[0];
