@@ -136,11 +136,15 @@ typedef const __attribute__((address_space(1))) uint32_t gword;
 typedef const __attribute__((address_space(3))) uint32_t lword;
 __device__ __forceinline__ gword* as_global(const uint32_t* p) { return (gword*)p; }
 __device__ __forceinline__ lword* as_lds(const uint32_t* p) { return (lword*)p; }
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint2 ld2(gword* buf, uint32_t ix) {
-  return *reinterpret_cast<const __attribute__((address_space(1))) uint2*>(buf + ix);
+  const u32x2 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x2*>(buf + ix);
+  return make_uint2(v.x, v.y);
 }
 __device__ __forceinline__ uint4 ld4(gword* buf, uint32_t ix) {
-  return *reinterpret_cast<const __attribute__((address_space(1))) uint4*>(buf + ix);
+  const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(buf + ix);
+  return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 enum : int { RUN = 0, DONE = 1 };
