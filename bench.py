@@ -71,10 +71,10 @@ def byte_model(vol, rays_sample, cap=4096):
             float(cnt.double().mean().item()), over, hits)
 
 
-def traffic_from_profile(name: str):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
-    reading for a plain 1 GiB copy) from the committed rocprofv3 PMC summary, or None when
-    absent or taken with a different kernel source."""
+def traffic_from_profile(name: str, kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by the same
+    counter's reading for a plain 1 GiB copy) from the committed rocprofv3 PMC summary, or
+    None when absent, taken for another kernel or with a different kernel source."""
     p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(p):
         return None
@@ -85,7 +85,9 @@ def traffic_from_profile(name: str):
     if d.get("kernel_hash") != kernel_source_hash():
         return None
     w = d.get("workloads", {}).get(name)
-    return None if w is None else round(float(w["bytes_per_launch"]))
+    if w is None or w.get("kernel") != kernel:
+        return None
+    return round(float(w["bytes_per_launch"]))
 
 
 def time_launches(fn_list, steps, warmup):
@@ -132,9 +134,9 @@ def run_surface512(args, torch, H, W, C):
     for v in vols:
         for j in range(len(views)):
             fns.append(lambda v=v, j=j: v.trace(d_views[j], hits[j]))
-    # Untuned reference pass (one lane per ray), then autotune each format on a held-out
-    # view (a fifth seeded camera at 960x540) and time the tuned schedules.
-    ms_plain, per_plain = time_launches(fns, args.steps, args.warmup)
+    # Autotune each format on a held-out view (a fifth seeded camera at 960x540), then time
+    # the tuned schedules: the timed region. The untuned comparison (--untuned) runs after
+    # it, so a profile of the timed kernels is not mixed with it.
     tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"], 960, 540)).cuda()
     scheds = []
     for v in vols:
@@ -143,55 +145,78 @@ def run_surface512(args, torch, H, W, C):
         else:
             scheds.append(H.schedule_dict(v.autotune(tune)))
     del tune
-    log(f"[bench] surface-512: {len(fns)} launches per step; warmup {args.warmup}, timing {args.steps} steps; "
-        f"untuned {ms_plain:.2f} ms/step")
+    log(f"[bench] surface-512: {len(fns)} launches per step; warmup {args.warmup}, timing {args.steps} steps")
     ms, per = time_launches(fns, args.steps, args.warmup)
     rays_per_step = sum(len(r) for r in views) * len(vols)
     value = rays_per_step / (ms * 1e-3) / 1e6
     log(f"[bench] surface-512: {ms:.2f} ms/step, {value:.1f} Mrays/s")
-    # Byte model per format on a seeded sample of each view's pixels.
+    per_plain = None
+    if args.untuned:
+        plain = H.schedule()
+        fns_plain = [lambda v=v, j=j: v.trace(d_views[j], hits[j], sched=plain) for v in vols for j in range(len(views))]
+        _, per_plain = time_launches(fns_plain, args.steps, args.warmup)
+    # Byte model per format and view on a seeded sample of each view's pixels.
     rng = np.random.default_rng(12345)
     sample_idx = [np.sort(rng.choice(len(r), size=min(args.sample, len(r)), replace=False)) for r in views]
     per_format = []
-    alg_bytes = 0.0
+    launch_bytes = []  # algorithmic bytes of each timed launch (format-major, like fns)
+    kernels = []       # trace kernel of each timed launch
     for fi, (spec, v) in enumerate(zip(cfg["specs"], vols)):
         info = v.info()
         bw, bs, loads, over = [], [], [], 0
         for j, r in enumerate(views):
             if args.sample <= 0:
                 bw.append(float("nan")), bs.append(float("nan")), loads.append(float("nan"))
-                continue
-            smp = torch.from_numpy(r[sample_idx[j]]).cuda()
-            w_, s_, l_, o_, _ = byte_model(v, smp)
-            bw.append(w_)
-            bs.append(s_)
-            loads.append(l_)
-            over += o_
+            else:
+                smp = torch.from_numpy(r[sample_idx[j]]).cuda()
+                w_, s_, l_, o_, _ = byte_model(v, smp)
+                bw.append(w_)
+                bs.append(s_)
+                loads.append(l_)
+                over += o_
+            launch_bytes.append(bs[-1] * len(r))
+            kernels.append(H.kernel_name(info, scheds[fi]))
         launch_ms = per[fi * len(views):(fi + 1) * len(views)]
         nrays = sum(len(r) for r in views)
-        fmt_bytes = float(np.mean(bs)) * nrays
-        alg_bytes += fmt_bytes
         fmt_ms = float(np.sum(launch_ms))
-        plain_ms = float(np.sum(per_plain[fi * len(views):(fi + 1) * len(views)]))
         per_format.append({
             "format": spec, "format_bytes": info["bytes"], "mrays_s": nrays / (fmt_ms * 1e-3) / 1e6,
-            "mrays_s_untuned": nrays / (plain_ms * 1e-3) / 1e6, "schedule": scheds[fi],
+            "schedule": scheds[fi], "kernel": kernels[-1],
             "ms": fmt_ms, "B_ray_sector": round(float(np.mean(bs)), 1), "B_ray_word": round(float(np.mean(bw)), 1),
             "loads_per_ray": round(float(np.mean(loads)), 1), "log_overflow_rays": over,
             "roof_mrays_s": HBM_PEAK_GBS * 1e9 / float(np.mean(bs)) / 1e6,
         })
+        if per_plain is not None:
+            plain_ms = float(np.sum(per_plain[fi * len(views):(fi + 1) * len(views)]))
+            per_format[-1]["mrays_s_untuned"] = nrays / (plain_ms * 1e-3) / 1e6
         per_format[-1]["frac_roofline"] = per_format[-1]["mrays_s"] / per_format[-1]["roof_mrays_s"]
-        log(f"[bench]   {spec:42s} {per_format[-1]['mrays_s']:8.1f} Mrays/s (untuned "
-            f"{per_format[-1]['mrays_s_untuned']:7.1f}, {scheds[fi]})  B_ray {np.mean(bs):7.1f} B "
-            f"({per_format[-1]['frac_roofline']:.1%} of HBM roof)  size {info['bytes'] / 2 ** 20:.1f} MiB")
-    launch_total_ms = float(np.sum(per))
-    achieved = alg_bytes / (launch_total_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile("surface-512")
+        log(f"[bench]   {spec:42s} {per_format[-1]['mrays_s']:8.1f} Mrays/s ({scheds[fi]}, {kernels[-1]})  "
+            f"B_ray {np.mean(bs):7.1f} B ({per_format[-1]['frac_roofline']:.1%} of HBM roof)  "
+            f"size {info['bytes'] / 2 ** 20:.1f} MiB")
+    # Roofline of the dominant kernel: the trace kernel with the largest share of the step.
+    # achieved = its algorithmic bytes per launch / its mean launch time (HIP events on the
+    # launch stream); both are means over its launches in one step.
+    tot = {}
+    for k, t in zip(kernels, per):
+        tot[k] = tot.get(k, 0.0) + t
+    dom = max(tot, key=tot.get)
+    idx = [i for i, k in enumerate(kernels) if k == dom]
+    avg_ms = float(np.mean([per[i] for i in idx]))
+    bytes_launch = float(np.mean([launch_bytes[i] for i in idx]))
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    all_achieved = float(np.sum(launch_bytes)) / (float(np.sum(per)) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic}
+                "traffic": traffic_from_profile("surface-512", dom),
+                "kernel": dom, "launches_per_step": len(idx), "share_of_step": round(tot[dom] / float(np.sum(per)), 3),
+                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": round(bytes_launch),
+                "grid_threads": len(views[0]),
+                "formats": sorted({cfg["specs"][i // len(views)] for i in idx}),
+                "all_launches_achieved": round(all_achieved, 1)}
+    log(f"[bench] surface-512 dominant kernel {dom}: {len(idx)} launches/step, {avg_ms * 1e3:.1f} us each, "
+        f"{achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%}); all launches {all_achieved:.0f} GB/s")
     return {
-        "value": value, "ms": ms, "ms_untuned": ms_plain, "rays_per_step": rays_per_step, "roofline": roofline,
+        "value": value, "ms": ms, "rays_per_step": rays_per_step, "roofline": roofline,
         "per_format": per_format,
         "codes": codes, "views": views, "sample_idx": sample_idx, "occupancy": len(codes) / n ** 3,
     }
@@ -253,12 +278,13 @@ def run_surface2048(args, torch, H, W, C):
         d_b = torch.from_numpy(b).cuda()
         hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
         plain = H.schedule()
-        ms_p0, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
-        ms_b0, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
         sched_p = H.schedule_dict(v.autotune(d_held)) if not args.no_tune else H.schedule_dict(plain)
         ms_p, _ = time_launches([lambda: v.trace(d_prim, h)], args.steps, args.warmup)
         sched_b = H.schedule_dict(v.autotune(torch.from_numpy(bh).cuda())) if not args.no_tune else sched_p
         ms_b, _ = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
+        # untuned comparison after the timed launches (a profile of those stays unmixed)
+        ms_p0, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
+        ms_b0, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
         rng = np.random.default_rng(7)
         if args.sample > 0:
             sp = torch.from_numpy(prim[rng.choice(len(prim), min(args.sample, len(prim)), replace=False)]).cuda()
@@ -267,12 +293,15 @@ def run_surface2048(args, torch, H, W, C):
             wb, bb, lb, _, _ = byte_model(v, sb)
         else:
             wp = bp = lp = wb = bb = lb = float("nan")
-        rec = {"format": spec, "format_bytes": v.info()["bytes"],
+        info = v.info()
+        rec = {"format": spec, "format_bytes": info["bytes"],
                "primary": {"rays": len(prim), "ms": ms_p, "mrays_s": len(prim) / ms_p / 1e3, "B_ray_sector": bp,
                            "B_ray_word": wp, "loads_per_ray": lp, "schedule": sched_p,
+                           "kernel": H.kernel_name(info, sched_p), "avg_launch_us": ms_p * 1e3,
                            "mrays_s_untuned": len(prim) / ms_p0 / 1e3},
                "incoherent": {"rays": len(b), "ms": ms_b, "mrays_s": len(b) / ms_b / 1e3, "B_ray_sector": bb,
                               "B_ray_word": wb, "loads_per_ray": lb, "schedule": sched_b,
+                              "kernel": H.kernel_name(info, sched_b), "avg_launch_us": ms_b * 1e3,
                               "mrays_s_untuned": len(b) / ms_b0 / 1e3}}
         for k in ("primary", "incoherent"):
             r = rec[k]
@@ -469,6 +498,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2048", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
+    ap.add_argument("--untuned", action="store_true", help="also time the 512^3 formats with the plain schedule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (PMC calibration of FETCH/WRITE_SIZE)")
     ap.add_argument("--no-batched", action="store_true")

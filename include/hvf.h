@@ -79,6 +79,8 @@ typedef struct hvf_info {
   uint64_t depth_offset[HVF_MAX_DEPTH]; /* first word of each depth: depths are stored in order */
   uint64_t num_voxels;                  /* occupied voxels */
   int32_t level_maxdist[HVF_MAX_LEVELS]; /* DF levels: the maximum stored distance M; else 0 */
+  uint32_t kernel_family;               /* template argument of the trace kernels this volume
+                                           launches (node/header kinds compiled in) */
 } hvf_info;
 
 /* How a trace is scheduled on the device. Results never depend on it.

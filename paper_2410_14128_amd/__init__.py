@@ -46,6 +46,7 @@ class hvf_info(ctypes.Structure):
         ("depth_offset", ctypes.c_uint64 * HVF_MAX_DEPTH),
         ("num_voxels", ctypes.c_uint64),
         ("level_maxdist", ctypes.c_int32 * HVF_MAX_LEVELS),
+        ("kernel_family", ctypes.c_uint32),
     ]
 
 
@@ -59,6 +60,14 @@ def schedule(persistent: int = 0, refill: int = 16, inner: int = 8, sort: int = 
              blocks_per_cu: int = 0, stack_depth: int = 0, lds_depths: int = 0) -> hvf_schedule:
     """A device schedule for a trace (results never depend on it)."""
     return hvf_schedule(persistent, refill, inner, sort, sort_bits, blocks_per_cu, stack_depth, lds_depths)
+
+
+def kernel_name(info: dict, sched: dict) -> str:
+    """Demangled-name stem of the trace kernel a volume launches under a schedule."""
+    if sched.get("sort"):
+        return "trace_indexed_kernel"
+    kind = "trace_persistent_kernel" if sched.get("persistent") else "trace_kernel"
+    return f"{kind}<{info['kernel_family']}u>"
 
 
 def schedule_dict(s: hvf_schedule) -> dict:
@@ -230,6 +239,7 @@ class Volume:
             "depth_offset": [int(I.depth_offset[d]) for d in range(nd)],
             "num_voxels": int(I.num_voxels),
             "level_maxdist": [int(I.level_maxdist[k]) for k in range(n)],
+            "kernel_family": int(I.kernel_family),
         }
 
     def words(self) -> np.ndarray:

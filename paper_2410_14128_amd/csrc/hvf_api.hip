@@ -299,6 +299,7 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
     I.depth_offset[d] = d < v->built.depth_offset.size() ? v->built.depth_offset[d] : 0;
   }
   I.num_voxels = v->built.nvox;
+  I.kernel_family = hvf::FAMILIES[hvf::family_of(v->layout)];
   *out = I;
   return HVF_OK;
 }
