@@ -205,14 +205,16 @@ def run_surface512(args, torch, H, W, C):
     bytes_launch = float(np.mean([launch_bytes[i] for i in idx]))
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     all_achieved = float(np.sum(launch_bytes)) / (float(np.sum(per)) * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
+    fin = bool(np.isfinite(achieved))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if fin else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if fin else None,
                 "traffic": traffic_from_profile("surface-512", dom),
                 "kernel": dom, "launches_per_step": len(idx), "share_of_step": round(tot[dom] / float(np.sum(per)), 3),
-                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": round(bytes_launch),
+                "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": round(bytes_launch) if np.isfinite(bytes_launch) else None,
                 "grid_threads": len(views[0]),
                 "formats": sorted({cfg["specs"][i // len(views)] for i in idx}),
-                "all_launches_achieved": round(all_achieved, 1)}
+                "all_launches_achieved": round(all_achieved, 1) if np.isfinite(all_achieved) else None}
     log(f"[bench] surface-512 dominant kernel {dom}: {len(idx)} launches/step, {avg_ms * 1e3:.1f} us each, "
         f"{achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%}); all launches {all_achieved:.0f} GB/s")
     return {

@@ -1,6 +1,7 @@
 // C-ABI entry points: build, upload, trace, info, save/load, errors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -18,8 +19,8 @@ hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
 hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
-hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule& sc,
-                        uint32_t* d_counter, hipStream_t s);
+hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                        const hvf_schedule& sc, hipStream_t s);
 }
 
 namespace {
@@ -131,8 +132,10 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
     return fail(HVF_E_INPUT, "the top " + std::to_string(sc.lds_depths) + " depths exceed the LDS prefix limit of " +
                                  std::to_string(hvf::HVF_LDS_PREFIX_MAX_WORDS) + " words");
   hipStream_t s = (hipStream_t)stream;
+  const int family = hvf::family_of(v->layout);
+  if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   uint32_t* counter = nullptr;
-  if (sc.persistent || sc.sort) {
+  if (sc.persistent) {
     if (!v->dcounters) {
       hipError_t e = hipMalloc(&v->dcounters, HVF_NUM_COUNTERS * 2 * sizeof(uint32_t));
       if (e != hipSuccess) {
@@ -142,8 +145,6 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
     }
     counter = v->dcounters + 2 * (v->counter_next++ % HVF_NUM_COUNTERS);
   }
-  if (sc.sort) return hvf::trace_sorted(F, d_rays, n, d_hits, sc, counter, s);
-  const int family = hvf::family_of(v->layout);
   if (!sc.persistent) return hvf::launch_trace(F, family, d_rays, n, d_hits, s);
   unsigned grid = 0;
   st = hvf::persistent_grid(F, sc.blocks_per_cu, &grid);
@@ -167,52 +168,71 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
     for (int refill : {8, 32})
       for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, bpc, 0, 0});
   for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, 0, 0, 0});
+  hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return fail(HVF_E_DEVICE, "hipEventCreate failed");
   }
-  float best_ms = 1e30f;
-  hvf_schedule best = cand[0];
   hvf_status st = HVF_OK;
-  auto time_one = [&](const hvf_schedule& c) {
-    st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);  // warm-up (uploads on first use)
-    if (st != HVF_OK) return;
+  // Mean time of `reps` launches of schedule c after one warm-up launch (uploads on first use).
+  auto time_one = [&](const hvf_schedule& c, int reps) -> float {
+    st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);
+    if (st != HVF_OK) return 0.0f;
     float tot = 0.0f;
-    const int reps = 3;
     bool ok = hipEventRecord(e0, s) == hipSuccess;
     for (int r = 0; r < reps && st == HVF_OK; ++r) st = hvf_trace_sched(v, d_sample, n, d_hits, &c, stream);
     ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(&tot, e0, e1) == hipSuccess;
-    if (st != HVF_OK) return;
-    if (!ok) {
-      st = fail(HVF_E_DEVICE, "event timing failed during autotune");
-      return;
-    }
-    if (tot / reps < best_ms) {
-      best_ms = tot / reps;
-      best = c;
-    }
+    if (st == HVF_OK && !ok) st = fail(HVF_E_DEVICE, "event timing failed during autotune");
+    return tot / (float)reps;
   };
-  for (const hvf_schedule& c : cand) {
-    time_one(c);
-    if (st != HVF_OK) break;
-  }
-  // Second round: stage the top depths of the buffer in LDS under the best schedule, for
-  // the three deepest prefixes that fit (distinct sizes only).
+  // Round one: every candidate once. Round two: the default, the best three of round one
+  // and the best one with the deepest LDS prefixes that fit, re-timed in interleaved
+  // passes; the lowest median wins, and it replaces the default only when it is at least
+  // 3% faster (timing noise must not pick a schedule).
+  std::vector<std::pair<float, size_t>> r1;
+  for (size_t i = 0; i < cand.size() && st == HVF_OK; ++i) r1.push_back({time_one(cand[i], 3), i});
   if (st == HVF_OK) {
-    const hvf_schedule base = best;
+    std::sort(r1.begin(), r1.end());
+    std::vector<hvf_schedule> fin;
+    fin.push_back(cand[0]);
+    for (size_t k = 0; k < r1.size() && fin.size() < 4; ++k)
+      if (r1[k].second != 0) fin.push_back(cand[r1[k].second]);
+    const hvf_schedule top = cand[r1[0].second];
     uint32_t last = 0;
     int tried = 0;
-    for (int k = nd; k >= 1 && tried < 3 && st == HVF_OK; --k) {
+    for (int k = nd; k >= 1 && tried < 3; --k) {
       uint32_t w = 0;
       if (!hvf::lds_prefix_words(v->layout, v->built, k, &w) || w == 0 || w == last) continue;
       last = w;
       ++tried;
-      hvf_schedule c = base;
+      hvf_schedule c = top;
       c.lds_depths = k;
-      time_one(c);
+      fin.push_back(c);
+    }
+    const int passes = 3;
+    std::vector<std::vector<float>> t(fin.size());
+    for (int pass = 0; pass < passes && st == HVF_OK; ++pass)
+      for (size_t i = 0; i < fin.size() && st == HVF_OK; ++i) t[i].push_back(time_one(fin[i], 3));
+    if (st == HVF_OK) {
+      auto median = [](std::vector<float> x) {
+        std::sort(x.begin(), x.end());
+        return x[x.size() / 2];
+      };
+      size_t bi = 0;
+      float bm = median(t[0]);
+      const float base_ms = bm;
+      for (size_t i = 1; i < fin.size(); ++i) {
+        const float m = median(t[i]);
+        if (m < bm) {
+          bm = m;
+          bi = i;
+        }
+      }
+      if (bm > 0.97f * base_ms) bi = 0;
+      best = fin[bi];
     }
   }
   (void)hipEventDestroy(e0);

@@ -289,6 +289,12 @@ int family_of(const Layout& L) {
   return NUM_FAMILIES - 1;
 }
 
+bool has_df(const Layout& L) {
+  for (const DepthInfo& d : L.d)
+    if (d.nk == NK_DF_PTR || d.nk == NK_DF_BLOCKS) return true;
+  return false;
+}
+
 DevFormat make_devformat(const Layout& L, const Spec& s, const uint32_t* dbuf) {
   DevFormat f{};
   f.buf = dbuf;

@@ -144,12 +144,15 @@ constexpr uint32_t FAM_RAW_OCTREE = FAM_OCTREE | fam_nk(NK_RAW_PTR) | fam_hk(HK_
 constexpr uint32_t FAM_DF_BRICK = FAM_RAW_BRICK | fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS);
 constexpr uint32_t FAM_DF_OCTREE = FAM_RAW_OCTREE | fam_nk(NK_DF_PTR);
 constexpr uint32_t FAM_ALL = 0x1FFu | (0x1Fu << 16);
-constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE,
-                                 FAM_RAW_OCTREE, FAM_DF_BRICK, FAM_DF_OCTREE, FAM_ALL};
-constexpr int NUM_FAMILIES = 8;
+constexpr uint32_t FAM_NODF = FAM_ALL & ~(fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS));
+constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE,
+                                 FAM_DF_BRICK,  FAM_DF_OCTREE, FAM_NODF,      FAM_ALL};
+constexpr int NUM_FAMILIES = 9;
 
 // Index into FAMILIES of the first family covering the layout.
 int family_of(const Layout& L);
+// Whether the layout has a distance-field depth.
+bool has_df(const Layout& L);
 
 // One batch of the batched launch: a volume and its ray / hit arrays. Rays of all
 // batches form one index space; batch b owns indices [first, first + n).

@@ -368,67 +368,95 @@ struct Walk {
       }
     }
     // Advance to the next cell of side 2^cs: the least far-plane time; every axis that
-    // crosses at that time steps.
+    // crosses at that time steps. While the walk stays in the same node and registers show
+    // the new cell to be empty (a voxel bit of the block mask, an octree valid bit, or a DF
+    // cell within the reach), it keeps advancing here instead of taking a full step per
+    // empty cell.
+    const bool regtest = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || nk >= NK_SVO_INNER ||
+                         ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS));
     const int stepv = 1 << cs;
-    float tf[3];
+    for (;;) {
+      float tf[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
-      tf[a] = R.is_par(a) ? INFINITY : tt;
-    }
-    const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
-    if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
-    t = m;
-    uint32_t dd = 0u;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
-      const bool mv = (tf[a] == m);
-      dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
-      p[a] = mv ? np : p[a];
-    }
-    // Pop to the deepest node that still contains the new cell (the root always does).
-    if (d > 0) {
-      const int hb = 31 - __clz(dd);
-      const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
-      if (nd != d) {
-        // Restore the deepest stacked ancestor r <= nd, then descend again along p (every
-        // ancestor of the current cell exists, so each child on the way is occupied).
-        const int r = 31 - __clz(F.stacked & ((2u << nd) - 1u));
-        const uint2 sv = stk[slot_of(F.stacked, r) * BLOCK];
-        base = sv.x;
-        valid = sv.y;
-        info = dtab[r];
-        for (int k = r; k < nd; ++k) {
-          const uint32_t knk = di_nk(info), kl = cell_lin(info);
-          uint32_t child = 0u;
-          uint2 cm = make_uint2(0u, 0u);
-          if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
-            child = F.w1(base + kl);  // an ancestor cell: non-empty, so a plain pointer
-            mem.note(base + kl, 1);
-          } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
-            cm = F.w2(base + 2u * kl);
-            mem.note(base + 2u * kl, 2);
-          } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
-            cm = F.w2(base + 4u * kl);
-            mem.note(base + 4u * kl, 2);
-          } else {
-            octree_child<FAM>(F, knk, kl, base, valid, child, cm, mem);
-          }
-          info = dtab[k + 1];
-          const uint2 h = enter<FAM>(F, info, child, cm, mem);
-          base = h.x;
-          valid = h.y;
-        }
-        d = nd;
-        reach = 0;
-        const int mask = ~((1 << di_cs(info)) - 1);
-        p[0] &= mask;
-        p[1] &= mask;
-        p[2] &= mask;
+      for (int a = 0; a < 3; ++a) {
+        const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
+        tf[a] = R.is_par(a) ? INFINITY : tt;
       }
+      const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
+      if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
+      t = m;
+      uint32_t dd = 0u;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
+        const bool mv = (tf[a] == m);
+        dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
+        p[a] = mv ? np : p[a];
+      }
+      // Pop to the deepest node that still contains the new cell (the root always does).
+      if (d > 0) {
+        const int hb = 31 - __clz(dd);
+        const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
+        if (nd != d) {
+          pop_to<FAM>(F, stk, nd, mem);
+          return RUN;
+        }
+      }
+      if (!regtest) return RUN;
+      if (++steps > MAX_STEPS) {
+        out = make_int4(-2, -2, -2, 0);
+        return DONE;
+      }
+      bool empty;
+      if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
+        empty = ((uint32_t)(abs(p[0] - a[0]) + abs(p[1] - a[1]) + abs(p[2] - a[2])) >> cs) < reach;
+      } else {
+        const uint32_t l2 = cell_lin(info);
+        const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && l2 < 32u) ? base : valid;
+        empty = ((word >> (l2 & 31u)) & 1u) == 0u;
+      }
+      if (!empty) return RUN;
     }
-    return RUN;
+  }
+
+  // Leave the current node for its ancestor at depth nd < d that contains the new cell:
+  // restore the deepest stacked ancestor r <= nd, then descend again along p (every
+  // ancestor of the current cell exists, so each child on the way is occupied).
+  template <uint32_t FAM, class Mem>
+  __device__ __forceinline__ void pop_to(const Fmt& F, uint2* stk, int nd, Mem& mem) {
+    const uint32_t* dtab = F.dtab;
+    const int r = 31 - __clz(F.stacked & ((2u << nd) - 1u));
+    const uint2 sv = stk[slot_of(F.stacked, r) * BLOCK];
+    base = sv.x;
+    valid = sv.y;
+    info = dtab[r];
+    for (int k = r; k < nd; ++k) {
+      const uint32_t knk = di_nk(info), kl = cell_lin(info);
+      uint32_t child = 0u;
+      uint2 cm = make_uint2(0u, 0u);
+      if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
+        child = F.w1(base + kl);  // an ancestor cell: non-empty, so a plain pointer
+        mem.note(base + kl, 1);
+      } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
+        cm = F.w2(base + 2u * kl);
+        mem.note(base + 2u * kl, 2);
+      } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
+        cm = F.w2(base + 4u * kl);
+        mem.note(base + 4u * kl, 2);
+      } else {
+        octree_child<FAM>(F, knk, kl, base, valid, child, cm, mem);
+      }
+      info = dtab[k + 1];
+      const uint2 h = enter<FAM>(F, info, child, cm, mem);
+      base = h.x;
+      valid = h.y;
+    }
+    d = nd;
+    reach = 0;
+    const int mask = ~((1 << di_cs(info)) - 1);
+    p[0] &= mask;
+    p[1] &= mask;
+    p[2] &= mask;
   }
 };
 
@@ -526,6 +554,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
 }
 
 // One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
+template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                               int4* __restrict__ hits, uint32_t n,
                                                               const uint32_t* __restrict__ perm,
@@ -542,8 +571,8 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   int4 out = miss_hit();
   Walk w;
   Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN)
-    while (w.template step<FAM_ALL>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
+    while (w.template step<FAM>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   hits[i] = out;
 }
@@ -599,6 +628,7 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, size_t n) 
 // its batch by binary search over the batch start table, and walks that batch's volume.
 // Per-depth descriptor tables of every batch and the start table live in LDS.
 // LDS layout: dtab[items * 16] | start[items + 1] | stack[max_depth * BLOCK] (uint2).
+template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __restrict__ items,
                                                             const uint32_t* __restrict__ dinfo_all, uint32_t nitems,
                                                             uint32_t total, uint32_t* __restrict__ counter,
@@ -660,7 +690,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
           const float4* rays = reinterpret_cast<const float4*>(it.rays);
           const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
           out = miss_hit();
-          active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN;
+          active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
           if (!active) hits[ray] = out;
         }
       }
@@ -668,7 +698,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
     if (drained && __ballot(active) == 0ull) break;
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
-        if (w.template step<FAM_ALL>(fm, stk, out, mem) == DONE) {
+        if (w.template step<FAM>(fm, stk, out, mem) == DONE) {
           hits[ray] = out;
           active = false;
           break;
@@ -732,6 +762,7 @@ size_t stack_lds_bytes(const DevFormat& F) {
     case 4: LAUNCH(FAM_RAW_OCTREE); break;   \
     case 5: LAUNCH(FAM_DF_BRICK); break;     \
     case 6: LAUNCH(FAM_DF_OCTREE); break;    \
+    case 7: LAUNCH(FAM_NODF); break;         \
     default: LAUNCH(FAM_ALL); break;         \
   }
 
@@ -795,7 +826,7 @@ size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
   return words * 4 + (size_t)max_depth * BLOCK * sizeof(uint2);
 }
 
-hvf_status batch_grid(uint32_t nitems, int max_depth, int blocks_per_cu, unsigned* grid) {
+hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu, unsigned* grid) {
   if (g_cu_count < 0) {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -806,8 +837,12 @@ hvf_status batch_grid(uint32_t nitems, int max_depth, int blocks_per_cu, unsigne
     g_cu_count = prop.multiProcessorCount;
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel, BLOCK,
-                                                   batch_lds_bytes(nitems, max_depth)) != hipSuccess ||
+  const hipError_t oe =
+      df ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ALL>, BLOCK,
+                                                        batch_lds_bytes(nitems, max_depth))
+         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_NODF>, BLOCK,
+                                                        batch_lds_bytes(nitems, max_depth));
+  if (oe != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
@@ -816,13 +851,17 @@ hvf_status batch_grid(uint32_t nitems, int max_depth, int blocks_per_cu, unsigne
 }
 
 hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo, uint32_t nitems, uint32_t total,
-                              int max_depth, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
-                              hipStream_t s) {
+                              int max_depth, bool df, uint32_t* d_counter, uint32_t refill, uint32_t inner,
+                              unsigned grid, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, d_counter, 0u, (size_t)1);
   hvf_status st = launch_check("fill");
   if (st != HVF_OK) return st;
-  hipLaunchKernelGGL(trace_batch_kernel, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s, d_items,
-                     d_dinfo, nitems, total, d_counter, refill, inner);
+  if (df)
+    hipLaunchKernelGGL(trace_batch_kernel<FAM_ALL>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
+                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
+  else
+    hipLaunchKernelGGL(trace_batch_kernel<FAM_NODF>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
+                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
   return launch_check("batched trace");
 }
 
@@ -843,9 +882,8 @@ struct SortScratch {
 SortScratch g_sort;
 }  // namespace
 
-hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, const hvf_schedule& sc,
-                        uint32_t* d_counter, hipStream_t s) {
-  (void)d_counter;
+hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                        const hvf_schedule& sc, hipStream_t s) {
   if (n >= (1ull << 31)) {
     hvf_set_error("at most 2^31 - 1 rays per sorted call");
     return HVF_E_INPUT;
@@ -887,9 +925,13 @@ hvf_status trace_sorted(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf
     hvf_set_error("radix sort failed");
     return HVF_E_DEVICE;
   }
-  hipLaunchKernelGGL(trace_indexed_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
-                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, idx_out,
-                     key_out);
+  const float4* r = reinterpret_cast<const float4*>(d_rays);
+  int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_INDEXED(FAMV) \
+  hipLaunchKernelGGL(trace_indexed_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
+                     idx_out, key_out)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_INDEXED)
+#undef HVF_LAUNCH_INDEXED
   return launch_check("sorted trace");
 }
 

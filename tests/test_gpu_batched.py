@@ -32,6 +32,13 @@ def cases(H):
         d = torch.from_numpy(rays).cuda()
         ref = v.trace(d, sched=H.schedule())
         out.append((spec, k, codes, rays, v, d, ref))
+    # distance-field levels (the batch then runs the all-kinds kernel)
+    for spec, k in (("D(2,2,2,4) G(3) --whole-level-dedup", 5), ("D(3,3,3,6) D(3,3,3,6)", 6)):
+        codes = W.scene_shell(90 + k, k, 6, 2, 1.4)
+        rays = np.concatenate([W.random_rays(k, (1 << k,) * 3, 3000), W.camera_rays(k, 0, (1 << k,) * 3, 64, 48)])
+        v = H.Volume(spec, codes)
+        d = torch.from_numpy(rays).cuda()
+        out.append((spec, k, codes, rays, v, d, v.trace(d, sched=H.schedule())))
     # an empty volume and an empty ray batch
     v = H.Volume("G(3) R(2,2,2)", np.zeros(0, np.uint64))
     r = W.random_rays(1, (32,) * 3, 1000)
