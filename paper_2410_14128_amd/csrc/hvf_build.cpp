@@ -277,7 +277,10 @@ bool lds_prefix_words(const Layout& L, const Built& B, int lds_depths, uint32_t*
 }
 
 void set_stacked(DevFormat& F, uint32_t mask) {
-  F.stacked = mask;
+  // Every depth stacked is stored as all ones, which the kernels test for a uniform fast
+  // path (slot = depth).
+  const uint32_t all = (F.ndepth >= 32) ? 0xFFFFFFFFu : ((1u << F.ndepth) - 1u);
+  F.stacked = (mask == all) ? 0xFFFFFFFFu : mask;
   F.nslots = (uint32_t)__builtin_popcount(mask);
 }
 

@@ -96,7 +96,7 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
 // the depth a walk returns to when its position changes in bit h (node sides shrink
 // strictly with depth, and every depth below the root is cubic).
 // stacked: bit d set = depth d keeps a node-stack slot (slot index = number of stacked
-// depths above d). A pop to a depth without a slot restores the deepest stacked ancestor
+// depths above d); all ones when every depth does. A pop to a depth without a slot restores the deepest stacked ancestor
 // and descends again along the current cell position.
 // lds_words: leading buffer words each block stages in LDS (0 = none); a multiple of 4.
 struct DevFormat {

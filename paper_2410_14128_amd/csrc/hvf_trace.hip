@@ -161,19 +161,24 @@ struct Fmt {
   uint32_t stacked;  // depths with a node-stack slot
   lword* pre;
   uint32_t npre;
+  // npre is uniform across the launch: with no staged prefix the reads take a scalar
+  // branch straight to global memory, with no per-lane mask handling.
   __device__ __forceinline__ uint32_t w1(uint32_t ix) const {
-    if (ix < npre) return pre[ix];
+    if (npre != 0u && ix < npre) return pre[ix];
     return buf[ix];
   }
   __device__ __forceinline__ uint2 w2(uint32_t ix) const {
-    if (ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
+    if (npre != 0u && ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
     return ld2(buf, ix);
   }
   __device__ __forceinline__ uint4 w4(uint32_t ix) const {
-    if (ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
+    if (npre != 0u && ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
     return ld4(buf, ix);
   }
 };
+
+// Every depth stacked (the default): the slot of depth d is d.
+constexpr uint32_t ALL_STACKED = 0xFFFFFFFFu;
 
 // Stack slot of depth d: the number of stacked depths above it.
 __device__ __forceinline__ uint32_t slot_of(uint32_t stacked, int d) { return __popc(stacked & ((1u << d) - 1u)); }
@@ -342,7 +347,10 @@ struct Walk {
     const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL);
     if (occ && !fin) {
       if (nk >= NK_SVO_INNER) octree_child<FAM>(F, nk, lin, base, valid, child, cm, mem);
-      if ((F.stacked >> d) & 1u) stk[slot_of(F.stacked, d) * BLOCK] = make_uint2(base, valid);
+      if (F.stacked == ALL_STACKED)  // uniform: every depth has a slot, slot = depth
+        stk[d * BLOCK] = make_uint2(base, valid);
+      else if ((F.stacked >> d) & 1u)
+        stk[slot_of(F.stacked, d) * BLOCK] = make_uint2(base, valid);
       ++d;
       reach = 0;
       info = dtab[d];
@@ -352,71 +360,43 @@ struct Walk {
       refine3(R, p, cs, di_cs(info), t);
       return RUN;
     }
-    if (occ) {
-      // An occupied single voxel: report it if the ray really spends time in it.
-      float e = R.t0, x = R.t1;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const bool par = R.is_par(a), ng = R.is_neg(a);
-        const float tn = R.T(a, ng ? p[a] + 1 : p[a]), tx = R.T(a, ng ? p[a] : p[a] + 1);
-        e = fmax_fx(e, par ? -INFINITY : tn);
-        x = fmin_fx(x, par ? INFINITY : tx);
-      }
-      if (e < x) {
-        out = make_int4(p[0], p[1], p[2], __float_as_int(e));
-        return DONE;
-      }
-    }
-    // Advance to the next cell of side 2^cs: the least far-plane time; every axis that
-    // crosses at that time steps. While the walk stays in the same node and registers show
-    // the new cell to be empty (a voxel bit of the block mask, an octree valid bit, or a DF
-    // cell within the reach), it keeps advancing here instead of taking a full step per
-    // empty cell.
-    const bool regtest = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || nk >= NK_SVO_INNER ||
-                         ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS));
+    // Far-plane times of the current cell: the advance below needs them, and for an occupied
+    // voxel they decide the hit.
     const int stepv = 1 << cs;
-    for (;;) {
-      float tf[3];
+    float tf[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
-        tf[a] = R.is_par(a) ? INFINITY : tt;
-      }
-      const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
-      if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
-      t = m;
-      uint32_t dd = 0u;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
-        const bool mv = (tf[a] == m);
-        dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
-        p[a] = mv ? np : p[a];
-      }
-      // Pop to the deepest node that still contains the new cell (the root always does).
-      if (d > 0) {
-        const int hb = 31 - __clz(dd);
-        const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
-        if (nd != d) {
-          pop_to<FAM>(F, stk, nd, mem);
-          return RUN;
-        }
-      }
-      if (!regtest) return RUN;
-      if (++steps > MAX_STEPS) {
-        out = make_int4(-2, -2, -2, 0);
-        return DONE;
-      }
-      bool empty;
-      if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
-        empty = ((uint32_t)(abs(p[0] - a[0]) + abs(p[1] - a[1]) + abs(p[2] - a[2])) >> cs) < reach;
-      } else {
-        const uint32_t l2 = cell_lin(info);
-        const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && l2 < 32u) ? base : valid;
-        empty = ((word >> (l2 & 31u)) & 1u) == 0u;
-      }
-      if (!empty) return RUN;
+    for (int a = 0; a < 3; ++a) {
+      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
+      tf[a] = R.is_par(a) ? INFINITY : tt;
     }
+    const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
+    // An occupied single voxel. The walk's t is always the entry time of its current cell:
+    // the root cell is entered at t0, an advance enters the next cell at the crossing time
+    // of the plane between them, and a descent picks the child holding the ray at t, whose
+    // near planes are crossed no later than t. So the voxel's visit interval is
+    // [t, min(t1, m)) and t < t1 always holds: it is visited iff t < m, and its entry
+    // time is t itself.
+    if (occ && t < m) {
+      out = make_int4(p[0], p[1], p[2], __float_as_int(t));
+      return DONE;
+    }
+    if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
+    t = m;
+    uint32_t dd = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
+      const bool mv = (tf[a] == m);
+      dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
+      p[a] = mv ? np : p[a];
+    }
+    // Pop to the deepest node that still contains the new cell (the root always does).
+    if (d > 0) {
+      const int hb = 31 - __clz(dd);
+      const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
+      if (nd != d) pop_to<FAM>(F, stk, nd, mem);
+    }
+    return RUN;
   }
 
   // Leave the current node for its ancestor at depth nd < d that contains the new cell:
@@ -425,6 +405,19 @@ struct Walk {
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ void pop_to(const Fmt& F, uint2* stk, int nd, Mem& mem) {
     const uint32_t* dtab = F.dtab;
+    if (F.stacked == ALL_STACKED) {  // uniform: the ancestor's own slot holds it
+      const uint2 sv = stk[nd * BLOCK];
+      base = sv.x;
+      valid = sv.y;
+      info = dtab[nd];
+      d = nd;
+      reach = 0;
+      const int mask = ~((1 << di_cs(info)) - 1);
+      p[0] &= mask;
+      p[1] &= mask;
+      p[2] &= mask;
+      return;
+    }
     const int r = 31 - __clz(F.stacked & ((2u << nd) - 1u));
     const uint2 sv = stk[slot_of(F.stacked, r) * BLOCK];
     base = sv.x;
