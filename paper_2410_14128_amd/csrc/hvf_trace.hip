@@ -149,6 +149,9 @@ __device__ __forceinline__ uint4 ld4(gword* buf, uint32_t ix) {
 
 enum : int { RUN = 0, DONE = 1 };
 
+// Template flag of the trace kernels: the top depths are staged in LDS.
+constexpr uint32_t FAM_PRE = 1u << 31;
+
 // The format a lane walks: word buffer, pop table, per-axis extents and the per-depth
 // descriptor table (in LDS). Uniform across a launch for single-volume kernels; per lane
 // in the batched kernel. The first npre words of the buffer (the top depths: nodes are
@@ -161,18 +164,21 @@ struct Fmt {
   uint32_t stacked;  // depths with a node-stack slot
   lword* pre;
   uint32_t npre;
-  // npre is uniform across the launch: with no staged prefix the reads take a scalar
-  // branch straight to global memory, with no per-lane mask handling.
+  // Kernels are compiled twice, with and without a staged prefix (FAM_PRE), so reads in
+  // the common unstaged case carry no per-lane test.
+  template <uint32_t FAM>
   __device__ __forceinline__ uint32_t w1(uint32_t ix) const {
-    if (npre != 0u && ix < npre) return pre[ix];
+    if ((FAM & FAM_PRE) && ix < npre) return pre[ix];
     return buf[ix];
   }
+  template <uint32_t FAM>
   __device__ __forceinline__ uint2 w2(uint32_t ix) const {
-    if (npre != 0u && ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
+    if ((FAM & FAM_PRE) && ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
     return ld2(buf, ix);
   }
+  template <uint32_t FAM>
   __device__ __forceinline__ uint4 w4(uint32_t ix) const {
-    if (npre != 0u && ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
+    if ((FAM & FAM_PRE) && ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
     return ld4(buf, ix);
   }
 };
@@ -219,18 +225,30 @@ struct Walk {
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ static uint2 enter(const Fmt& F, uint32_t nd, uint32_t ptr, uint2 m, Mem& mem) {
     const uint32_t hk = di_hk(nd);
-    if ((FAM & fam_hk(HK_RAW)) && hk == HK_RAW) return make_uint2(ptr, 0u);
-    if ((FAM & fam_hk(HK_MASK)) && hk == HK_MASK) return m;
-    if ((FAM & fam_hk(HK_DAG)) && hk == HK_DAG) {
-      mem.note(ptr, 1);
-      return make_uint2(ptr + 1u, F.w1(ptr) & 0xFFu);
+    constexpr uint32_t LOADS = fam_hk(HK_DAG) | fam_hk(HK_SVO) | fam_hk(HK_MASKLOAD);
+    // One 8-byte load serves every header kind read at the pointer: an SVDAG node's mask
+    // word (the node also holds at least one child word, so the load stays inside it), an
+    // SVO node's two words, a one-block brick's mask.
+    uint2 h = make_uint2(0u, 0u);
+    if ((FAM & LOADS) && (hk == HK_DAG || hk == HK_SVO || hk == HK_MASKLOAD)) {
+      h = F.template w2<FAM>(ptr);
+      mem.note(ptr, hk == HK_DAG ? 1u : 2u);
     }
-    // HK_SVO (first, masks) or HK_MASKLOAD (lo, hi)
-    const uint2 h = F.w2(ptr);
-    mem.note(ptr, 2);
-    if (!(FAM & fam_hk(HK_SVO))) return h;
-    if (!(FAM & fam_hk(HK_MASKLOAD))) return make_uint2(h.x, h.y & 0xFFu);
-    return make_uint2(h.x, (hk == HK_SVO) ? (h.y & 0xFFu) : h.y);
+    uint32_t b = h.x, v = h.y;  // HK_MASKLOAD
+    if (FAM & fam_hk(HK_SVO)) v = (hk == HK_SVO) ? (h.y & 0xFFu) : v;
+    if (FAM & fam_hk(HK_DAG)) {
+      b = (hk == HK_DAG) ? ptr + 1u : b;
+      v = (hk == HK_DAG) ? (h.x & 0xFFu) : v;
+    }
+    if (FAM & fam_hk(HK_MASK)) {
+      b = (hk == HK_MASK) ? m.x : b;
+      v = (hk == HK_MASK) ? m.y : v;
+    }
+    if (FAM & fam_hk(HK_RAW)) {
+      b = (hk == HK_RAW) ? ptr : b;
+      v = (hk == HK_RAW) ? 0u : v;
+    }
+    return make_uint2(b, v);
   }
 
   // Pointer (and, for SVDAG descriptors, the child's header) of the occupied child `lin`
@@ -243,12 +261,12 @@ struct Walk {
     if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) {
       child = base + 2u * rank;
     } else if ((FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER) {
-      const uint2 dsc = F.w2(base + 2u * rank);  // (child pointer, child masks)
+      const uint2 dsc = F.template w2<FAM>(base + 2u * rank);  // (child pointer, child masks)
       mem.note(base + 2u * rank, 2);
       child = dsc.x;
       cm = make_uint2(dsc.x + 1u, dsc.y & 0xFFu);
     } else {
-      child = F.w1(base + rank);
+      child = F.template w1<FAM>(base + rank);
       mem.note(base + rank, 1);
     }
   }
@@ -263,7 +281,7 @@ struct Walk {
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int start(const Fmt& F, Mem& mem) {
     const uint32_t* dtab = F.dtab;
-    const uint32_t root = F.w1(0);  // word 0: pointer to the root sub-volume; 0 = empty
+    const uint32_t root = F.template w1<FAM>(0);  // word 0: pointer to the root sub-volume; 0 = empty
     mem.note(0, 1);
     if (root == 0u) return DONE;
     d = 0;
@@ -307,11 +325,11 @@ struct Walk {
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
     if ((FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR) {
-      child = F.w1(base + lin);
+      child = F.template w1<FAM>(base + lin);
       mem.note(base + lin, 1);
       occ = child != 0u;
     } else if ((FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS) {
-      cm = F.w2(base + 2u * lin);
+      cm = F.template w2<FAM>(base + 2u * lin);
       mem.note(base + 2u * lin, 2);
       occ = (cm.x | cm.y) != 0u;
     } else if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
@@ -321,12 +339,12 @@ struct Walk {
       if (l1 >= reach) {  // not known to be empty: read the cell
         uint32_t dist;
         if ((FAM & fam_nk(NK_DF_PTR)) && nk == NK_DF_PTR) {
-          child = F.w1(base + lin);
+          child = F.template w1<FAM>(base + lin);
           mem.note(base + lin, 1);
           occ = (child & DF_EMPTY) == 0u;
           dist = child & ~DF_EMPTY;
         } else {
-          const uint4 q = F.w4(base + 4u * lin);
+          const uint4 q = F.template w4<FAM>(base + 4u * lin);
           mem.note(base + 4u * lin, 4);
           cm = make_uint2(q.x, q.y);
           occ = (q.x | q.y) != 0u;
@@ -428,13 +446,13 @@ struct Walk {
       uint32_t child = 0u;
       uint2 cm = make_uint2(0u, 0u);
       if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
-        child = F.w1(base + kl);  // an ancestor cell: non-empty, so a plain pointer
+        child = F.template w1<FAM>(base + kl);  // an ancestor cell: non-empty, so a plain pointer
         mem.note(base + kl, 1);
       } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
-        cm = F.w2(base + 2u * kl);
+        cm = F.template w2<FAM>(base + 2u * kl);
         mem.note(base + 2u * kl, 2);
       } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
-        cm = F.w2(base + 4u * kl);
+        cm = F.template w2<FAM>(base + 4u * kl);
         mem.note(base + 4u * kl, 2);
       } else {
         octree_child<FAM>(F, knk, kl, base, valid, child, cm, mem);
@@ -472,6 +490,18 @@ __device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
 
 __device__ __forceinline__ int4 miss_hit() { return make_int4(-1, -1, -1, __float_as_int(INFINITY)); }
 
+// The whole walk of one ray: its result (a miss if it never hits).
+template <uint32_t FAM>
+__device__ __forceinline__ int4 trace_one(const Fmt& fm, uint2* stk, const float4 r0, const float4 r1) {
+  int4 out = miss_hit();
+  Walk w;
+  Plain mem;
+  if (setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
+    while (w.template step<FAM>(fm, stk, out, mem) == RUN) {
+    }
+  return out;
+}
+
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                       int4* __restrict__ hits, uint32_t n) {
@@ -483,29 +513,14 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  int4 out = miss_hit();
-  Walk w;
-  Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
-    while (w.template step<FAM>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
-    }
-  hits[i] = out;
+  hits[i] = F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
+                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1);
 }
 
-// Persistent variant: a grid sized to the device; each wave keeps its lanes busy by
-// fetching a new ray for every idle lane from a global counter whenever at least
-// `refill` lanes are idle (or the whole wave is). *counter must be 0 at launch.
 template <uint32_t FAM>
-__global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat F, const float4* __restrict__ rays,
-                                                                 int4* __restrict__ hits, uint32_t n,
-                                                                 uint32_t* __restrict__ counter, uint32_t refill,
-                                                                 uint32_t inner) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
-  extern __shared__ uint2 stk_all[];
-  const uint32_t* pre = stage_prefix(F, stk_all);
-  load_dtab(F, dtab);
-  const Fmt fm = fmt_of(F, dtab, pre);
-  uint2* stk = stk_all + threadIdx.x;
+__device__ __forceinline__ void persistent_loop(const Fmt& fm, uint2* stk, const float4* __restrict__ rays,
+                                                int4* __restrict__ hits, uint32_t n, uint32_t* __restrict__ counter,
+                                                uint32_t refill, uint32_t inner) {
   const uint32_t lane = __lane_id();
   Walk w;
   Plain mem;
@@ -528,7 +543,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
           ray = id;
           out = miss_hit();
           const float4 r0 = rays[2 * (size_t)id], r1 = rays[2 * (size_t)id + 1];
-          active = setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
+          active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
           if (!active) hits[id] = out;
         }
       }
@@ -546,6 +561,26 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
   }
 }
 
+// Persistent variant: a grid sized to the device; each wave keeps its lanes busy by
+// fetching a new ray for every idle lane from a global counter whenever at least
+// `refill` lanes are idle (or the whole wave is). *counter must be 0 at launch.
+template <uint32_t FAM>
+__global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                                 int4* __restrict__ hits, uint32_t n,
+                                                                 uint32_t* __restrict__ counter, uint32_t refill,
+                                                                 uint32_t inner) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
+  load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
+  uint2* stk = stk_all + threadIdx.x;
+  if (F.lds_words)
+    persistent_loop<FAM | FAM_PRE>(fm, stk, rays, hits, n, counter, refill, inner);
+  else
+    persistent_loop<FAM>(fm, stk, rays, hits, n, counter, refill, inner);
+}
+
 // One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F, const float4* __restrict__ rays,
@@ -561,13 +596,8 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   if (k >= n || key[k] == 0xFFFFFFFFu) return;  // rays that miss the root box were answered
   const uint32_t i = perm[k];
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  int4 out = miss_hit();
-  Walk w;
-  Plain mem;
-  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
-    while (w.template step<FAM>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
-    }
-  hits[i] = out;
+  hits[i] = F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
+                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
