@@ -319,6 +319,25 @@ def run_surface2048(args, torch, H, W, C):
     return {"occupancy": len(codes) / n ** 3, "formats": out}
 
 
+def run_bounce2048(args, torch, H, W, C):
+    """Only the incoherent launch of the 2048^3 leg (first format, plain schedule), for
+    counter profiles: the primary frame is traced once to derive the bounce rays, then the
+    bounce rays are traced warmup + steps times."""
+    cfg = C.SURF2048
+    codes = C.scene(cfg)
+    prim = C.primary_rays(cfg, 0)
+    v = H.Volume(cfg["specs"][0], codes)
+    v.upload()
+    h = v.trace(torch.from_numpy(prim).cuda())
+    torch.cuda.synchronize()
+    b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+    d_b = torch.from_numpy(b).cuda()
+    hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+    ms, _ = time_launches([lambda: v.trace(d_b, hb, sched=H.schedule())], args.steps, args.warmup)
+    log(f"[bench] bounce-2048 {cfg['specs'][0]}: {len(b)} rays, {ms * 1e3:.1f} us per launch, "
+        f"{len(b) / ms / 1e3:.1f} Mrays/s")
+
+
 def run_batched(args, torch, H, W, C):
     """64 volumes of random hybrid formats, 64 ray batches of uneven size: one graph-captured
     persistent launch versus one hvf_trace launch per volume on the same stream."""
@@ -510,7 +529,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "batched", "served", "df"], default=None,
+    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df"], default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -536,6 +555,9 @@ def main():
     torch.cuda.set_device(0)
     if args.only == "surface2048":
         run_surface2048(args, torch, H, W, C)
+        return
+    if args.only == "bounce2048":
+        run_bounce2048(args, torch, H, W, C)
         return
     if args.only == "batched":
         run_batched(args, torch, H, W, C)
