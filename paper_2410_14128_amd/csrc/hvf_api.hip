@@ -92,9 +92,12 @@ hvf_status hvf_upload(hvf_volume* v, void* stream) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const size_t bytes = v->built.words.size() * sizeof(uint32_t);
   uint32_t* p = nullptr;
-  e = hipMalloc(&p, bytes);
+  // Four spare zero words after the buffer: the kernels read 8 bytes at any word index.
+  e = hipMalloc(&p, bytes + HVF_BUFFER_PAD_WORDS * sizeof(uint32_t));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc of the word buffer");
-  e = hipMemcpyAsync(p, v->built.words.data(), bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
+  e = hipMemsetAsync(p + v->built.words.size(), 0, HVF_BUFFER_PAD_WORDS * sizeof(uint32_t), (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p, v->built.words.data(), bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) {
     (void)hipFree(p);

@@ -185,6 +185,9 @@ struct hvf_volume {
 };
 
 constexpr int HVF_NUM_COUNTERS = 64;
+// Zero words allocated after a device word buffer, so 8- and 16-byte reads that start at
+// any word of the buffer stay inside the allocation.
+constexpr size_t HVF_BUFFER_PAD_WORDS = 4;
 
 // Thread-local error text.
 void hvf_set_error(const std::string& s);

@@ -100,13 +100,16 @@ __device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const in
 // that holds the ray at time t: one mid-plane comparison per bit and axis. For d > 0 the
 // upper half holds the ray iff T(mid) <= t; for d < 0 iff t < T(mid); a parallel axis
 // compares floor(o) with mid. Plane times are never NaN once setup has passed.
+// Both comparisons are evaluated and combined with bit operations (a parallel axis's plane
+// time is +-inf or NaN and simply unused), so no per-lane branch is taken.
 __device__ __forceinline__ void refine3(const Ray& R, int p[3], int hi, int lo, float t) {
   for (int b = hi - 1; b >= lo; --b) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int mid = p[a] + (1 << b);
-      const float tm = R.T(a, mid);
-      const bool up = R.is_par(a) ? (R.vo[a] >= mid) : ((tm <= t) != R.is_neg(a));
+      const bool par = R.is_par(a);
+      const bool cross = (R.T(a, mid) <= t) != R.is_neg(a);
+      const bool up = (cross & !par) | ((R.vo[a] >= mid) & par);
       p[a] = up ? mid : p[a];
     }
   }
@@ -230,7 +233,8 @@ struct Walk {
     // word (the node also holds at least one child word, so the load stays inside it), an
     // SVO node's two words, a one-block brick's mask.
     uint2 h = make_uint2(0u, 0u);
-    if ((FAM & LOADS) && (hk == HK_DAG || hk == HK_SVO || hk == HK_MASKLOAD)) {
+    constexpr uint32_t LOAD_KINDS = (1u << HK_DAG) | (1u << HK_SVO) | (1u << HK_MASKLOAD);
+    if ((FAM & LOADS) && ((LOAD_KINDS >> hk) & 1u)) {
       h = F.template w2<FAM>(ptr);
       mem.note(ptr, hk == HK_DAG ? 1u : 2u);
     }
@@ -295,8 +299,9 @@ struct Walk {
       for (int a = 0; a < 3; ++a) {
         if (b >= F.ext[a]) continue;
         const int mid = p[a] + (1 << b);
-        const float tm = R.T(a, mid);
-        const bool up = R.is_par(a) ? (R.vo[a] >= mid) : ((tm <= R.t0) != R.is_neg(a));
+        const bool par = R.is_par(a);
+        const bool cross = (R.T(a, mid) <= R.t0) != R.is_neg(a);
+        const bool up = (cross & !par) | ((R.vo[a] >= mid) & par);
         p[a] = up ? mid : p[a];
       }
     }
@@ -321,18 +326,14 @@ struct Walk {
     const int cs = di_cs(info);
     // Child cell of the current node holding the ray (octree nodes: w = 1, the octant).
     const uint32_t lin = cell_lin(info);
-    bool occ;
+    // Register test: a voxel's bit in the block mask (base:valid) or an octree child's valid bit.
+    const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && lin < 32u) ? base : valid;
+    bool occ = ((word >> (lin & 31u)) & 1u) != 0u;
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
-    if ((FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR) {
-      child = F.template w1<FAM>(base + lin);
-      mem.note(base + lin, 1);
-      occ = child != 0u;
-    } else if ((FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS) {
-      cm = F.template w2<FAM>(base + 2u * lin);
-      mem.note(base + 2u * lin, 2);
-      occ = (cm.x | cm.y) != 0u;
-    } else if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
+    constexpr uint32_t OCT = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_FINAL);
+    const uint32_t rank = (FAM & OCT) ? (uint32_t)__popc(valid & ((1u << lin) - 1u)) : 0u;
+    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
       // Cell positions at this depth are multiples of 2^cs, so the shift is exact.
       const uint32_t l1 = (uint32_t)(abs(p[0] - a[0]) + abs(p[1] - a[1]) + abs(p[2] - a[2])) >> cs;
       occ = false;
@@ -358,13 +359,27 @@ struct Walk {
         }
       }
     } else {
-      // A voxel's bit in the block mask (base:valid), or an octree child's valid bit.
-      const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && lin < 32u) ? base : valid;
-      occ = ((word >> (lin & 31u)) & 1u) != 0u;
+      // One 8-byte read serves every kind whose test or descent reads memory: a pointer-grid
+      // cell, a block mask, or the occupied octree child's pointer or (pointer, masks)
+      // descriptor. The device buffer ends with spare zero words, so a read that starts at
+      // its last word stays inside the allocation.
+      const bool rawk = (FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR;
+      const bool blk = (FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS;
+      const bool optr = (FAM & fam_nk(NK_OCT_PTR)) && nk == NK_OCT_PTR;
+      const bool dagi = (FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER;
+      const uint32_t idx = rawk ? lin : (blk ? 2u * lin : (dagi ? 2u * rank : rank));
+      if (rawk || blk || ((optr || dagi) && occ)) {
+        const uint2 q = F.template w2<FAM>(base + idx);
+        mem.note(base + idx, (blk || dagi) ? 2u : 1u);
+        child = q.x;
+        cm = blk ? q : make_uint2(q.x + 1u, q.y & 0xFFu);
+      }
+      if (rawk) occ = child != 0u;
+      if (blk) occ = (cm.x | cm.y) != 0u;
+      if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) child = base + 2u * rank;
     }
     const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL);
     if (occ && !fin) {
-      if (nk >= NK_SVO_INNER) octree_child<FAM>(F, nk, lin, base, valid, child, cm, mem);
       if (F.stacked == ALL_STACKED)  // uniform: every depth has a slot, slot = depth
         stk[d * BLOCK] = make_uint2(base, valid);
       else if ((F.stacked >> d) & 1u)
@@ -394,11 +409,11 @@ struct Walk {
     // near planes are crossed no later than t. So the voxel's visit interval is
     // [t, min(t1, m)) and t < t1 always holds: it is visited iff t < m, and its entry
     // time is t itself.
-    if (occ && t < m) {
-      out = make_int4(p[0], p[1], p[2], __float_as_int(t));
-      return DONE;
-    }
-    if (!(m < R.t1)) return DONE;  // leaves the clipped ray interval: miss
+    // One exit test for both ends of a walk: the hit, or leaving the clipped ray interval
+    // (a miss, which leaves out untouched).
+    const bool hit = occ && t < m;
+    if (hit) out = make_int4(p[0], p[1], p[2], __float_as_int(t));
+    if (hit || !(m < R.t1)) return DONE;
     t = m;
     uint32_t dd = 0u;
 #pragma unroll
@@ -408,12 +423,11 @@ struct Walk {
       dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
       p[a] = mv ? np : p[a];
     }
-    // Pop to the deepest node that still contains the new cell (the root always does).
-    if (d > 0) {
-      const int hb = 31 - __clz(dd);
-      const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
-      if (nd != d) pop_to<FAM>(F, stk, nd, mem);
-    }
+    // Pop to the deepest node that still contains the new cell (the root always does; at
+    // depth 0 the min keeps nd = 0). Some axis always steps, so dd != 0.
+    const int hb = 31 - __clz(dd);
+    const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
+    if (nd != d) pop_to<FAM>(F, stk, nd, mem);
     return RUN;
   }
 
