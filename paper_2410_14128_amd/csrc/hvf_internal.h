@@ -145,9 +145,11 @@ constexpr uint32_t FAM_DF_BRICK = FAM_RAW_BRICK | fam_nk(NK_DF_PTR) | fam_nk(NK_
 constexpr uint32_t FAM_DF_OCTREE = FAM_RAW_OCTREE | fam_nk(NK_DF_PTR);
 constexpr uint32_t FAM_ALL = 0x1FFu | (0x1Fu << 16);
 constexpr uint32_t FAM_NODF = FAM_ALL & ~(fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS));
-constexpr uint32_t FAMILIES[] = {FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE,
-                                 FAM_DF_BRICK,  FAM_DF_OCTREE, FAM_NODF,      FAM_ALL};
-constexpr int NUM_FAMILIES = 9;
+constexpr uint32_t FAM_BRICK = fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) | fam_hk(HK_RAW) | fam_hk(HK_MASK) |
+                               fam_hk(HK_MASKLOAD);
+constexpr uint32_t FAMILIES[] = {FAM_BRICK,     FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE,
+                                 FAM_RAW_OCTREE, FAM_DF_BRICK,  FAM_DF_OCTREE, FAM_NODF,      FAM_ALL};
+constexpr int NUM_FAMILIES = 10;
 
 // Index into FAMILIES of the first family covering the layout.
 int family_of(const Layout& L);

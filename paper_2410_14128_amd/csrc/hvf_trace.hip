@@ -275,6 +275,18 @@ struct Walk {
     }
   }
 
+  // Far-plane crossing times of the current cell (side 2^cs) per axis (+inf on parallel
+  // axes) and their minimum.
+  __device__ __forceinline__ void far_times(int cs, float tf[3], float& m) const {
+    const int stepv = 1 << cs;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
+      tf[a] = R.is_par(a) ? INFINITY : tt;
+    }
+    m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
+  }
+
   __device__ __forceinline__ uint32_t cell_lin(uint32_t in) const {
     const int c = di_cs(in);
     const uint32_t wx = bf(in, 12, 4), wy = bf(in, 16, 4), wz = bf(in, 20, 4);
@@ -331,6 +343,7 @@ struct Walk {
     bool occ = ((word >> (lin & 31u)) & 1u) != 0u;
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
+    float tf[3], m;
     constexpr uint32_t OCT = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_FINAL);
     const uint32_t rank = (FAM & OCT) ? (uint32_t)__popc(valid & ((1u << lin) - 1u)) : 0u;
     if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
@@ -368,12 +381,18 @@ struct Walk {
       const bool optr = (FAM & fam_nk(NK_OCT_PTR)) && nk == NK_OCT_PTR;
       const bool dagi = (FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER;
       const uint32_t idx = rawk ? lin : (blk ? 2u * lin : (dagi ? 2u * rank : rank));
+      uint2 q = make_uint2(0u, 0u);
       if (rawk || blk || ((optr || dagi) && occ)) {
-        const uint2 q = F.template w2<FAM>(base + idx);
+        q = F.template w2<FAM>(base + idx);
         mem.note(base + idx, (blk || dagi) ? 2u : 1u);
-        child = q.x;
-        cm = blk ? q : make_uint2(q.x + 1u, q.y & 0xFFu);
       }
+      // The far-plane times below do not depend on the read: computing them before its
+      // first use lets the load's latency overlap them. The empty asm statement takes them
+      // as operands and is a scheduling boundary, so the compiler cannot sink them past it.
+      far_times(cs, tf, m);
+      asm volatile("" ::"v"(tf[0]), "v"(tf[1]), "v"(tf[2]), "v"(m));
+      child = q.x;
+      cm = blk ? q : make_uint2(q.x + 1u, q.y & 0xFFu);
       if (rawk) occ = child != 0u;
       if (blk) occ = (cm.x | cm.y) != 0u;
       if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) child = base + 2u * rank;
@@ -393,16 +412,11 @@ struct Walk {
       refine3(R, p, cs, di_cs(info), t);
       return RUN;
     }
-    // Far-plane times of the current cell: the advance below needs them, and for an occupied
-    // voxel they decide the hit.
+    // Far-plane times of the current cell (computed above on the common path): the advance
+    // below needs them, and for an occupied voxel they decide the hit.
+    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS))
+      far_times(cs, tf, m);
     const int stepv = 1 << cs;
-    float tf[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
-      tf[a] = R.is_par(a) ? INFINITY : tt;
-    }
-    const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
     // An occupied single voxel. The walk's t is always the entry time of its current cell:
     // the root cell is entered at t0, an advance enters the next cell at the crossing time
     // of the plane between them, and a descent picks the child holding the ray at t, whose
@@ -792,14 +806,15 @@ size_t stack_lds_bytes(const DevFormat& F) {
 
 #define HVF_FAMILY_SWITCH(family, LAUNCH) \
   switch (family) {                          \
-    case 0: LAUNCH(FAM_DAG_BRICK); break;    \
-    case 1: LAUNCH(FAM_SVO_BRICK); break;    \
-    case 2: LAUNCH(FAM_RAW_BRICK); break;    \
-    case 3: LAUNCH(FAM_OCTREE); break;       \
-    case 4: LAUNCH(FAM_RAW_OCTREE); break;   \
-    case 5: LAUNCH(FAM_DF_BRICK); break;     \
-    case 6: LAUNCH(FAM_DF_OCTREE); break;    \
-    case 7: LAUNCH(FAM_NODF); break;         \
+    case 0: LAUNCH(FAM_BRICK); break;        \
+    case 1: LAUNCH(FAM_DAG_BRICK); break;    \
+    case 2: LAUNCH(FAM_SVO_BRICK); break;    \
+    case 3: LAUNCH(FAM_RAW_BRICK); break;    \
+    case 4: LAUNCH(FAM_OCTREE); break;       \
+    case 5: LAUNCH(FAM_RAW_OCTREE); break;   \
+    case 6: LAUNCH(FAM_DF_BRICK); break;     \
+    case 7: LAUNCH(FAM_DF_OCTREE); break;    \
+    case 8: LAUNCH(FAM_NODF); break;         \
     default: LAUNCH(FAM_ALL); break;         \
   }
 
