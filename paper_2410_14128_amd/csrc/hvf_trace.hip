@@ -287,27 +287,6 @@ struct Walk {
     m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
   }
 
-  // The cell an advance moves to (every axis whose far-plane time equals m steps) and the
-  // depth of the deepest node that still contains it (the root always does; at depth 0 the
-  // min keeps 0). Computed before the step knows whether it advances, so that it overlaps
-  // the step's memory read; when m is reached on no axis (only if the ray has already
-  // left its interval) the depth is unused.
-  template <uint32_t FAM>
-  __device__ __forceinline__ void advance_target(const Fmt& F, int cs, const float tf[3], float m, int np[3],
-                                                 int& nd) const {
-    const int stepv = 1 << cs;
-    uint32_t dd = 0u;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int s = p[a] + (R.is_neg(a) ? -stepv : stepv);
-      const bool mv = (tf[a] == m);
-      dd |= mv ? (uint32_t)(s ^ p[a]) : 0u;
-      np[a] = mv ? s : p[a];
-    }
-    const int hb = dd ? 31 - __clz(dd) : 0;
-    nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
-  }
-
   __device__ __forceinline__ uint32_t cell_lin(uint32_t in) const {
     const int c = di_cs(in);
     const uint32_t wx = bf(in, 12, 4), wy = bf(in, 16, 4), wz = bf(in, 20, 4);
@@ -365,7 +344,6 @@ struct Walk {
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
     float tf[3], m;
-    int np[3], nd;  // the next cell and the depth to pop to, if the walk advances
     constexpr uint32_t OCT = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_FINAL);
     const uint32_t rank = (FAM & OCT) ? (uint32_t)__popc(valid & ((1u << lin) - 1u)) : 0u;
     if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
@@ -412,8 +390,7 @@ struct Walk {
       // first use lets the load's latency overlap them. The empty asm statement takes them
       // as operands and is a scheduling boundary, so the compiler cannot sink them past it.
       far_times(cs, tf, m);
-      advance_target<FAM>(F, cs, tf, m, np, nd);
-      asm volatile("" ::"v"(tf[0]), "v"(tf[1]), "v"(tf[2]), "v"(m), "v"(np[0]), "v"(np[1]), "v"(np[2]), "v"(nd));
+      asm volatile("" ::"v"(tf[0]), "v"(tf[1]), "v"(tf[2]), "v"(m));
       child = q.x;
       cm = blk ? q : make_uint2(q.x + 1u, q.y & 0xFFu);
       if (rawk) occ = child != 0u;
@@ -437,10 +414,9 @@ struct Walk {
     }
     // Far-plane times of the current cell (computed above on the common path): the advance
     // below needs them, and for an occupied voxel they decide the hit.
-    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
+    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS))
       far_times(cs, tf, m);
-      advance_target<FAM>(F, cs, tf, m, np, nd);
-    }
+    const int stepv = 1 << cs;
     // An occupied single voxel. The walk's t is always the entry time of its current cell:
     // the root cell is entered at t0, an advance enters the next cell at the crossing time
     // of the plane between them, and a descent picks the child holding the ray at t, whose
@@ -453,9 +429,18 @@ struct Walk {
     if (hit) out = make_int4(p[0], p[1], p[2], __float_as_int(t));
     if (hit || !(m < R.t1)) return DONE;
     t = m;
-    p[0] = np[0];
-    p[1] = np[1];
-    p[2] = np[2];
+    uint32_t dd = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int np = p[a] + (R.is_neg(a) ? -stepv : stepv);
+      const bool mv = (tf[a] == m);
+      dd |= mv ? (uint32_t)(np ^ p[a]) : 0u;
+      p[a] = mv ? np : p[a];
+    }
+    // Pop to the deepest node that still contains the new cell (the root always does; at
+    // depth 0 the min keeps nd = 0). Some axis always steps, so dd != 0.
+    const int hb = 31 - __clz(dd);
+    const int nd = min(d, (int)((F.pop_lut >> (4 * hb)) & 15u));
     if (nd != d) pop_to<FAM>(F, stk, nd, mem);
     return RUN;
   }
