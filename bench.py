@@ -258,6 +258,50 @@ def run_df512(args, torch, H, C, res):
     return out
 
 
+def run_sweep(args, torch, H, W, C):
+    """Every format of the paper's table on the matching synthetic volume: GPU-layout size
+    against Mrays/s, one lane per ray (1080p primary rays of view 0; at 2048^3 also the
+    bounce rays of those hits), and the Pareto set of (size, primary Mrays/s)."""
+    out = []
+    for log2n, cfg in ((9, C.SURF512), (11, C.SURF2048)):
+        codes = C.scene(cfg)
+        prim = C.primary_rays(cfg, 0)
+        d_prim = torch.from_numpy(prim).cuda()
+        h = torch.empty((len(prim), 4), dtype=torch.int32, device="cuda")
+        d_b = hb = None
+        for label, k, spec in C.TABLE_FORMATS:
+            if k != log2n:
+                continue
+            sp = C.table_spec(spec)
+            t0 = time.time()
+            v = H.Volume(sp, codes)
+            tb = time.time() - t0
+            v.upload()
+            plain = H.schedule()
+            ms, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
+            rec = {"label": label, "format": sp, "side": 1 << k, "bytes": v.info()["bytes"], "build_s": round(tb, 2),
+                   "primary_mrays_s": round(len(prim) / ms / 1e3, 1)}
+            if k == 11:
+                if d_b is None:
+                    torch.cuda.synchronize()
+                    b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+                    d_b = torch.from_numpy(b).cuda()
+                    hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+                msb, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
+                rec["bounce_mrays_s"] = round(d_b.shape[0] / msb / 1e3, 1)
+            log(f"[bench] sweep {label:2d} {sp:44s} {rec['bytes'] / 2 ** 20:9.1f} MiB  primary {rec['primary_mrays_s']:8.1f}"
+                + (f"  bounce {rec['bounce_mrays_s']:8.1f}" if "bounce_mrays_s" in rec else "") + " Mrays/s")
+            out.append(rec)
+            v.close()
+    for side in (512, 2048):
+        rows = sorted([r for r in out if r["side"] == side], key=lambda r: (r["bytes"], -r["primary_mrays_s"]))
+        best = -1.0
+        for r in rows:
+            r["pareto"] = r["primary_mrays_s"] > best
+            best = max(best, r["primary_mrays_s"])
+    return out
+
+
 def run_surface2048(args, torch, H, W, C):
     cfg = C.SURF2048
     n = 1 << cfg["log2n"]
@@ -529,7 +573,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df"], default=None,
+    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep"],
+                    default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -558,6 +603,9 @@ def main():
         return
     if args.only == "bounce2048":
         run_bounce2048(args, torch, H, W, C)
+        return
+    if args.only == "sweep":
+        print(json.dumps({"format_sweep": run_sweep(args, torch, H, W, C)}))
         return
     if args.only == "batched":
         run_batched(args, torch, H, W, C)

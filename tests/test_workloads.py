@@ -55,3 +55,20 @@ def test_bounce_rays_leave_the_surface():
     b, src = W.bounce_rays(1, rays, hits)
     assert len(b) == 1 and src[0] == 0
     assert abs(b[0, 0] - (2.0 - 2 ** -6)) < 1e-6 and b[0, 4] < 0  # leaves through the -x face
+
+
+def test_table_formats_recipe_matches_the_pinned_table():
+    """The sweep's format list is the paper's table (pinned in tests/golden)."""
+    import os
+    import re
+    from workloads import configs as C
+    gold = [l.split(maxsplit=2) for l in open(os.path.join(os.path.dirname(__file__), "golden", "table_formats.txt"))
+            if l.strip() and not l.startswith("#")]
+
+    def norm(s):
+        s = re.sub(r"D\((\d+)\^3,(\d+)\)", r"D(\1,\1,\1,\2)", s)
+        return re.sub(r"R\((\d+)\^3\)", r"R(\1,\1,\1)", s).strip()
+
+    assert len(gold) == len(C.TABLE_FORMATS) == 40
+    for (lab, side, spec), (l2, k, sp) in zip(gold, C.TABLE_FORMATS):
+        assert int(lab) == l2 and int(side) == 1 << k and norm(spec) == sp

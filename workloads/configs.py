@@ -35,6 +35,29 @@ SURF512_DF = ["D(3,3,3,6) D(3,3,3,6) G(3) --whole-level-dedup", "D(3,3,3,6) R(3,
               "D(4,4,4,6) S(5)", "D(4,4,4,6) G(5) --whole-level-dedup", "D(5,5,5,6) D(4,4,4,6)",
               "D(5,5,5,6) R(4,4,4)", "D(9,9,9,6)"]
 
+# The 40 evaluated format signatures of the paper's table (Sec. 6): (label, log2 side,
+# spec). Rows 1-20 represent a 2048^3 grid, rows 21-40 a 512^3 grid; R(k^3) is R(k,k,k)
+# and D(k^3,M) is D(k,k,k,M). SVDAG levels are built with whole-level de-duplication.
+TABLE_FORMATS = [
+    (1, 11, "D(4,4,4,6) D(3,3,3,6) G(4)"), (2, 11, "D(4,4,4,6) R(3,3,3) G(4)"), (3, 11, "R(4,4,4) R(3,3,3) G(4)"),
+    (4, 11, "R(4,4,4) S(3) G(4)"), (5, 11, "R(4,4,4) R(4,4,4) R(3,3,3)"), (6, 11, "D(4,4,4,6) S(7)"),
+    (7, 11, "D(4,4,4,6) G(7)"), (8, 11, "D(6,6,6,6) S(5)"), (9, 11, "D(6,6,6,6) G(5)"), (10, 11, "R(4,4,4) S(7)"),
+    (11, 11, "R(4,4,4) G(7)"), (12, 11, "R(6,6,6) S(5)"), (13, 11, "R(6,6,6) G(5)"), (14, 11, "R(3,3,3) G(8)"),
+    (15, 11, "R(8,8,8) G(3)"), (16, 11, "S(7) G(4)"), (17, 11, "S(5) G(6)"), (18, 11, "S(3) G(8)"), (19, 11, "S(11)"),
+    (20, 11, "G(11)"),
+    (21, 9, "D(3,3,3,6) D(3,3,3,6) G(3)"), (22, 9, "D(3,3,3,6) R(3,3,3) G(3)"), (23, 9, "R(3,3,3) R(3,3,3) G(3)"),
+    (24, 9, "R(3,3,3) R(3,3,3) R(3,3,3)"), (25, 9, "R(4,4,4) R(1,1,1) R(4,4,4)"), (26, 9, "D(4,4,4,6) S(5)"),
+    (27, 9, "D(4,4,4,6) G(5)"), (28, 9, "R(4,4,4) S(5)"), (29, 9, "R(4,4,4) G(5)"), (30, 9, "R(2,2,2) G(7)"),
+    (31, 9, "R(7,7,7) G(2)"), (32, 9, "S(5) R(4,4,4)"), (33, 9, "G(5) R(4,4,4)"), (34, 9, "D(5,5,5,6) D(4,4,4,6)"),
+    (35, 9, "D(5,5,5,6) R(4,4,4)"), (36, 9, "R(5,5,5) R(4,4,4)"), (37, 9, "R(9,9,9)"), (38, 9, "D(9,9,9,6)"),
+    (39, 9, "S(9)"), (40, 9, "G(9)"),
+]
+
+
+def table_spec(spec: str) -> str:
+    return spec + " --whole-level-dedup" if "G(" in spec else spec
+
+
 # 2048^3 surface volume: 96 spheres + 32 tori; SVDAG top 7 levels -> Raw 16^3 bricks, and
 # SVO -> Raw 8^3; 1080p primary rays plus one cosine-weighted bounce per primary hit.
 SURF2048 = dict(name="surface-2048", log2n=11, seed=3, n_sph=96, n_tor=32, scale=1.2, width=1920, height=1080,
