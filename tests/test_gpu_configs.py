@@ -143,3 +143,28 @@ def test_max_extent_volume(H):
     ref = oracle.brute(codes, (16, 16, 16), rays)
     assert compare(got, ref, "max extent") == 0
     assert np.all(got[:, 0] >= 0)
+
+
+# ------------------------------------------------------------------ the paper's 40 formats
+@pytest.mark.parametrize("label,k,spec", [t for t in C.TABLE_FORMATS if t[1] == 9], ids=lambda x: str(x))
+def test_table_format_512(H, surf512, label, k, spec):
+    """Every 512^3 row of the format table against the flat DDA (the same occupancy)."""
+    cfg, codes, views = surf512
+    dense = _dense(codes, 9)
+    vol = H.Volume(C.table_spec(spec), codes)
+    rays = views[label % 4]
+    got = _trace_full(vol, rays)
+    idx = np.random.default_rng(label).choice(len(rays), 4000, replace=False)
+    assert compare(got[idx], oracle.flat_dda(dense, (9, 9, 9), rays[idx]), f"row {label} {spec}") == 0
+
+
+@pytest.mark.parametrize("label,k,spec", [t for t in C.TABLE_FORMATS if t[1] == 11], ids=lambda x: str(x))
+def test_table_format_2048(H, surf2048, label, k, spec):
+    """Every 2048^3 row of the format table against the oracle's G(11) hits (every format
+    of one volume has the same first hits)."""
+    cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
+    vol = H.Volume(C.table_spec(spec), codes)
+    got = _trace_full(vol, prim)
+    assert compare(got[idx], ref_p, f"row {label} {spec} primary") == 0
+    assert compare(_trace_full(vol, bounce), ref_b, f"row {label} {spec} bounce") == 0
+    assert compare(_trace_full(vol, rnd[:5000]), ref_r[:5000], f"row {label} {spec} random") == 0
