@@ -123,6 +123,23 @@ typedef struct hvf_schedule {
  * Makes no HIP call. */
 hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, hvf_volume** out);
 
+/* Build a volume on the device (Sec. 4.1) from Morton codes already in device memory.
+ * The word buffer, statistics and host copy are identical to hvf_build's for the same
+ * spec and codes; the nodes of every depth come from the codes by flag, scan and sort
+ * passes on hip_stream (a hipStream_t, or NULL for the null stream), and SVDAG nodes are
+ * de-duplicated by sorted content hashes, confirmed word by word.
+ * format_spec: as for hvf_build; distance-field levels D(...) give HVF_E_UNSUPPORTED.
+ * d_morton, n: device pointer to n strictly ascending Morton codes (x bit 0, y bit 1,
+ *   z bit 2 of each 3-bit group), all inside the volume; n < 2^31. Read only, not retained.
+ * out: receives a new handle owned by the caller (release with hvf_free); its device
+ *   buffer is already resident on the current device (no upload needed).
+ * Synchronises hip_stream before returning; temporary device memory (a few words per code
+ * and per node) is freed before returning.
+ * Errors: HVF_E_SPEC, HVF_E_INPUT (null pointers, codes not ascending or outside the
+ * volume), HVF_E_OVERFLOW, HVF_E_NOMEM, HVF_E_DEVICE, HVF_E_UNSUPPORTED. */
+hvf_status hvf_build_device(const char* format_spec, const uint64_t* d_morton, size_t n, void* hip_stream,
+                            hvf_volume** out);
+
 /* Copy the word buffer to device memory owned by the handle, on hip_stream (a
  * hipStream_t, or NULL for the null stream). Called implicitly by the first trace.
  * Errors: HVF_E_INPUT, HVF_E_NOMEM, HVF_E_DEVICE. */

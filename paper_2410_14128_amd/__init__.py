@@ -106,6 +106,8 @@ def lib():
         vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
         L.hvf_build.restype = i32
         L.hvf_build.argtypes = [ctypes.c_char_p, vp, sz, ctypes.POINTER(vp)]
+        L.hvf_build_device.restype = i32
+        L.hvf_build_device.argtypes = [ctypes.c_char_p, vp, sz, vp, ctypes.POINTER(vp)]
         L.hvf_upload.restype = i32
         L.hvf_upload.argtypes = [vp, vp]
         L.hvf_trace.restype = i32
@@ -194,6 +196,21 @@ class Volume:
             _check(lib().hvf_build(spec.encode(), c.ctypes.data if len(c) else None, len(c), ctypes.byref(h)))
             self._h = h.value
         self.spec = spec
+
+    @classmethod
+    def from_device(cls, spec: str, codes, stream=None) -> "Volume":
+        """Build on the device from a uint64 (or int64) CUDA tensor of ascending Morton codes."""
+        import torch
+        if not isinstance(codes, torch.Tensor) or not codes.is_cuda:
+            raise TypeError("codes must be a device tensor")
+        if codes.dtype not in (torch.int64, torch.uint64) or codes.dim() != 1:
+            raise TypeError("codes must be a 1-D 64-bit integer tensor")
+        c = codes.contiguous()
+        h = ctypes.c_void_p()
+        n = c.numel()
+        _check(lib().hvf_build_device(spec.encode(), c.data_ptr() if n else None, n, _stream_ptr(stream),
+                                      ctypes.byref(h)))
+        return cls(spec, _handle=h.value)
 
     @classmethod
     def load(cls, path: str) -> "Volume":

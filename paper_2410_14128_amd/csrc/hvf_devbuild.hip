@@ -1,0 +1,707 @@
+// Construction of a format on the device from a device array of sorted Morton codes
+// (the bottom-up construction of Sec. 4.1, reorganised as data-parallel passes).
+//
+// The result is word for word the buffer the host builder produces (same layout rules):
+//  * the nodes of a depth are the distinct values of code >> 3s (s = log2 of the node side;
+//    the root depth has one node). Sorted codes give them in Morton order, which is the
+//    order in which a depth-first construction in Morton order creates them;
+//  * a node's children are a contiguous run of the next depth's nodes: those whose key,
+//    shifted to the node's side, equals the node's key. One flag pass and one scan over the
+//    child keys give every child its parent and every parent its run;
+//  * word offsets are assigned bottom-up. An SVDAG node below its level's root takes the
+//    offset of the first node in Morton order with the same content (mask word and child
+//    offsets) inside the same sub-volume, or inside the whole level with whole-level
+//    de-duplication (Sec. 4.3). Equal content is found by sorting 64-bit content hashes
+//    and confirmed word by word, so a hash collision never merges different nodes;
+//  * depths are placed in order at 64-byte aligned word offsets (SVO pointer arrays right
+//    after their depth) and child references are written as absolute word offsets.
+// Distance-field levels are not built on the device.
+#include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
+#include <climits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hvf_internal.h"
+
+namespace hvf {
+namespace {
+
+constexpr unsigned TB = 256;
+
+inline unsigned grid_for(size_t n) { return (unsigned)((n + TB - 1) / TB); }
+
+// One coordinate (bits 0, 3, 6, ...) of an interleaved Morton code.
+__device__ __forceinline__ uint64_t coord_of(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+  v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+  v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
+  v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
+  v = (v ^ (v >> 32)) & 0x1FFFFFull;
+  return v;
+}
+
+// err bit 0: not strictly ascending; bit 1: outside the volume.
+__global__ void k_validate(const uint64_t* __restrict__ c, size_t n, int ex, int ey, int ez,
+                           uint32_t* __restrict__ err) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t v = c[i];
+  uint32_t e = 0;
+  if (i > 0 && v <= c[i - 1]) e |= 1u;
+  if ((coord_of(v) >> ex) || (coord_of(v >> 1) >> ey) || (coord_of(v >> 2) >> ez) || (v >> 63)) e |= 2u;
+  if (e) atomicOr(err, e);
+}
+
+// flag[i] = 1 where x[i] >> sh starts a new run.
+__global__ void k_run_flags(const uint64_t* __restrict__ x, size_t n, int sh, uint32_t* __restrict__ flag) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (i == 0 || (x[i] >> sh) != (x[i - 1] >> sh)) ? 1u : 0u;
+}
+
+// out[rank - 1] = x >> sh at every run start (rank: inclusive scan of the flags).
+__global__ void k_run_keys(const uint64_t* __restrict__ x, size_t n, int sh, const uint32_t* __restrict__ flag,
+                           const uint32_t* __restrict__ rank, uint64_t* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  out[rank[i] - 1u] = x[i] >> sh;
+}
+
+__global__ void k_decrement(uint32_t* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) x[i] -= 1u;
+}
+
+__global__ void k_iota(uint32_t* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) x[i] = (uint32_t)i;
+}
+
+__global__ void k_stride_ids(uint32_t* __restrict__ x, size_t n, uint32_t f) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) x[i] = (uint32_t)i * f;
+}
+
+__global__ void k_gather(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx, size_t n,
+                         uint32_t* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// First child and child count of every parent (children of a parent are contiguous and
+// every parent has at least one): starts first, ends in a second pass.
+__global__ void k_child_first(const uint32_t* __restrict__ par, size_t nc, uint32_t* __restrict__ first) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  const uint32_t p = par[j];
+  if (j == 0 || par[j - 1] != p) first[p] = (uint32_t)j;
+}
+
+__global__ void k_child_count(const uint32_t* __restrict__ par, size_t nc, const uint32_t* __restrict__ first,
+                              uint32_t* __restrict__ count) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  const uint32_t p = par[j];
+  if (j + 1 == nc || par[j + 1] != p) count[p] = (uint32_t)(j + 1) - first[p];
+}
+
+// Octree child masks: bit (child key & 7) of the parent; at the deepest depth of the last
+// level the children are voxels (node = rank - 1, or the root when rank is null).
+__global__ void k_valid(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ par, size_t nc,
+                        uint32_t* __restrict__ valid) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  atomicOr(&valid[par ? par[j] : 0u], 1u << (uint32_t)(ckey[j] & 7u));
+}
+
+__global__ void k_valid_voxels(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
+                               uint32_t* __restrict__ valid) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  atomicOr(&valid[rank ? rank[i] - 1u : 0u], 1u << (uint32_t)(codes[i] & 7u));
+}
+
+// Mask word of an octree node: child mask, and as leaf mask too at a level's deepest depth.
+__global__ void k_masks(uint32_t* __restrict__ valid, size_t n, int deepest) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t v = valid[i];
+  valid[i] = v | (deepest ? (v << 8) : 0u);
+}
+
+// ---------------------------------------------------------------- SVDAG de-duplication
+struct DagView {
+  const uint32_t* masks;
+  const uint32_t* first;  // null: no children (the last level's deepest depth)
+  const uint32_t* count;
+  const uint32_t* cid;    // children's word offsets at the next depth
+  const uint32_t* group;  // sub-volume of each node; null with whole-level de-duplication
+};
+
+__device__ __forceinline__ uint64_t mix64(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  h *= 0xBF58476D1CE4E5B9ull;
+  return h ^ (h >> 29);
+}
+
+__global__ void k_dag_hash(DagView V, size_t n, uint64_t* __restrict__ hash) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  uint64_t h = mix64(0x51ED27D3A9C1B4F5ull, V.group ? V.group[x] : 0u);
+  h = mix64(h, V.masks[x]);
+  if (V.first) {
+    const uint32_t f = V.first[x], c = V.count[x];
+    for (uint32_t t = 0; t < c; ++t) h = mix64(h, V.cid[f + t]);
+  }
+  hash[x] = h;
+}
+
+__device__ bool dag_equal(const DagView& V, uint32_t a, uint32_t b) {
+  if (V.masks[a] != V.masks[b]) return false;
+  if (V.group && V.group[a] != V.group[b]) return false;
+  if (!V.first) return true;
+  const uint32_t fa = V.first[a], fb = V.first[b], c = V.count[a];
+  if (V.count[b] != c) return false;
+  for (uint32_t t = 0; t < c; ++t)
+    if (V.cid[fa + t] != V.cid[fb + t]) return false;
+  return true;
+}
+
+// head[k] = k at the start of a run of equal sorted hashes, else 0 (max-scanned after).
+__global__ void k_hash_heads(const uint64_t* __restrict__ sh, size_t n, uint32_t* __restrict__ head) {
+  const size_t k = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (k >= n) return;
+  head[k] = (k == 0 || sh[k] != sh[k - 1]) ? (uint32_t)k : 0u;
+}
+
+// canon[x]: the first node in Morton order with x's content. A run of equal hashes lists
+// its nodes in ascending index (stable sort of an ascending index), so the first equal
+// entry of x's run is that node; the run's head is it unless hashes collide.
+__global__ void k_canon(DagView V, const uint32_t* __restrict__ sidx, const uint32_t* __restrict__ head, size_t n,
+                        uint32_t* __restrict__ canon) {
+  const size_t k = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t x = sidx[k];
+  const uint32_t h = head[k];
+  uint32_t c = x;
+  if (h != (uint32_t)k) {
+    if (dag_equal(V, sidx[h], x)) {
+      c = sidx[h];
+    } else {
+      for (uint32_t q = h + 1; q < (uint32_t)k; ++q)
+        if (dag_equal(V, sidx[q], x)) {
+          c = sidx[q];
+          break;
+        }
+    }
+  }
+  canon[x] = c;
+}
+
+// Words of the nodes that are stored (their own canonical node), 0 for merged ones.
+__global__ void k_dag_sizes(const uint32_t* __restrict__ canon, const uint32_t* __restrict__ count, size_t n,
+                            int inner, uint64_t* __restrict__ usize, uint32_t* __restrict__ uflag) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  const bool u = canon[x] == (uint32_t)x;
+  const uint64_t len = 1u + (count ? count[x] : 0u) * (inner ? 2u : 1u);
+  usize[x] = u ? len : 0u;
+  uflag[x] = u ? 1u : 0u;
+}
+
+__global__ void k_dag_ids(const uint32_t* __restrict__ canon, const uint64_t* __restrict__ off, size_t n,
+                          uint32_t* __restrict__ id) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x < n) id[x] = (uint32_t)off[canon[x]];
+}
+
+// ---------------------------------------------------------------- writing the buffer
+// Bricks of the last Raw level: one bit per voxel in the 64-bit mask of its block.
+__global__ void k_write_bricks(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
+                               int ns, int b, int wx, int wy, uint64_t stride, uint32_t* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t c = codes[i];
+  const uint64_t local = rank ? (c & ((1ull << (3 * ns)) - 1ull)) : c;
+  const uint64_t lx = coord_of(local), ly = coord_of(local >> 1), lz = coord_of(local >> 2);
+  const uint64_t m = (1ull << b) - 1ull;
+  const uint64_t blk = (lx >> b) | ((ly >> b) << wx) | ((lz >> b) << (wx + wy));
+  const uint64_t bit = (lx & m) | ((ly & m) << b) | ((lz & m) << (2 * b));
+  const uint64_t node = rank ? rank[i] - 1u : 0u;
+  atomicOr(&dst[node * stride + 2 * blk + (bit >> 5)], 1u << (uint32_t)(bit & 31u));
+}
+
+// Raw pointer grids: the cell of each child holds its absolute word offset (0 = empty).
+// The root grid may be non-cubic (w0, w1 = log2 cells along x, y); below it the child key's
+// low 3*w0 bits locate the cell.
+__global__ void k_write_raw(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ par,
+                            const uint32_t* __restrict__ cid, size_t nc, int w0, int w1, int root, uint64_t cells,
+                            uint32_t child_base, uint32_t* __restrict__ dst) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  const uint64_t k = ckey[j];
+  const uint64_t local = root ? k : (k & ((1ull << (3 * w0)) - 1ull));
+  const uint64_t cell = coord_of(local) | (coord_of(local >> 1) << w0) | (coord_of(local >> 2) << (w0 + w1));
+  dst[(uint64_t)(par ? par[j] : 0u) * cells + cell] = child_base + cid[j];
+}
+
+// SVO nodes {first word, masks}. mode 1: children are this level's nodes (the first
+// child's absolute offset); mode 2: children are next-level roots (absolute offset of the
+// node's first entry in the depth's pointer array); mode 0: no children.
+__global__ void k_write_svo(const uint32_t* __restrict__ masks, const uint32_t* __restrict__ first,
+                            const uint32_t* __restrict__ cid, size_t n, int mode, uint32_t target,
+                            uint32_t* __restrict__ dst) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  uint32_t w0 = 0;
+  if (mode == 1) w0 = target + cid[first[x]];
+  if (mode == 2) w0 = target + first[x];
+  dst[2 * x] = w0;
+  dst[2 * x + 1] = masks[x];
+}
+
+__global__ void k_write_ptrs(const uint32_t* __restrict__ cid, size_t nc, uint32_t child_base,
+                             uint32_t* __restrict__ dst) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j < nc) dst[j] = child_base + cid[j];
+}
+
+// Stored SVDAG nodes: mask word, then per child its absolute offset, followed by the
+// child's mask word when the children belong to the same level.
+__global__ void k_write_dag(DagView V, const uint32_t* __restrict__ canon, const uint32_t* __restrict__ id,
+                            const uint32_t* __restrict__ cmask, size_t n, int inner, uint32_t child_base,
+                            uint32_t* __restrict__ dst) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n || canon[x] != (uint32_t)x) return;
+  uint32_t* o = dst + id[x];
+  o[0] = V.masks[x];
+  if (!V.first) return;
+  const uint32_t f = V.first[x], c = V.count[x];
+  for (uint32_t t = 0; t < c; ++t) {
+    if (inner) {
+      o[1 + 2 * t] = child_base + V.cid[f + t];
+      o[2 + 2 * t] = cmask[f + t];
+    } else {
+      o[1 + t] = child_base + V.cid[f + t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host orchestration
+struct DepthState {
+  size_t n = 0;               // nodes (before de-duplication)
+  uint64_t* keys = nullptr;   // node keys (code >> 3*ns), ascending
+  uint32_t* parent = nullptr; // parent index of every node (depths >= 1)
+  uint32_t* first = nullptr;  // first child at the next depth
+  uint32_t* count = nullptr;
+  uint32_t* group = nullptr;  // SVDAG levels: index of the node's sub-volume root
+  uint32_t* masks = nullptr;  // octree nodes: mask word
+  uint32_t* canon = nullptr;  // SVDAG nodes: canonical node
+  uint32_t* id = nullptr;     // word offset inside the depth
+  uint64_t stored = 0;        // nodes stored
+  uint64_t words = 0;         // arena words
+  uint64_t aux = 0;           // pointer-array words (SVO nodes above the next level)
+  int ns = 0;                 // log2 node side (depths >= 1)
+};
+
+class DeviceBuilder {
+ public:
+  DeviceBuilder(const Spec& s, const Layout& l, const uint64_t* codes, size_t n, hipStream_t st)
+      : S(s), L(l), codes_(codes), n_(n), s_(st) {}
+  ~DeviceBuilder() {
+    for (void* p : owned_) (void)hipFree(p);
+    if (buf_) (void)hipFree(buf_);
+  }
+
+  hvf_status run(Built& B, uint32_t** dbuf);
+  const std::string& error() const { return err_; }
+
+ private:
+  const Spec& S;
+  const Layout& L;
+  const uint64_t* codes_;
+  size_t n_;
+  hipStream_t s_;
+  std::vector<void*> owned_;
+  void* tmp_ = nullptr;
+  size_t tmp_bytes_ = 0;
+  uint32_t* buf_ = nullptr;
+  std::string err_;
+  hvf_status st_ = HVF_OK;
+
+  bool fail(hvf_status s, const std::string& m) {
+    if (st_ == HVF_OK) {
+      st_ = s;
+      err_ = m;
+    }
+    return false;
+  }
+  bool hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    return fail(e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE,
+                std::string("device construction, ") + what + ": " + hipGetErrorString(e));
+  }
+  bool launched(const char* what) { return hip(hipGetLastError(), what); }
+  template <class T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, (count ? count : 1) * sizeof(T));
+    if (!hip(e, "hipMalloc")) return nullptr;
+    owned_.push_back(p);
+    return static_cast<T*>(p);
+  }
+  bool scratch(size_t bytes) {
+    if (bytes <= tmp_bytes_) return true;
+    tmp_ = alloc<char>(bytes);
+    tmp_bytes_ = tmp_ ? bytes : 0;
+    return tmp_ != nullptr;
+  }
+  template <class T>
+  bool fetch(const T* p, T& v) {
+    return hip(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s_), "hipMemcpyAsync") &&
+           hip(hipStreamSynchronize(s_), "hipStreamSynchronize");
+  }
+  bool inclusive_sum(const uint32_t* in, uint32_t* out, size_t n) {
+    size_t b = 0;
+    if (!hip(hipcub::DeviceScan::InclusiveSum(nullptr, b, in, out, (int)n, s_), "scan") || !scratch(b)) return false;
+    return hip(hipcub::DeviceScan::InclusiveSum(tmp_, b, in, out, (int)n, s_), "scan");
+  }
+  bool exclusive_sum(const uint64_t* in, uint64_t* out, size_t n) {
+    size_t b = 0;
+    if (!hip(hipcub::DeviceScan::ExclusiveSum(nullptr, b, in, out, (int)n, s_), "scan") || !scratch(b)) return false;
+    return hip(hipcub::DeviceScan::ExclusiveSum(tmp_, b, in, out, (int)n, s_), "scan");
+  }
+  bool max_scan(const uint32_t* in, uint32_t* out, size_t n) {
+    size_t b = 0;
+    if (!hip(hipcub::DeviceScan::InclusiveScan(nullptr, b, in, out, hipcub::Max(), (int)n, s_), "scan") ||
+        !scratch(b))
+      return false;
+    return hip(hipcub::DeviceScan::InclusiveScan(tmp_, b, in, out, hipcub::Max(), (int)n, s_), "scan");
+  }
+  bool sum(const uint32_t* in, uint32_t* out, size_t n) {
+    size_t b = 0;
+    if (!hip(hipcub::DeviceReduce::Sum(nullptr, b, in, out, (int)n, s_), "reduce") || !scratch(b)) return false;
+    return hip(hipcub::DeviceReduce::Sum(tmp_, b, in, out, (int)n, s_), "reduce");
+  }
+  bool sort_pairs(const uint64_t* kin, uint64_t* kout, const uint32_t* vin, uint32_t* vout, size_t n) {
+    size_t b = 0;
+    if (!hip(hipcub::DeviceRadixSort::SortPairs(nullptr, b, kin, kout, vin, vout, (int)n, 0, 64, s_), "sort") ||
+        !scratch(b))
+      return false;
+    return hip(hipcub::DeviceRadixSort::SortPairs(tmp_, b, kin, kout, vin, vout, (int)n, 0, 64, s_), "sort");
+  }
+
+  static bool is_brick(const DepthInfo& di) {
+    return di.nk == NK_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD);
+  }
+  static bool is_octree(const DepthInfo& di) {
+    return di.nk == NK_SVO_INNER || di.nk == NK_DAG_INNER || di.nk == NK_OCT_PTR || di.nk == NK_OCT_FINAL;
+  }
+  bool dedup(int i, std::vector<DepthState>& D, bool has_children);
+};
+
+// SVDAG depth i: canonical nodes, stored-node offsets, word count.
+bool DeviceBuilder::dedup(int i, std::vector<DepthState>& D, bool has_children) {
+  const DepthInfo& di = L.d[i];
+  DepthState& q = D[i];
+  const size_t n = q.n;
+  DagView V{q.masks, has_children ? q.first : nullptr, has_children ? q.count : nullptr,
+            has_children ? D[i + 1].id : nullptr, S.wld ? nullptr : q.group};
+  q.canon = alloc<uint32_t>(n);
+  if (!q.canon) return false;
+  if (di.j == 0) {
+    // A sub-volume root is stored as is (its parent level points at it).
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(TB), 0, s_, q.canon, n);
+    if (!launched("iota")) return false;
+  } else {
+    uint64_t* hash = alloc<uint64_t>(n);
+    uint64_t* shash = alloc<uint64_t>(n);
+    uint32_t* idx = alloc<uint32_t>(n);
+    uint32_t* sidx = alloc<uint32_t>(n);
+    uint32_t* head = alloc<uint32_t>(n);
+    uint32_t* runh = alloc<uint32_t>(n);
+    if (!hash || !shash || !idx || !sidx || !head || !runh) return false;
+    hipLaunchKernelGGL(k_dag_hash, dim3(grid_for(n)), dim3(TB), 0, s_, V, n, hash);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(TB), 0, s_, idx, n);
+    if (!launched("hash") || !sort_pairs(hash, shash, idx, sidx, n)) return false;
+    hipLaunchKernelGGL(k_hash_heads, dim3(grid_for(n)), dim3(TB), 0, s_, shash, n, head);
+    if (!launched("heads") || !max_scan(head, runh, n)) return false;
+    hipLaunchKernelGGL(k_canon, dim3(grid_for(n)), dim3(TB), 0, s_, V, sidx, runh, n, q.canon);
+    if (!launched("canon")) return false;
+  }
+  uint64_t* usize = alloc<uint64_t>(n);
+  uint64_t* off = alloc<uint64_t>(n);
+  uint32_t* uflag = alloc<uint32_t>(n);
+  uint32_t* nstored = alloc<uint32_t>(1);
+  q.id = alloc<uint32_t>(n);
+  if (!usize || !off || !uflag || !nstored || !q.id) return false;
+  const int inner = di.nk == NK_DAG_INNER;
+  hipLaunchKernelGGL(k_dag_sizes, dim3(grid_for(n)), dim3(TB), 0, s_, q.canon, V.count, n, inner, usize, uflag);
+  if (!launched("sizes") || !exclusive_sum(usize, off, n) || !sum(uflag, nstored, n)) return false;
+  hipLaunchKernelGGL(k_dag_ids, dim3(grid_for(n)), dim3(TB), 0, s_, q.canon, off, n, q.id);
+  if (!launched("ids")) return false;
+  uint64_t last_off = 0, last_size = 0;
+  uint32_t stored = 0;
+  if (!fetch(off + n - 1, last_off) || !fetch(usize + n - 1, last_size) || !fetch(nstored, stored)) return false;
+  q.words = last_off + last_size;
+  q.stored = stored;
+  return true;
+}
+
+hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf) {
+  const int nd = (int)L.d.size();
+  std::vector<DepthState> D(nd);
+  for (int i = 1; i < nd; ++i) D[i].ns = L.d[i].cs + L.d[i].w[0];
+  // 1. the codes: strictly ascending and inside the volume
+  uint32_t* err = alloc<uint32_t>(1);
+  if (!err || !hip(hipMemsetAsync(err, 0, sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, S.ext[0], S.ext[1], S.ext[2], err);
+  uint32_t herr = 0;
+  if (!launched("validate") || !fetch(err, herr)) return st_;
+  if (herr & 1u) return fail(HVF_E_INPUT, "Morton codes must be strictly ascending"), st_;
+  if (herr & 2u) return fail(HVF_E_INPUT, "Morton code outside the volume"), st_;
+  // Nodes of more than 2^31 words are out of range of the traversal's 32-bit offsets.
+  for (const DepthInfo& di : L.d) {
+    const int sw = di.w[0] + di.w[1] + di.w[2];
+    const uint64_t node_words = is_brick(di) ? (2ull << (di.nk == NK_BLOCKS ? sw : 0)) : (1ull << sw);
+    if ((di.nk == NK_RAW_PTR || is_brick(di)) && node_words >= (1ull << 31))
+      return fail(HVF_E_OVERFLOW, "a single node of this format needs 2^31 words or more, beyond 32-bit word offsets"),
+             st_;
+  }
+  // 2. node keys, bottom-up. The deepest stored depth takes its nodes from the codes (and
+  //    keeps every code's node rank: bricks and final octree masks are filled per voxel).
+  const int dl = L.d[nd - 1].arena ? nd - 1 : nd - 2;
+  uint32_t* flag = alloc<uint32_t>(n_);
+  if (!flag) return st_;
+  uint32_t* code_rank = nullptr;
+  if (dl == 0) {
+    D[0].n = 1;
+  } else {
+    DepthState& q = D[dl];
+    code_rank = alloc<uint32_t>(n_);
+    if (!code_rank) return st_;
+    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag);
+    uint32_t cnt = 0;
+    if (!launched("flags") || !inclusive_sum(flag, code_rank, n_) || !fetch(code_rank + n_ - 1, cnt)) return st_;
+    q.n = cnt;
+    if (!(q.keys = alloc<uint64_t>(q.n))) return st_;
+    hipLaunchKernelGGL(k_run_keys, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag, code_rank, q.keys);
+    if (!launched("keys")) return st_;
+  }
+  for (int i = dl - 1; i >= 0; --i) {
+    DepthState& q = D[i];
+    DepthState& c = D[i + 1];
+    if (!(c.parent = alloc<uint32_t>(c.n))) return st_;
+    if (i == 0) {
+      q.n = 1;
+      if (!hip(hipMemsetAsync(c.parent, 0, c.n * sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
+    } else {
+      const int sh = 3 * (q.ns - c.ns);
+      hipLaunchKernelGGL(k_run_flags, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag);
+      uint32_t cnt = 0;
+      if (!launched("flags") || !inclusive_sum(flag, c.parent, c.n) || !fetch(c.parent + c.n - 1, cnt)) return st_;
+      q.n = cnt;
+      if (!(q.keys = alloc<uint64_t>(q.n))) return st_;
+      hipLaunchKernelGGL(k_run_keys, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag, c.parent, q.keys);
+      hipLaunchKernelGGL(k_decrement, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n);
+      if (!launched("parents")) return st_;
+    }
+    q.first = alloc<uint32_t>(q.n);
+    q.count = alloc<uint32_t>(q.n);
+    if (!q.first || !q.count) return st_;
+    hipLaunchKernelGGL(k_child_first, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first);
+    hipLaunchKernelGGL(k_child_count, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first, q.count);
+    if (!launched("child runs")) return st_;
+  }
+  // 3. sub-volume of every SVDAG node (top-down)
+  if (!S.wld) {
+    for (int i = 0; i <= dl; ++i) {
+      const DepthInfo& di = L.d[i];
+      if (S.lv[di.level].kind != LK_DAG) continue;
+      DepthState& q = D[i];
+      if (!(q.group = alloc<uint32_t>(q.n))) return st_;
+      if (di.j == 0)
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.group, q.n);
+      else
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(q.n)), dim3(TB), 0, s_, D[i - 1].group, q.parent, q.n, q.group);
+      if (!launched("groups")) return st_;
+    }
+  }
+  // 4. word offsets inside every depth, bottom-up
+  for (int i = dl; i >= 0; --i) {
+    const DepthInfo& di = L.d[i];
+    DepthState& q = D[i];
+    const bool kids = i < dl;  // children at depth i + 1 (else voxels)
+    if (is_brick(di) || di.nk == NK_RAW_PTR) {
+      const int sw = di.w[0] + di.w[1] + di.w[2];
+      const uint64_t per = is_brick(di) ? (2ull << (di.nk == NK_BLOCKS ? sw : 0)) : (1ull << sw);
+      q.words = q.n * per;
+      q.stored = q.n;
+      if (q.words >= (1ull << 32)) return fail(HVF_E_OVERFLOW, "format needs 2^32 words or more"), st_;
+      if (!(q.id = alloc<uint32_t>(q.n))) return st_;
+      hipLaunchKernelGGL(k_stride_ids, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.id, q.n, (uint32_t)per);
+      if (!launched("ids")) return st_;
+      continue;
+    }
+    if (!is_octree(di)) return fail(HVF_E_UNSUPPORTED, "node kind not built on the device"), st_;
+    if (!(q.masks = alloc<uint32_t>(q.n)) || !hip(hipMemsetAsync(q.masks, 0, q.n * sizeof(uint32_t), s_), "memset"))
+      return st_;
+    if (kids) {
+      const DepthState& c = D[i + 1];
+      hipLaunchKernelGGL(k_valid, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.parent, c.n, q.masks);
+    } else {
+      hipLaunchKernelGGL(k_valid_voxels, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, code_rank, n_, q.masks);
+    }
+    const int deepest = di.nk == NK_OCT_FINAL || di.nk == NK_OCT_PTR;
+    hipLaunchKernelGGL(k_masks, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.masks, q.n, deepest);
+    if (!launched("masks")) return st_;
+    if (di.hk == HK_SVO) {
+      q.words = 2ull * q.n;
+      q.stored = q.n;
+      q.aux = (di.nk == NK_OCT_PTR) ? D[i + 1].n : 0;
+      if (!(q.id = alloc<uint32_t>(q.n))) return st_;
+      hipLaunchKernelGGL(k_stride_ids, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.id, q.n, 2u);
+      if (!launched("ids")) return st_;
+    } else if (!dedup(i, D, kids)) {
+      return st_;
+    }
+    if (q.words >= (1ull << 32)) return fail(HVF_E_OVERFLOW, "format needs 2^32 words or more"), st_;
+  }
+  // 5. placement: depths in order, each at a 64-byte boundary, pointer arrays after them
+  std::vector<uint64_t> base(nd), auxb(nd);
+  uint64_t cur = 1;
+  for (int i = 0; i < nd; ++i) {
+    cur = (cur + 15) & ~15ull;
+    base[i] = cur;
+    cur += D[i].words;
+    auxb[i] = cur;
+    cur += D[i].aux;
+  }
+  if (cur >= (1ull << 32))
+    return fail(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond 32-bit word offsets"), st_;
+  const size_t total = (size_t)cur + HVF_BUFFER_PAD_WORDS;
+  if (!hip(hipMalloc(&buf_, total * sizeof(uint32_t)), "hipMalloc of the word buffer") ||
+      !hip(hipMemsetAsync(buf_, 0, total * sizeof(uint32_t), s_), "hipMemsetAsync"))
+    return st_;
+  // 6. node words with absolute child offsets
+  for (int i = 0; i <= dl; ++i) {
+    const DepthInfo& di = L.d[i];
+    const DepthState& q = D[i];
+    uint32_t* dst = buf_ + base[i];
+    const uint32_t nb = (i + 1 < nd) ? (uint32_t)base[i + 1] : 0u;
+    if (is_brick(di)) {
+      const int wx = di.nk == NK_BLOCKS ? di.w[0] : 0, wy = di.nk == NK_BLOCKS ? di.w[1] : 0;
+      const int wz = di.nk == NK_BLOCKS ? di.w[2] : 0;
+      const uint64_t stride = 2ull << (wx + wy + wz);
+      hipLaunchKernelGGL(k_write_bricks, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, i == 0 ? nullptr : code_rank,
+                         n_, q.ns, L.brick_b, wx, wy, stride, dst);
+    } else if (di.nk == NK_RAW_PTR) {
+      const DepthState& c = D[i + 1];
+      const uint64_t cells = 1ull << (di.w[0] + di.w[1] + di.w[2]);
+      hipLaunchKernelGGL(k_write_raw, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, i == 0 ? nullptr : c.parent, c.id,
+                         c.n, di.w[0], di.w[1], i == 0 ? 1 : 0, cells, nb, dst);
+    } else if (di.hk == HK_SVO) {
+      const int mode = di.nk == NK_SVO_INNER ? 1 : (di.nk == NK_OCT_PTR ? 2 : 0);
+      const uint32_t target = mode == 1 ? nb : (uint32_t)auxb[i];
+      hipLaunchKernelGGL(k_write_svo, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.masks, q.first,
+                         mode == 1 ? D[i + 1].id : nullptr, q.n, mode, target, dst);
+      if (mode == 2)
+        hipLaunchKernelGGL(k_write_ptrs, dim3(grid_for(D[i + 1].n)), dim3(TB), 0, s_, D[i + 1].id, D[i + 1].n, nb,
+                           buf_ + auxb[i]);
+    } else {
+      const bool kids = i < dl && di.nk != NK_OCT_FINAL;
+      DagView V{q.masks, kids ? q.first : nullptr, kids ? q.count : nullptr, kids ? D[i + 1].id : nullptr, nullptr};
+      const int inner = di.nk == NK_DAG_INNER;
+      hipLaunchKernelGGL(k_write_dag, dim3(grid_for(q.n)), dim3(TB), 0, s_, V, q.canon, q.id,
+                         inner ? D[i + 1].masks : nullptr, q.n, inner, nb, dst);
+    }
+    if (!launched("write")) return st_;
+  }
+  const uint32_t root = (uint32_t)base[0];  // the root is the first node of depth 0
+  if (!hip(hipMemcpyAsync(buf_, &root, sizeof(uint32_t), hipMemcpyHostToDevice, s_), "hipMemcpyAsync")) return st_;
+  // 7. host copy and statistics
+  try {
+    B.words.assign((size_t)cur, 0u);
+  } catch (const std::bad_alloc&) {
+    return fail(HVF_E_NOMEM, "host allocation failed"), st_;
+  }
+  if (!hip(hipMemcpyAsync(B.words.data(), buf_, (size_t)cur * sizeof(uint32_t), hipMemcpyDeviceToHost, s_),
+           "download of the word buffer") ||
+      !hip(hipStreamSynchronize(s_), "hipStreamSynchronize"))
+    return st_;
+  B.nvox = n_;
+  B.depth_nodes.assign(nd, 0);
+  B.depth_offset.assign(nd, 0);
+  B.depth_words.assign(nd, 0);
+  B.level_nodes.assign(S.lv.size(), 0);
+  for (int i = 0; i < nd; ++i) {
+    B.depth_nodes[i] = D[i].stored;
+    B.depth_offset[i] = base[i];
+    B.depth_words[i] = D[i].words + D[i].aux;
+    B.level_nodes[L.d[i].level] += D[i].stored;
+  }
+  *dbuf = buf_;
+  buf_ = nullptr;
+  return HVF_OK;
+}
+
+}  // namespace
+}  // namespace hvf
+
+namespace {
+hvf_status devbuild_fail(hvf_status s, const std::string& m) {
+  hvf_set_error(m);
+  return s;
+}
+}  // namespace
+
+extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* d_morton, size_t n, void* stream,
+                                       hvf_volume** out) {
+  if (!out) return devbuild_fail(HVF_E_INPUT, "null output handle pointer");
+  *out = nullptr;
+  hvf::Spec spec;
+  std::string err;
+  hvf_status st = hvf::parse_spec(format_spec, spec, err);
+  if (st != HVF_OK) return devbuild_fail(st, err);
+  for (const hvf::LevelSpec& lv : spec.lv)
+    if (lv.maxd) return devbuild_fail(HVF_E_UNSUPPORTED, "distance-field levels are built on the host only");
+  if (n && !d_morton) return devbuild_fail(HVF_E_INPUT, "null Morton code array");
+  if (n > (size_t)INT_MAX) return devbuild_fail(HVF_E_UNSUPPORTED, "a device construction takes fewer than 2^31 codes");
+  hvf_volume* v = new (std::nothrow) hvf_volume();
+  if (!v) return devbuild_fail(HVF_E_NOMEM, "host allocation failed");
+  v->spec = spec;
+  v->layout = hvf::make_layout(spec);
+  if (n == 0) {
+    st = hvf::build_words(v->spec, v->layout, nullptr, 0, v->built, err);
+    if (st == HVF_OK) st = hvf_upload(v, stream);
+    if (st != HVF_OK) {
+      hvf_free(v);
+      return st;
+    }
+    *out = v;
+    return HVF_OK;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    hvf_free(v);
+    return devbuild_fail(HVF_E_DEVICE, "hipGetDevice failed");
+  }
+  uint32_t* dbuf = nullptr;
+  {
+    hvf::DeviceBuilder b(v->spec, v->layout, d_morton, n, (hipStream_t)stream);
+    st = b.run(v->built, &dbuf);
+    if (st != HVF_OK) {
+      const std::string m = b.error();
+      hvf_free(v);
+      return devbuild_fail(st, m);
+    }
+  }
+  v->dbuf = dbuf;
+  v->device = dev;
+  *out = v;
+  return HVF_OK;
+}

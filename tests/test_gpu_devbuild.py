@@ -1,0 +1,136 @@
+"""Device construction (hvf_build_device) through the C-ABI.
+
+A device-built volume must hold the host builder's word buffer word for word (same
+layout, same SVDAG de-duplication, same statistics), and tracing it must match the
+oracle element by element (hit and xyz bit-exact, t within 1e-6 relative).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_util import compare, gpu_trace
+from tests.test_oracle_pins import EDGE_CASES, EDGE_SPECS, EDGE_VOX, SPECS_8, codes_of
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2410_14128_amd as H
+    H.lib()
+    return H
+
+
+def dev_codes(codes):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(codes, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def same_volume(H, spec, codes):
+    host = H.Volume(spec, codes)
+    dev = H.Volume.from_device(spec, dev_codes(codes))
+    wh, wd = host.words(), dev.words()
+    assert len(wh) == len(wd), f"{spec}: {len(wd)} words, host {len(wh)}"
+    bad = np.nonzero(wh != wd)[0]
+    assert len(bad) == 0, f"{spec}: {len(bad)} words differ, first at {bad[:5].tolist()}: " \
+                          f"{wd[bad[:5]].tolist()} vs host {wh[bad[:5]].tolist()}"
+    ih, idv = host.info(), dev.info()
+    for k in ("num_words", "depth_nodes", "depth_offset", "level_nodes", "num_voxels", "kernel_family"):
+        assert ih[k] == idv[k], (spec, k, ih[k], idv[k])
+    return host, dev
+
+
+@pytest.mark.parametrize("spec", SPECS_8)
+def test_every_type_sequence_words(H, spec):
+    for seed, p in ((1, 0.05), (2, 0.2), (3, 0.6), (4, 1.0)):
+        same_volume(H, spec, W.scene_bernoulli(seed, 3, 3, 3, p))
+
+
+@pytest.mark.parametrize("spec", ["R(1,0,2) R(2,2,2)", "R(3,2,4)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)",
+                                  "R(0,0,0) R(2,2,2)", "R(2,1,0) G(2) --whole-level-dedup", "R(1,1,1)", "S(1)",
+                                  "G(1)", "R(0,1,2) R(1,1,1)"])
+def test_noncubic_and_tiny_tops(H, spec):
+    ex = H.Volume(spec).info()["extent_log2"]
+    for seed, p in ((5, 0.1), (6, 0.5)):
+        same_volume(H, spec, W.scene_bernoulli(seed, ex[0], ex[1], ex[2], p))
+
+
+@pytest.mark.parametrize("spec", ["G(6)", "G(3) G(3)", "G(6) --whole-level-dedup", "G(3) G(3) --whole-level-dedup",
+                                  "S(2) G(4)", "G(4) R(2,2,2)", "R(2,2,2) G(2) R(2,2,2)"])
+def test_repetitive_scene_dedup(H, spec):
+    """A periodic pattern: many equal subtrees, inside and across sub-volumes."""
+    xyz = np.stack(np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij"), -1).reshape(-1, 3)
+    keep = ((xyz[:, 0] % 8) < 3) & ((xyz[:, 1] % 4) != 1) & (((xyz[:, 2] + xyz[:, 0] // 16) % 8) < 5)
+    codes = np.sort(W.morton_encode(xyz[keep].astype(np.uint32)))
+    host, dev = same_volume(H, spec, codes)
+    if spec.startswith("G(6)"):
+        assert host.info()["depth_nodes"][3] < 64  # de-duplication did merge nodes
+
+
+def test_scenes_256(H):
+    codes = W.scene_shell(4, 8, 12, 6, 1.2)
+    for spec in ["R(4,4,4) R(4,4,4)", "S(8)", "G(8)", "G(8) --whole-level-dedup", "R(6,6,6) G(2)",
+                 "S(4) G(2) R(2,2,2)", "G(5) R(3,3,3)", "R(2,2,2) S(3) G(3) --whole-level-dedup"]:
+        same_volume(H, spec, codes)
+
+
+def test_surface_512_formats(H):
+    codes = C.scene(C.SURF512)
+    for spec in C.SURF512["specs"]:
+        same_volume(H, spec, codes)
+
+
+def test_trace_device_built_against_oracle(H):
+    codes = W.scene_solid_noise(1, log2n=6, n_sph=8, rmin=4, rmax=16, noise=0.05)
+    rays = W.camera_rays(1, 0, (64, 64, 64), 128, 128)
+    for spec in ["R(2,2,2) S(2) R(2,2,2)", "G(4) R(2,2,2)", "S(2) G(4) --whole-level-dedup"]:
+        dev = H.Volume.from_device(spec, dev_codes(codes))
+        got = gpu_trace(dev, rays)
+        ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
+        assert compare(got, ref, spec) == 0
+
+
+@pytest.mark.parametrize("spec", EDGE_SPECS)
+def test_edge_suite_device_built(H, spec):
+    codes = codes_of(EDGE_VOX)
+    rays = np.concatenate([r for r, _ in EDGE_CASES])
+    got = gpu_trace(H.Volume.from_device(spec, dev_codes(codes)), rays)
+    ref = oracle.Volume(spec, codes).trace(rays)
+    assert compare(got, ref, spec) == 0
+
+
+def test_empty_single_and_full(H):
+    for spec in ["R(3,3,3)", "G(3)", "S(1) R(2,2,2)"]:
+        same_volume(H, spec, np.zeros(0, np.uint64))
+        same_volume(H, spec, np.array([0], np.uint64))
+        same_volume(H, spec, np.array([511], np.uint64))
+        same_volume(H, spec, np.arange(512, dtype=np.uint64))
+
+
+def test_errors(H):
+    import torch
+    codes = W.scene_bernoulli(1, 3, 3, 3, 0.3)
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("R(3,3,3)", dev_codes(codes[::-1].copy()))
+    assert e.value.name == "HVF_E_INPUT"
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("R(2,2,2)", dev_codes(codes))  # codes beyond a 4^3 volume
+    assert e.value.name == "HVF_E_INPUT"
+    dup = np.concatenate([codes[:3], codes[2:]])
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("R(3,3,3)", dev_codes(dup))
+    assert e.value.name == "HVF_E_INPUT"
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("D(3,3,3,4)", dev_codes(codes))
+    assert e.value.name == "HVF_E_UNSUPPORTED"
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("Q(3)", dev_codes(codes))
+    assert e.value.name == "HVF_E_SPEC"
+    with pytest.raises(TypeError):
+        H.Volume.from_device("R(3,3,3)", torch.from_numpy(codes.view(np.int64)))
+    # the failed calls leave nothing behind: a build right after still matches
+    same_volume(H, "G(3)", codes)
