@@ -302,6 +302,47 @@ def run_sweep(args, torch, H, W, C):
     return out
 
 
+def run_construction(args, torch, H, C, formats_2048=None):
+    """Format construction from sorted Morton codes: the host builder plus the upload of its
+    buffer, against hvf_build_device on codes already resident on the device (median of
+    three builds each; the device figure includes the download of the host copy). The two
+    word buffers are compared word for word."""
+    out = []
+    specs = formats_2048 or [C.table_spec(sp) for _, k, sp in C.TABLE_FORMATS if k == 11 and "D(" not in sp]
+    for cfg, fmts in ((C.SURF512, C.SURF512["specs"]), (C.SURF2048, specs)):
+        codes = C.scene(cfg)
+        d_codes = torch.from_numpy(codes.view(np.int64)).cuda()
+        H.Volume.from_device("S(3)", d_codes[:1] * 0).close()  # load the construction kernels
+        for sp in fmts:
+            th, td = [], []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                vh = H.Volume(sp, codes)
+                vh.upload()
+                torch.cuda.synchronize()
+                th.append(time.perf_counter() - t0)
+                t0 = time.perf_counter()
+                vd = H.Volume.from_device(sp, d_codes)
+                torch.cuda.synchronize()
+                td.append(time.perf_counter() - t0)
+                same = bool(np.array_equal(vh.words(), vd.words()))
+                nbytes = vh.info()["bytes"]
+                vh.close()
+                vd.close()
+                if not same:
+                    raise RuntimeError(f"device construction differs from the host builder for {sp}")
+            rec = {"format": sp, "side": 1 << cfg["log2n"], "voxels": int(len(codes)), "bytes": nbytes,
+                   "host_ms": round(1e3 * float(np.median(th)), 2), "device_ms": round(1e3 * float(np.median(td)), 2),
+                   "identical": same}
+            rec["speedup"] = round(rec["host_ms"] / rec["device_ms"], 1)
+            log(f"[bench] build {rec['side']:4d}^3 {sp:44s} {nbytes / 2 ** 20:8.1f} MiB  host+upload "
+                f"{rec['host_ms']:8.1f} ms  device {rec['device_ms']:7.1f} ms  x{rec['speedup']}")
+            out.append(rec)
+        del d_codes
+    return out
+
+
 def run_surface2048(args, torch, H, W, C):
     cfg = C.SURF2048
     n = 1 << cfg["log2n"]
@@ -569,11 +610,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-df", action="store_true", help="skip the distance-field format leg")
+    ap.add_argument("--no-build", action="store_true", help="skip the construction (host vs device) leg")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep"],
+    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep", "build"],
                     default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
@@ -610,6 +652,9 @@ def main():
     if args.only == "batched":
         run_batched(args, torch, H, W, C)
         return
+    if args.only == "build":
+        print(json.dumps({"construction": run_construction(args, torch, H, C)}))
+        return
     if args.only == "served":
         print(json.dumps(run_served(args, torch, H, W, C)))
         return
@@ -630,6 +675,9 @@ def main():
     served = None
     if not args.no_served:
         served = run_served(args, torch, H, W, C)
+    construction = None
+    if not args.no_build:
+        construction = run_construction(args, torch, H, C, formats_2048=C.BUILD_2048)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(res, C, args.cpu_rays)
@@ -648,6 +696,7 @@ def main():
         "distance_field_512": df,
         "batched": batched,
         "served": served,
+        "construction": construction,
         "kernel_hash": kernel_source_hash(),
     }
     print(json.dumps(line))

@@ -133,8 +133,9 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
  *   z bit 2 of each 3-bit group), all inside the volume; n < 2^31. Read only, not retained.
  * out: receives a new handle owned by the caller (release with hvf_free); its device
  *   buffer is already resident on the current device (no upload needed).
- * Synchronises hip_stream before returning; temporary device memory (a few words per code
- * and per node) is freed before returning.
+ * Synchronises hip_stream before returning; temporary device memory (about 40 bytes per
+ * code) is freed before returning. The host copy of the words (hvf_words, hvf_save) is
+ * downloaded from the device buffer when first read.
  * Errors: HVF_E_SPEC, HVF_E_INPUT (null pointers, codes not ascending or outside the
  * volume), HVF_E_OVERFLOW, HVF_E_NOMEM, HVF_E_DEVICE, HVF_E_UNSUPPORTED. */
 hvf_status hvf_build_device(const char* format_spec, const uint64_t* d_morton, size_t n, void* hip_stream,

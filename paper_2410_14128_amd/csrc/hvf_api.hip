@@ -301,6 +301,41 @@ hvf_status hvf_trace_host(hvf_volume* v, const hvf_ray* rays, size_t n, hvf_hit*
   return st;
 }
 
+}  // extern "C"
+
+namespace hvf {
+hvf_status host_words(const hvf_volume* v) {
+  std::lock_guard<std::mutex> g(v->host_mu);
+  if (!v->host_pending) return HVF_OK;
+  hvf_volume* m = const_cast<hvf_volume*>(v);
+  try {
+    m->built.words.assign(v->pending_words, 0u);
+  } catch (const std::bad_alloc&) {
+    return fail(HVF_E_NOMEM, "host allocation failed");
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  const bool other = e == hipSuccess && cur != v->device;
+  if (other) e = hipSetDevice(v->device);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->built.words.data(), v->dbuf, v->pending_words * sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (other) (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    m->built.words.clear();
+    return hip_fail(e, "download of the word buffer");
+  }
+  m->host_pending = false;
+  return HVF_OK;
+}
+
+size_t word_count(const hvf_volume* v) {
+  std::lock_guard<std::mutex> g(v->host_mu);
+  return v->host_pending ? v->pending_words : v->built.words.size();
+}
+}  // namespace hvf
+
+extern "C" {
+
 hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
   if (!v || !out) return fail(HVF_E_INPUT, "null argument");
   hvf_info I;
@@ -316,7 +351,7 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
   for (int a = 0; a < 3; ++a) I.extent_log2[a] = v->spec.ext[a];
   I.whole_level_dedup = v->spec.wld ? 1 : 0;
   I.num_depths = (int32_t)v->layout.d.size();
-  I.num_words = v->built.words.size();
+  I.num_words = hvf::word_count(v);
   for (size_t d = 0; d < v->layout.d.size() && d < HVF_MAX_DEPTH; ++d) {
     I.depth_nodes[d] = d < v->built.depth_nodes.size() ? v->built.depth_nodes[d] : 0;
     I.depth_offset[d] = d < v->built.depth_offset.size() ? v->built.depth_offset[d] : 0;
@@ -329,7 +364,11 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
 
 hvf_status hvf_words(const hvf_volume* v, uint32_t* words, size_t cap, size_t* n_words) {
   if (!v || !n_words) return fail(HVF_E_INPUT, "null argument");
-  const size_t n = v->built.words.size();
+  if (words) {
+    const hvf_status st = hvf::host_words(v);
+    if (st != HVF_OK) return st;
+  }
+  const size_t n = hvf::word_count(v);
   if (words) std::memcpy(words, v->built.words.data(), (cap < n ? cap : n) * sizeof(uint32_t));
   *n_words = n;
   return HVF_OK;
@@ -354,6 +393,8 @@ struct HashedFile {
 
 hvf_status hvf_save(const hvf_volume* v, const char* path) {
   if (!v || !path) return fail(HVF_E_INPUT, "null argument");
+  const hvf_status hst = hvf::host_words(v);
+  if (hst != HVF_OK) return hst;
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(HVF_E_INPUT, std::string("cannot open ") + path);
   const hvf::Built& B = v->built;

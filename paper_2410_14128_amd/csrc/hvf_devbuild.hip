@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
+#include <algorithm>
 #include <climits>
 #include <new>
 #include <string>
@@ -109,28 +110,30 @@ __global__ void k_child_count(const uint32_t* __restrict__ par, size_t nc, const
   if (j + 1 == nc || par[j + 1] != p) count[p] = (uint32_t)(j + 1) - first[p];
 }
 
-// Octree child masks: bit (child key & 7) of the parent; at the deepest depth of the last
-// level the children are voxels (node = rank - 1, or the root when rank is null).
-__global__ void k_valid(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ par, size_t nc,
-                        uint32_t* __restrict__ valid) {
-  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
-  if (j >= nc) return;
-  atomicOr(&valid[par ? par[j] : 0u], 1u << (uint32_t)(ckey[j] & 7u));
+// Octree mask words (child mask, also the leaf mask at a level's deepest depth): bit
+// (child key & 7) for every child in the node's run of children.
+__global__ void k_masks_children(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ first,
+                                 const uint32_t* __restrict__ count, size_t n, int deepest,
+                                 uint32_t* __restrict__ masks) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  const uint32_t f = first[x], c = count[x];
+  uint32_t v = 0;
+  for (uint32_t t = 0; t < c; ++t) v |= 1u << (uint32_t)(ckey[f + t] & 7u);
+  masks[x] = v | (deepest ? (v << 8) : 0u);
 }
 
-__global__ void k_valid_voxels(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
-                               uint32_t* __restrict__ valid) {
+// The same at the last level's deepest depth, whose children are voxels: the first code of
+// every node (node = rank - 1; the root when rank is null) ORs the node's run of codes.
+__global__ void k_masks_voxels(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
+                               uint32_t* __restrict__ masks) {
   const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
   if (i >= n) return;
-  atomicOr(&valid[rank ? rank[i] - 1u : 0u], 1u << (uint32_t)(codes[i] & 7u));
-}
-
-// Mask word of an octree node: child mask, and as leaf mask too at a level's deepest depth.
-__global__ void k_masks(uint32_t* __restrict__ valid, size_t n, int deepest) {
-  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t v = valid[i];
-  valid[i] = v | (deepest ? (v << 8) : 0u);
+  const uint32_t r = rank ? rank[i] : 1u;
+  if (i > 0 && (!rank || rank[i - 1] == r)) return;
+  uint32_t v = 0;
+  for (size_t j = i; j < n && j < i + 8 && (!rank || rank[j] == r); ++j) v |= 1u << (uint32_t)(codes[j] & 7u);
+  masks[r - 1u] = v | (v << 8);
 }
 
 // ---------------------------------------------------------------- SVDAG de-duplication
@@ -220,19 +223,31 @@ __global__ void k_dag_ids(const uint32_t* __restrict__ canon, const uint64_t* __
 }
 
 // ---------------------------------------------------------------- writing the buffer
-// Bricks of the last Raw level: one bit per voxel in the 64-bit mask of its block.
+// Bricks of the last Raw level: one bit per voxel in the 64-bit mask of its block. A
+// block is an aligned cube of side 2^b, so its voxels are one run of codes with equal
+// code >> 3b; the run's first code builds both mask words and stores them.
 __global__ void k_write_bricks(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
                                int ns, int b, int wx, int wy, uint64_t stride, uint32_t* __restrict__ dst) {
   const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
   if (i >= n) return;
   const uint64_t c = codes[i];
+  const uint64_t blk_key = c >> (3 * b);
+  if (i > 0 && (codes[i - 1] >> (3 * b)) == blk_key) return;
   const uint64_t local = rank ? (c & ((1ull << (3 * ns)) - 1ull)) : c;
   const uint64_t lx = coord_of(local), ly = coord_of(local >> 1), lz = coord_of(local >> 2);
-  const uint64_t m = (1ull << b) - 1ull;
   const uint64_t blk = (lx >> b) | ((ly >> b) << wx) | ((lz >> b) << (wx + wy));
-  const uint64_t bit = (lx & m) | ((ly & m) << b) | ((lz & m) << (2 * b));
+  const uint64_t m = (1ull << b) - 1ull;
+  const uint64_t span = 1ull << (3 * b);
+  uint32_t w[2] = {0u, 0u};
+  for (size_t j = i; j < n && j < i + span && (codes[j] >> (3 * b)) == blk_key; ++j) {
+    const uint64_t v = codes[j];
+    const uint64_t bit = (coord_of(v) & m) | ((coord_of(v >> 1) & m) << b) | ((coord_of(v >> 2) & m) << (2 * b));
+    w[bit >> 5] |= 1u << (uint32_t)(bit & 31u);
+  }
   const uint64_t node = rank ? rank[i] - 1u : 0u;
-  atomicOr(&dst[node * stride + 2 * blk + (bit >> 5)], 1u << (uint32_t)(bit & 31u));
+  uint32_t* o = dst + node * stride + 2 * blk;
+  o[0] = w[0];
+  o[1] = w[1];
 }
 
 // Raw pointer grids: the cell of each child holds its absolute word offset (0 = empty).
@@ -313,11 +328,11 @@ class DeviceBuilder {
   DeviceBuilder(const Spec& s, const Layout& l, const uint64_t* codes, size_t n, hipStream_t st)
       : S(s), L(l), codes_(codes), n_(n), s_(st) {}
   ~DeviceBuilder() {
-    for (void* p : owned_) (void)hipFree(p);
+    for (void* p : chunks_) (void)hipFree(p);
     if (buf_) (void)hipFree(buf_);
   }
 
-  hvf_status run(Built& B, uint32_t** dbuf);
+  hvf_status run(Built& B, uint32_t** dbuf, size_t* nwords);
   const std::string& error() const { return err_; }
 
  private:
@@ -326,7 +341,11 @@ class DeviceBuilder {
   const uint64_t* codes_;
   size_t n_;
   hipStream_t s_;
-  std::vector<void*> owned_;
+  // Temporaries come from a few large chunks (a bump allocator), all freed at the end:
+  // one hipMalloc per array would cost more than the construction's kernels.
+  std::vector<void*> chunks_;
+  char* chunk_ = nullptr;
+  size_t left_ = 0;
   void* tmp_ = nullptr;
   size_t tmp_bytes_ = 0;
   uint32_t* buf_ = nullptr;
@@ -348,11 +367,20 @@ class DeviceBuilder {
   bool launched(const char* what) { return hip(hipGetLastError(), what); }
   template <class T>
   T* alloc(size_t count) {
-    void* p = nullptr;
-    const hipError_t e = hipMalloc(&p, (count ? count : 1) * sizeof(T));
-    if (!hip(e, "hipMalloc")) return nullptr;
-    owned_.push_back(p);
-    return static_cast<T*>(p);
+    const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (bytes > left_) {
+      // Chunks of about 40 bytes per code: enough for the deepest depths' arrays at once.
+      const size_t size = std::max(bytes, (size_t)40 * n_ + ((size_t)8 << 20));
+      void* p = nullptr;
+      if (!hip(hipMalloc(&p, size), "hipMalloc of construction temporaries")) return nullptr;
+      chunks_.push_back(p);
+      chunk_ = static_cast<char*>(p);
+      left_ = size;
+    }
+    void* r = chunk_;
+    chunk_ += bytes;
+    left_ -= bytes;
+    return static_cast<T*>(r);
   }
   bool scratch(size_t bytes) {
     if (bytes <= tmp_bytes_) return true;
@@ -452,7 +480,7 @@ bool DeviceBuilder::dedup(int i, std::vector<DepthState>& D, bool has_children) 
   return true;
 }
 
-hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf) {
+hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   const int nd = (int)L.d.size();
   std::vector<DepthState> D(nd);
   for (int i = 1; i < nd; ++i) D[i].ns = L.d[i].cs + L.d[i].w[0];
@@ -548,16 +576,13 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf) {
       continue;
     }
     if (!is_octree(di)) return fail(HVF_E_UNSUPPORTED, "node kind not built on the device"), st_;
-    if (!(q.masks = alloc<uint32_t>(q.n)) || !hip(hipMemsetAsync(q.masks, 0, q.n * sizeof(uint32_t), s_), "memset"))
-      return st_;
-    if (kids) {
-      const DepthState& c = D[i + 1];
-      hipLaunchKernelGGL(k_valid, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.parent, c.n, q.masks);
-    } else {
-      hipLaunchKernelGGL(k_valid_voxels, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, code_rank, n_, q.masks);
-    }
+    if (!(q.masks = alloc<uint32_t>(q.n))) return st_;
     const int deepest = di.nk == NK_OCT_FINAL || di.nk == NK_OCT_PTR;
-    hipLaunchKernelGGL(k_masks, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.masks, q.n, deepest);
+    if (kids)
+      hipLaunchKernelGGL(k_masks_children, dim3(grid_for(q.n)), dim3(TB), 0, s_, D[i + 1].keys, q.first, q.count, q.n,
+                         deepest, q.masks);
+    else
+      hipLaunchKernelGGL(k_masks_voxels, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, code_rank, n_, q.masks);
     if (!launched("masks")) return st_;
     if (di.hk == HK_SVO) {
       q.words = 2ull * q.n;
@@ -623,16 +648,8 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf) {
   }
   const uint32_t root = (uint32_t)base[0];  // the root is the first node of depth 0
   if (!hip(hipMemcpyAsync(buf_, &root, sizeof(uint32_t), hipMemcpyHostToDevice, s_), "hipMemcpyAsync")) return st_;
-  // 7. host copy and statistics
-  try {
-    B.words.assign((size_t)cur, 0u);
-  } catch (const std::bad_alloc&) {
-    return fail(HVF_E_NOMEM, "host allocation failed"), st_;
-  }
-  if (!hip(hipMemcpyAsync(B.words.data(), buf_, (size_t)cur * sizeof(uint32_t), hipMemcpyDeviceToHost, s_),
-           "download of the word buffer") ||
-      !hip(hipStreamSynchronize(s_), "hipStreamSynchronize"))
-    return st_;
+  if (!hip(hipStreamSynchronize(s_), "hipStreamSynchronize")) return st_;
+  // 7. statistics (the host copy of the words is downloaded when first read)
   B.nvox = n_;
   B.depth_nodes.assign(nd, 0);
   B.depth_offset.assign(nd, 0);
@@ -644,6 +661,7 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf) {
     B.depth_words[i] = D[i].words + D[i].aux;
     B.level_nodes[L.d[i].level] += D[i].stored;
   }
+  *nwords = (size_t)cur;
   *dbuf = buf_;
   buf_ = nullptr;
   return HVF_OK;
@@ -691,9 +709,10 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
     return devbuild_fail(HVF_E_DEVICE, "hipGetDevice failed");
   }
   uint32_t* dbuf = nullptr;
+  size_t nwords = 0;
   {
     hvf::DeviceBuilder b(v->spec, v->layout, d_morton, n, (hipStream_t)stream);
-    st = b.run(v->built, &dbuf);
+    st = b.run(v->built, &dbuf, &nwords);
     if (st != HVF_OK) {
       const std::string m = b.error();
       hvf_free(v);
@@ -702,6 +721,8 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   }
   v->dbuf = dbuf;
   v->device = dev;
+  v->host_pending = true;
+  v->pending_words = nwords;
   *out = v;
   return HVF_OK;
 }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -184,7 +185,19 @@ struct hvf_volume {
   hvf_schedule sched{0, 16, 8, 0, 4, 0, 0, 0};
   uint32_t* dcounters = nullptr;  // device ray counters for persistent launches
   unsigned counter_next = 0;
+  // A volume built on the device keeps built.words empty until a caller reads the host
+  // copy (hvf_words, hvf_save); host_words() downloads it then, once, under host_mu.
+  mutable std::mutex host_mu;
+  bool host_pending = false;
+  size_t pending_words = 0;
 };
+
+namespace hvf {
+// Host copy of the word buffer (downloads it first for a device-built volume).
+hvf_status host_words(const hvf_volume* v);
+// Number of words of the buffer, whether or not the host copy is present.
+size_t word_count(const hvf_volume* v);
+}  // namespace hvf
 
 constexpr int HVF_NUM_COUNTERS = 64;
 // Zero words allocated after a device word buffer, so 8- and 16-byte reads that start at

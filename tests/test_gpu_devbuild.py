@@ -134,3 +134,20 @@ def test_errors(H):
         H.Volume.from_device("R(3,3,3)", torch.from_numpy(codes.view(np.int64)))
     # the failed calls leave nothing behind: a build right after still matches
     same_volume(H, "G(3)", codes)
+
+
+def test_host_copy_on_demand(H, tmp_path):
+    """The host copy of a device-built volume is fetched when first read: size first, then
+    save/load, then the words; a loaded copy traces like the original."""
+    codes = W.scene_shell(2, 7, 6, 3, 1.3)
+    spec = "R(2,2,2) G(3) R(2,2,2)"
+    dev = H.Volume.from_device(spec, dev_codes(codes))
+    host = H.Volume(spec, codes)
+    assert dev.info()["num_words"] == host.info()["num_words"]
+    path = str(tmp_path / "dev.hvf")
+    dev.save(path)
+    back = H.Volume.load(path)
+    assert np.array_equal(back.words(), host.words())
+    assert np.array_equal(dev.words(), host.words())
+    rays = W.random_rays(3, (128, 128, 128), 20000)
+    assert np.array_equal(gpu_trace(back, rays), gpu_trace(dev, rays))

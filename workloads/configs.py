@@ -64,6 +64,10 @@ SURF2048 = dict(name="surface-2048", log2n=11, seed=3, n_sph=96, n_tor=32, scale
                 views=1, specs=["G(7) R(4,4,4) --whole-level-dedup", "S(8) R(3,3,3)"], bounce_seed=33)
 
 
+# Formats of the 2048^3 volume whose construction (host against device) the bench line reports.
+BUILD_2048 = ["S(11)", "G(11) --whole-level-dedup", "R(6,6,6) G(5) --whole-level-dedup", "R(4,4,4) R(4,4,4) R(3,3,3)"]
+
+
 def scene(cfg: dict) -> np.ndarray:
     if cfg["name"].startswith("small"):
         return scene_solid_noise(cfg["seed"], log2n=cfg["log2n"], n_sph=8, rmin=4.0, rmax=16.0, noise=0.05)
