@@ -47,10 +47,15 @@ __device__ __forceinline__ uint32_t di_hk(uint32_t i) { return bf(i, 4, 4); }
 __device__ __forceinline__ int di_cs(uint32_t i) { return (int)bf(i, 8, 4); }
 __device__ __forceinline__ int di_w(uint32_t i, int a) { return (int)bf(i, 12 + 4 * a, 4); }
 
+// After setup, an axis the ray is parallel to (1/d_a not finite) carries o_a = floor(o_a)
+// + 0.5 and 1/d_a = +inf, and its sign bit is clear. Its plane time (p - o_a) * inf is
+// then -inf for every plane p <= floor(o_a) and +inf for every plane above (never NaN: p
+// is an integer, o_a is not), so the generic tests below need no parallel-axis case: a
+// mid-plane test "T(mid) <= t" says whether floor(o_a) lies in the upper half, and a far
+// plane is never crossed.
 struct Ray {
   float o[3], inv[3];
-  uint32_t neg, par;  // bit a set: d_a < 0 / axis a parallel
-  int vo[3];          // floor(o_a) on parallel axes
+  uint32_t neg, par;  // bit a set: d_a < 0 (clear on parallel axes) / axis a parallel
   float t0, t1;
   __device__ __forceinline__ bool is_par(int a) const { return (par >> a) & 1u; }
   __device__ __forceinline__ bool is_neg(int a) const { return (neg >> a) & 1u; }
@@ -63,6 +68,7 @@ __device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const in
   const float o[3] = {r0.x, r0.y, r0.z}, d[3] = {r1.x, r1.y, r1.z};
   bool ok = true;
   R.neg = R.par = 0;
+  float po[3];  // o_a as a parallel axis carries it after the clip
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     ok = ok && isfinite(o[a]) && isfinite(d[a]);
@@ -71,11 +77,11 @@ __device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const in
     const bool par = !isfinite(R.inv[a]);
     R.par |= (uint32_t)par << a;
     R.neg |= (uint32_t)(d[a] < 0.0f) << a;
-    R.vo[a] = 0;
+    po[a] = 0.5f;
     if (par) {
       const bool in = (o[a] >= 0.0f) && (o[a] < (float)(1 << ext[a]));
       ok = ok && in;
-      if (in) R.vo[a] = (int)floorf(o[a]);
+      if (in) po[a] = floorf(o[a]) + 0.5f;  // exact: floor(o_a) < 2^21
     }
   }
   if (!ok || R.par == 7u) return false;
@@ -93,23 +99,26 @@ __device__ __forceinline__ bool setup(const float4 r0, const float4 r1, const in
   }
   R.t0 = fmax_fx(r0.w, tn);
   R.t1 = fmin_fx(r1.w, tf);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (R.is_par(a)) {
+      R.o[a] = po[a];
+      R.inv[a] = INFINITY;
+    }
+  R.neg &= ~R.par;
   return R.t0 < R.t1;
 }
 
 // Narrow the cell position p (aligned to 2^hi on every axis) to the 2^lo-aligned cell
 // that holds the ray at time t: one mid-plane comparison per bit and axis. For d > 0 the
-// upper half holds the ray iff T(mid) <= t; for d < 0 iff t < T(mid); a parallel axis
-// compares floor(o) with mid. Plane times are never NaN once setup has passed.
-// Both comparisons are evaluated and combined with bit operations (a parallel axis's plane
-// time is +-inf or NaN and simply unused), so no per-lane branch is taken.
+// upper half holds the ray iff T(mid) <= t; for d < 0 iff t < T(mid); on a parallel axis
+// the same test compares floor(o) with mid (see Ray). No per-lane branch is taken.
 __device__ __forceinline__ void refine3(const Ray& R, int p[3], int hi, int lo, float t) {
   for (int b = hi - 1; b >= lo; --b) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int mid = p[a] + (1 << b);
-      const bool par = R.is_par(a);
-      const bool cross = (R.T(a, mid) <= t) != R.is_neg(a);
-      const bool up = (cross & !par) | ((R.vo[a] >= mid) & par);
+      const bool up = (R.T(a, mid) <= t) != R.is_neg(a);
       p[a] = up ? mid : p[a];
     }
   }
@@ -281,8 +290,7 @@ struct Walk {
     const int stepv = 1 << cs;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float tt = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);
-      tf[a] = R.is_par(a) ? INFINITY : tt;
+      tf[a] = R.T(a, R.is_neg(a) ? p[a] : p[a] + stepv);  // +inf on a parallel axis
     }
     m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
   }
@@ -311,9 +319,7 @@ struct Walk {
       for (int a = 0; a < 3; ++a) {
         if (b >= F.ext[a]) continue;
         const int mid = p[a] + (1 << b);
-        const bool par = R.is_par(a);
-        const bool cross = (R.T(a, mid) <= R.t0) != R.is_neg(a);
-        const bool up = (cross & !par) | ((R.vo[a] >= mid) & par);
+        const bool up = (R.T(a, mid) <= R.t0) != R.is_neg(a);
         p[a] = up ? mid : p[a];
       }
     }
