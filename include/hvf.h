@@ -91,7 +91,12 @@ typedef struct hvf_info {
  *   traversal steps.
  * sort = 1: trace rays in the order of a coherence key (origin cell of side 2^sort_bits
  *   voxels in Morton order, then direction octant) computed and sorted on the device;
- *   results are still written at each ray's own index. */
+ *   results are still written at each ray's own index.
+ * split = K > 0 (a power of two, 2..64; needs persistent = 0 and sort = 0): every ray walks
+ *   at most split_budget steps; a ray still walking then has the rest of its interval,
+ *   [t, t1), cut into K segments that K lanes walk side by side from the root in a second
+ *   launch, and its result is that of the first segment with one. This shortens the few
+ *   long walks that otherwise keep a launch's last waves busy. */
 typedef struct hvf_schedule {
   int32_t persistent;
   int32_t refill;
@@ -104,6 +109,8 @@ typedef struct hvf_schedule {
   int32_t lds_depths;  /* > 0: every block first copies the nodes of the top lds_depths
                           depths (a prefix of the buffer, at most 32 KiB) into LDS and
                           reads them there; HVF_E_INPUT if the prefix is larger */
+  int32_t split;        /* 0, or K: see above */
+  int32_t split_budget; /* steps of the first launch when split > 0 (1..2^20) */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).

@@ -18,6 +18,8 @@ hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t 
 hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
 hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid);
+hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                              uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                         const hvf_schedule& sc, hipStream_t s);
@@ -113,8 +115,11 @@ hvf_status check_sched(const hvf_schedule& sc) {
   if (sc.persistent < 0 || sc.persistent > 1 || sc.refill < 1 || sc.refill > 64 || sc.inner < 1 || sc.inner > 4096 ||
       sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16 || sc.blocks_per_cu < 0 ||
       sc.blocks_per_cu > 64 || sc.stack_depth < 0 || sc.stack_depth > HVF_MAX_DEPTH || sc.lds_depths < 0 ||
-      sc.lds_depths > HVF_MAX_DEPTH)
+      sc.lds_depths > HVF_MAX_DEPTH || sc.split < 0 || sc.split > 64 || (sc.split & (sc.split - 1)) != 0 ||
+      sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))))
     return fail(HVF_E_INPUT, "schedule field out of range");
+  if (sc.split && (sc.persistent || sc.sort))
+    return fail(HVF_E_INPUT, "the split schedule runs without persistent lanes and without sorting");
   return HVF_OK;
 }
 }  // namespace
@@ -137,6 +142,22 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   hipStream_t s = (hipStream_t)stream;
   const int family = hvf::family_of(v->layout);
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
+  if (sc.split) {
+    const size_t need = 2 + 2 * n;
+    if (need > v->dsplit_words) {
+      if (v->dsplit) (void)hipFree(v->dsplit);
+      v->dsplit = nullptr;
+      v->dsplit_words = 0;
+      hipError_t e = hipMalloc(&v->dsplit, need * sizeof(uint32_t));
+      if (e != hipSuccess) {
+        v->dsplit = nullptr;
+        return hip_fail(e, "hipMalloc of the split survivor list");
+      }
+      v->dsplit_words = need;
+    }
+    return hvf::launch_trace_split(F, family, d_rays, n, d_hits, (uint32_t)sc.split_budget,
+                                   (uint32_t)__builtin_ctz((unsigned)sc.split), v->dsplit, s);
+  }
   uint32_t* counter = nullptr;
   if (sc.persistent) {
     if (!v->dcounters) {
@@ -171,6 +192,8 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
     for (int refill : {8, 32})
       for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, bpc, 0, 0});
   for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, 0, 0, 0});
+  for (int k : {4, 8, 16})
+    for (int budget : {32, 64}) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, k, budget});
   hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");
@@ -485,12 +508,13 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
 
 void hvf_free(hvf_volume* v) {
   if (!v) return;
-  if (v->dbuf || v->dcounters) {
+  if (v->dbuf || v->dcounters || v->dsplit) {
     int cur = 0;
     const bool other = hipGetDevice(&cur) == hipSuccess && v->device >= 0 && cur != v->device;
     if (other) (void)hipSetDevice(v->device);
     if (v->dbuf) (void)hipFree(v->dbuf);
     if (v->dcounters) (void)hipFree(v->dcounters);
+    if (v->dsplit) (void)hipFree(v->dsplit);
     if (other) (void)hipSetDevice(cur);
   }
   delete v;

@@ -185,6 +185,8 @@ struct hvf_volume {
   hvf_schedule sched{0, 16, 8, 0, 4, 0, 0, 0};
   uint32_t* dcounters = nullptr;  // device ray counters for persistent launches
   unsigned counter_next = 0;
+  uint32_t* dsplit = nullptr;  // split schedule: 2 counters + survivor list (grown on demand)
+  size_t dsplit_words = 0;
   // A volume built on the device keeps built.words empty until a caller reads the host
   // copy (hvf_words, hvf_save); host_words() downloads it then, once, under host_mu.
   mutable std::mutex host_mu;

@@ -536,6 +536,38 @@ __device__ __forceinline__ int4 trace_one(const Fmt& fm, uint2* stk, const float
   return out;
 }
 
+// The walk of one ray for at most `budget` steps (0: no limit). A walk still running after
+// them stops with *rest = its t, the entry time of the cell it would test next; the rest
+// of the ray, [t, t1), is then traced by the split pass. *rest < 0 otherwise.
+template <uint32_t FAM>
+__device__ __forceinline__ int4 trace_budget(const Fmt& fm, uint2* stk, const float4 r0, const float4 r1,
+                                             uint32_t budget, float* rest) {
+  int4 out = miss_hit();
+  Walk w;
+  Plain mem;
+  *rest = -1.0f;
+  if (setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
+    while (w.template step<FAM>(fm, stk, out, mem) == RUN)
+      if (w.steps == budget) {
+        *rest = w.t;
+        break;
+      }
+  return out;
+}
+
+// Append the lanes with rest >= 0 to the survivor list (ray index, t): one atomic per wave.
+__device__ __forceinline__ void push_survivor(bool cut, uint32_t i, float rest, uint2* __restrict__ surv,
+                                              uint32_t* __restrict__ nsurv) {
+  const uint64_t cm = __ballot(cut);
+  if (!cut) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const int leader = __ffsll((unsigned long long)cm) - 1;
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(nsurv, (uint32_t)__popcll(cm));
+  base = __shfl(base, leader);
+  surv[base + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull))] = make_uint2(i, __float_as_uint(rest));
+}
+
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                       int4* __restrict__ hits, uint32_t n) {
@@ -549,6 +581,98 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
   hits[i] = F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
                         : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1);
+}
+
+// First pass of the split schedule: trace_kernel with a step budget. Rays that finish
+// write their result; the others join the survivor list for trace_split_kernel.
+template <uint32_t FAM>
+__global__ __launch_bounds__(BLOCK) void trace_budget_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                             int4* __restrict__ hits, uint32_t n, uint32_t budget,
+                                                             uint2* __restrict__ surv, uint32_t* __restrict__ nsurv) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
+  load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  float rest;
+  const int4 out = F.lds_words ? trace_budget<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1, budget, &rest)
+                               : trace_budget<FAM>(fm, stk_all + threadIdx.x, r0, r1, budget, &rest);
+  const bool cut = rest >= 0.0f;
+  if (!cut) hits[i] = out;
+  push_survivor(cut, i, rest, surv, nsurv);
+}
+
+// Boundary k of the split of the rest [tc, t1) of a ray into K segments: tc, t1 at the
+// ends, in between tc + (t1 - tc) * k / K (k / K is exact for a power of two K).
+// Non-decreasing in k and never above t1, so the segments [f(k), f(k + 1)) partition
+// [tc, t1) whatever the rounding.
+__device__ __forceinline__ float split_time(float tc, float t1, uint32_t k, uint32_t K) {
+  if (k == 0u) return tc;
+  if (k == K) return t1;
+  return tc + (t1 - tc) * ((float)k / (float)K);
+}
+
+// Second pass of the split schedule: each survivor's rest [tc, t1) is cut into K segments
+// traced side by side, one lane each, by K consecutive lanes of a wave; each segment is a
+// fresh walk from the root over its own interval. A walk over [a, b) tests every cell
+// entered before b, and plane times are monotone in the plane coordinate, so a walk
+// started at a stands in the cell the whole walk occupies at time a. Hence the result of
+// the ray is that of its first segment with a result, and a miss if none has one. Wave w
+// of the grid takes the groups of 64 / K survivors w, w + (waves in the grid), ... (a
+// fixed stride: a shared work counter would serialise every wave on one address).
+template <uint32_t FAM>
+__device__ __forceinline__ void split_loop(const DevFormat& F, const Fmt& fm, uint2* stk,
+                                           const float4* __restrict__ rays, int4* __restrict__ hits,
+                                           const uint2* __restrict__ surv, uint32_t ns, uint32_t klog2) {
+  const uint32_t lane = threadIdx.x & 63u, K = 1u << klog2, per_wave = 64u >> klog2;
+  const uint32_t k = lane & (K - 1u), g0 = lane & ~(K - 1u);
+  const uint64_t gmask = (K == 64u) ? ~0ull : ((1ull << K) - 1ull);
+  const uint32_t waves = gridDim.x * (BLOCK / 64u), wave = blockIdx.x * (BLOCK / 64u) + threadIdx.x / 64u;
+  for (uint32_t grp = wave;; grp += waves) {
+    const uint32_t base = grp * per_wave;
+    if (base >= ns) break;  // uniform across the wave
+    const uint32_t sidx = base + (lane >> klog2);
+    int4 out = miss_hit();
+    uint32_t ray = 0;
+    if (sidx < ns) {
+      const uint2 sv = surv[sidx];
+      ray = sv.x;
+      const float tc = __uint_as_float(sv.y);
+      const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
+      Walk w;
+      Plain mem;
+      if (setup(r0, r1, fm.ext, w.R)) {
+        const float t1 = w.R.t1;
+        w.R.t0 = split_time(tc, t1, k, K);
+        w.R.t1 = split_time(tc, t1, k + 1u, K);
+        if (w.R.t0 < w.R.t1 && w.template start<FAM>(fm, mem) == RUN)
+          while (w.template step<FAM>(fm, stk, out, mem) == RUN) {
+          }
+      }
+    }
+    const uint64_t gm = (__ballot(out.x != -1) >> g0) & gmask;  // segments with a result
+    const uint32_t first = gm ? (uint32_t)(__ffsll((unsigned long long)gm) - 1) : 0u;
+    if (sidx < ns && k == first) hits[ray] = out;
+  }
+}
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(BLOCK) void trace_split_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                            int4* __restrict__ hits, const uint2* __restrict__ surv,
+                                                            const uint32_t* __restrict__ nsurv, uint32_t klog2) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
+  load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
+  const uint32_t ns = *nsurv;
+  if (F.lds_words)
+    split_loop<FAM | FAM_PRE>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, klog2);
+  else
+    split_loop<FAM>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, klog2);
 }
 
 template <uint32_t FAM>
@@ -839,6 +963,55 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_TRACE)
 #undef HVF_LAUNCH_TRACE
   return launch_check("trace");
+}
+
+hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+
+// The split schedule: trace_budget_kernel over all rays, then trace_split_kernel over the
+// survivors on a device-filling grid. scratch: the survivor count and a spare word (zeroed
+// here), then room for n survivors (8 bytes each), 8-byte aligned.
+hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                              uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s) {
+  if (n == 0) return HVF_OK;
+  if (n >= (1ull << 31)) {
+    hvf_set_error("at most 2^31 - 1 rays per split call");
+    return HVF_E_INPUT;
+  }
+  if (g_cu_count < 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      hvf_set_error("hipGetDeviceProperties failed");
+      return HVF_E_DEVICE;
+    }
+    g_cu_count = prop.multiProcessorCount;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_split_kernel<FAM_ALL>, BLOCK, stack_lds_bytes(F)) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const unsigned grid2 = (unsigned)(g_cu_count * per_cu);
+  uint32_t* nsurv = scratch;
+  uint2* surv = reinterpret_cast<uint2*>(scratch + 2);
+  hvf_status st = launch_fill_u32(scratch, 0u, 2, s);
+  if (st != HVF_OK) return st;
+  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  const float4* r = reinterpret_cast<const float4*>(d_rays);
+  int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_BUDGET(FAMV)                                                                                   \
+  hipLaunchKernelGGL(trace_budget_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
+                     budget, surv, nsurv)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_BUDGET)
+#undef HVF_LAUNCH_BUDGET
+  st = launch_check("budgeted trace");
+  if (st != HVF_OK) return st;
+#define HVF_LAUNCH_SPLIT(FAMV)                                                                                    \
+  hipLaunchKernelGGL(trace_split_kernel<FAMV>, dim3(grid2), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, surv, nsurv, \
+                     klog2)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_SPLIT)
+#undef HVF_LAUNCH_SPLIT
+  return launch_check("split trace");
 }
 
 // Blocks of the persistent kernel per CU (at most blocks_per_cu if > 0) times CUs.

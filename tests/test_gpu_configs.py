@@ -106,6 +106,31 @@ def test_surface2048(H, surf2048, spec):
     assert compare(_trace_full(vol, rnd), ref_r, f"{spec} random") == 0
 
 
+@pytest.mark.parametrize("sd", [dict(split=8, split_budget=32), dict(split=16, split_budget=64),
+                                dict(split=4, split_budget=16, lds_depths=3)], ids=lambda d: str(d))
+def test_surface2048_split_schedule(H, surf2048, sd):
+    """Whole 1080p frames traced with split walks equal the plain schedule bit for bit."""
+    import torch
+    cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
+    vol = H.Volume("G(7) R(4,4,4) --whole-level-dedup", codes)
+    sc = H.schedule(**sd)
+    plain = _trace_full(vol, prim)
+    got = vol.trace(torch.from_numpy(prim).cuda(), sched=sc)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got, plain)
+    assert compare(got[idx], ref_p, f"split {sd} primary") == 0
+    b_full, _ = W.bounce_rays(cfg["bounce_seed"], prim, plain)
+    bp = _trace_full(vol, b_full)
+    bs = vol.trace(torch.from_numpy(b_full).cuda(), sched=sc)
+    torch.cuda.synchronize()
+    assert np.array_equal(bs.cpu().numpy(), bp)
+    for rays, ref, what in ((bounce, ref_b, "bounce"), (rnd, ref_r, "random")):
+        g = vol.trace(torch.from_numpy(rays).cuda(), sched=sc)
+        torch.cuda.synchronize()
+        assert compare(g.cpu().numpy(), ref, f"split {sd} {what}") == 0
+
+
 def test_counting_variant_matches_plain(H, surf512):
     import torch
     cfg, codes, views = surf512

@@ -95,7 +95,10 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(persistent=1, refill=64, inner=64), dict(sort=1, sort_bits=0), dict(sort=1, sort_bits=4),
              dict(sort=1, sort_bits=9), dict(lds_depths=1), dict(lds_depths=2), dict(lds_depths=16),
              dict(lds_depths=3, persistent=1, refill=16, inner=8), dict(lds_depths=2, stack_depth=2),
-             dict(lds_depths=2, sort=1, sort_bits=4)]
+             dict(lds_depths=2, sort=1, sort_bits=4),
+             dict(split=2, split_budget=1), dict(split=4, split_budget=3), dict(split=8, split_budget=8),
+             dict(split=64, split_budget=2), dict(split=16, split_budget=32), dict(split=32, split_budget=5),
+             dict(split=8, split_budget=4, lds_depths=2), dict(split=4, split_budget=2, stack_depth=2)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))

@@ -218,3 +218,18 @@ def test_df_layout_sizes():
     assert c["depth_offset"][0] == d["depth_offset"][0] and c["num_words"] - c["depth_offset"][0] == 4 * 64
     assert d["num_words"] - d["depth_offset"][0] == 2 * 64
     assert a["kinds"] == "DR" and a["level_maxdist"] == [6, 0]
+
+
+def test_schedule_checks_split_fields():
+    """Out-of-range split fields are refused before any device work (no GPU needed)."""
+    import ctypes
+    v = H.Volume("R(3,3,3)", np.array([0, 7, 100], np.uint64))
+    bad = [H.schedule(split=3, split_budget=8), H.schedule(split=1, split_budget=8), H.schedule(split=128, split_budget=8),
+           H.schedule(split=4, split_budget=0), H.schedule(split=4, split_budget=(1 << 20) + 1),
+           H.schedule(split=4, split_budget=8, persistent=1), H.schedule(split=4, split_budget=8, sort=1),
+           H.schedule(split=-2, split_budget=8)]
+    for sc in bad:
+        st = H.lib().hvf_trace_sched(v.handle, None, 1, None, ctypes.byref(sc), None)
+        assert H.STATUS[st] == "HVF_E_INPUT", H.schedule_dict(sc)
+    assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(split=8, split_budget=64))) == [
+        f"trace_budget_kernel<{v.info()['kernel_family']}u>", f"trace_split_kernel<{v.info()['kernel_family']}u>"]
