@@ -134,10 +134,11 @@ def run_surface512(args, torch, H, W, C):
     for v in vols:
         for j in range(len(views)):
             fns.append(lambda v=v, j=j: v.trace(d_views[j], hits[j]))
-    # Autotune each format on a held-out view (a fifth seeded camera at 960x540), then time
+    # Autotune each format on a held-out view (a fifth seeded camera at the timed 1920x1080:
+    # schedules that shorten a launch's tail pay off differently at other ray counts), then time
     # the tuned schedules: the timed region. The untuned comparison (--untuned) runs after
     # it, so a profile of the timed kernels is not mixed with it.
-    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"], 960, 540)).cuda()
+    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"])).cuda()
     scheds = []
     for v in vols:
         if args.no_tune:
@@ -237,7 +238,7 @@ def run_df512(args, torch, H, C, res):
     codes, views = res["codes"], res["views"]
     d_views = [torch.from_numpy(r).cuda() for r in views]
     hits = [torch.empty((len(r), 4), dtype=torch.int32, device="cuda") for r in views]
-    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"], 960, 540)).cuda()
+    tune = torch.from_numpy(C.primary_rays(cfg, cfg["views"])).cuda()
     nrays = sum(len(r) for r in views)
     out = []
     for spec in C.SURF512_DF:
@@ -351,7 +352,7 @@ def run_surface2048(args, torch, H, W, C):
     log(f"[bench] surface-2048: {len(codes)} voxels ({len(codes) / n ** 3:.4%}) in {time.time() - t0:.1f}s")
     prim = C.primary_rays(cfg, 0)
     d_prim = torch.from_numpy(prim).cuda()
-    held = C.primary_rays(cfg, 1, 960, 540)
+    held = C.primary_rays(cfg, 1)  # held-out camera at the timed resolution, for the autotuner
     d_held = torch.from_numpy(held).cuda()
     out = []
     for spec in cfg["specs"]:
