@@ -286,9 +286,14 @@ void set_stacked(DevFormat& F, uint32_t mask) {
 
 int family_of(const Layout& L) {
   uint32_t need = 0;
-  for (const DepthInfo& d : L.d) need |= fam_nk(d.nk) | fam_hk(d.hk);
+  bool cubic = true, w1 = true;
+  for (const DepthInfo& d : L.d) {
+    need |= fam_nk(d.nk) | fam_hk(d.hk);
+    cubic = cubic && d.w[0] == d.w[1] && d.w[1] == d.w[2];
+    w1 = w1 && d.w[0] == 1 && d.w[1] == 1 && d.w[2] == 1;
+  }
   for (int i = 0; i < NUM_FAMILIES; ++i)
-    if ((FAMILIES[i] & need) == need) return i;
+    if ((FAMILIES[i] & need) == need && (cubic || !fam_cubic(FAMILIES[i])) && (w1 || !fam_w1(FAMILIES[i]))) return i;
   return NUM_FAMILIES - 1;
 }
 

@@ -151,6 +151,11 @@ constexpr uint32_t FAM_BRICK = fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) | fam_hk(HK_
 constexpr uint32_t FAMILIES[] = {FAM_BRICK,     FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE,
                                  FAM_RAW_OCTREE, FAM_DF_BRICK,  FAM_DF_OCTREE, FAM_NODF,      FAM_ALL};
 constexpr int NUM_FAMILIES = 10;
+// Families whose kernels take every depth to be cubic (w equal on the three axes: the root
+// is an octree level, and levels below the first are cubic), and the one whose depths all
+// have w = 1 (octree levels only). family_of assigns them only to layouts that are.
+constexpr bool fam_cubic(uint32_t f) { return f == FAM_DAG_BRICK || f == FAM_SVO_BRICK || f == FAM_OCTREE; }
+constexpr bool fam_w1(uint32_t f) { return f == FAM_OCTREE; }
 
 // Index into FAMILIES of the first family covering the layout.
 int family_of(const Layout& L);

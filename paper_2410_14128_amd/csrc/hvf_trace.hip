@@ -295,8 +295,18 @@ struct Walk {
     m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
   }
 
+  // Index of the child cell holding the ray: the cell position's bits [c, c + w_a) per axis,
+  // x lowest. Octree-only families have w = 1 at every depth and cubic families one w for
+  // all three axes, known at compile time or read once.
+  template <uint32_t FAM>
   __device__ __forceinline__ uint32_t cell_lin(uint32_t in) const {
     const int c = di_cs(in);
+    constexpr uint32_t F0 = FAM & ~FAM_PRE;
+    if (fam_w1(F0)) return bf((uint32_t)p[0], c, 1) | (bf((uint32_t)p[1], c, 1) << 1) | (bf((uint32_t)p[2], c, 1) << 2);
+    if (fam_cubic(F0)) {
+      const uint32_t w = bf(in, 12, 4);
+      return bf((uint32_t)p[0], c, w) | (bf((uint32_t)p[1], c, w) << w) | (bf((uint32_t)p[2], c, w) << (2 * w));
+    }
     const uint32_t wx = bf(in, 12, 4), wy = bf(in, 16, 4), wz = bf(in, 20, 4);
     return bf((uint32_t)p[0], c, wx) | (bf((uint32_t)p[1], c, wy) << wx) | (bf((uint32_t)p[2], c, wz) << (wx + wy));
   }
@@ -343,7 +353,7 @@ struct Walk {
     const uint32_t nk = di_nk(info);
     const int cs = di_cs(info);
     // Child cell of the current node holding the ray (octree nodes: w = 1, the octant).
-    const uint32_t lin = cell_lin(info);
+    const uint32_t lin = cell_lin<FAM>(info);
     // Register test: a voxel's bit in the block mask (base:valid) or an octree child's valid bit.
     const uint32_t word = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS && lin < 32u) ? base : valid;
     bool occ = ((word >> (lin & 31u)) & 1u) != 0u;
@@ -476,7 +486,7 @@ struct Walk {
     valid = sv.y;
     info = dtab[r];
     for (int k = r; k < nd; ++k) {
-      const uint32_t knk = di_nk(info), kl = cell_lin(info);
+      const uint32_t knk = di_nk(info), kl = cell_lin<FAM>(info);
       uint32_t child = 0u;
       uint2 cm = make_uint2(0u, 0u);
       if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
