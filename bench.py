@@ -344,6 +344,42 @@ def run_construction(args, torch, H, C, formats_2048=None):
     return out
 
 
+def run_restart(args, torch, H, W, C):
+    """Restarting sparse-voxel intersection (--restart-sv) against the stacked walk, for every
+    2048^3 format of the paper's table with an SVO or SVDAG level (Sec. 4.3): 1080p primary
+    rays of view 0 and their bounce rays, plain schedule, one lane per ray."""
+    cfg = C.SURF2048
+    codes = C.scene(cfg)
+    prim = C.primary_rays(cfg, 0)
+    d_prim = torch.from_numpy(prim).cuda()
+    h = torch.empty((len(prim), 4), dtype=torch.int32, device="cuda")
+    plain = H.schedule()
+    out = []
+    d_b = hb = None
+    for label, k, spec in C.TABLE_FORMATS:
+        if k != 11 or not any(c in spec for c in ("S(", "G(")):
+            continue
+        base = C.table_spec(spec)
+        rec = {"label": label, "format": base}
+        for key, sp in (("stacked", base), ("restart", base + " --restart-sv")):
+            v = H.Volume(sp, codes)
+            v.upload()
+            ms, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
+            if d_b is None:
+                torch.cuda.synchronize()
+                b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+                d_b = torch.from_numpy(b).cuda()
+                hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+            msb, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
+            rec[key] = {"primary_mrays_s": round(len(prim) / ms / 1e3, 1), "bounce_mrays_s": round(d_b.shape[0] / msb / 1e3, 1)}
+            v.close()
+        rec["primary_ratio"] = round(rec["restart"]["primary_mrays_s"] / rec["stacked"]["primary_mrays_s"], 3)
+        rec["bounce_ratio"] = round(rec["restart"]["bounce_mrays_s"] / rec["stacked"]["bounce_mrays_s"], 3)
+        log(f"[bench] restart {label:2d} {base:44s} primary x{rec['primary_ratio']:.3f}  bounce x{rec['bounce_ratio']:.3f}")
+        out.append(rec)
+    return out
+
+
 def run_surface2048(args, torch, H, W, C):
     cfg = C.SURF2048
     n = 1 << cfg["log2n"]
@@ -616,7 +652,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep", "build"],
+    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep", "build",
+                             "restart"],
                     default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
@@ -652,6 +689,9 @@ def main():
         return
     if args.only == "batched":
         run_batched(args, torch, H, W, C)
+        return
+    if args.only == "restart":
+        print(json.dumps({"restart_sv": run_restart(args, torch, H, W, C)}))
         return
     if args.only == "build":
         print(json.dumps({"construction": run_construction(args, torch, H, C)}))
