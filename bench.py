@@ -309,8 +309,8 @@ def run_construction(args, torch, H, C, formats_2048=None):
     three builds each; the device figure includes the download of the host copy). The two
     word buffers are compared word for word."""
     out = []
-    specs = formats_2048 or [C.table_spec(sp) for _, k, sp in C.TABLE_FORMATS if k == 11 and "D(" not in sp]
-    for cfg, fmts in ((C.SURF512, C.SURF512["specs"]), (C.SURF2048, specs)):
+    specs = formats_2048 or [C.table_spec(sp) for _, k, sp in C.TABLE_FORMATS if k == 11]
+    for cfg, fmts in ((C.SURF512, C.SURF512["specs"] + C.SURF512_DF), (C.SURF2048, specs)):
         codes = C.scene(cfg)
         d_codes = torch.from_numpy(codes.view(np.int64)).cuda()
         H.Volume.from_device("S(3)", d_codes[:1] * 0).close()  # load the construction kernels

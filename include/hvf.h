@@ -135,7 +135,8 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
  * spec and codes; the nodes of every depth come from the codes by flag, scan and sort
  * passes on hip_stream (a hipStream_t, or NULL for the null stream), and SVDAG nodes are
  * de-duplicated by sorted content hashes, confirmed word by word.
- * format_spec: as for hvf_build; distance-field levels D(...) give HVF_E_UNSUPPORTED.
+ * format_spec: as for hvf_build, distance-field levels included (their capped distances
+ *   come from separable relaxations along x, y and z on the device).
  * d_morton, n: device pointer to n strictly ascending Morton codes (x bit 0, y bit 1,
  *   z bit 2 of each 3-bit group), all inside the volume; n < 2^31. Read only, not retained.
  * out: receives a new handle owned by the caller (release with hvf_free); its device
@@ -144,7 +145,7 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
  * code) is freed before returning. The host copy of the words (hvf_words, hvf_save) is
  * downloaded from the device buffer when first read.
  * Errors: HVF_E_SPEC, HVF_E_INPUT (null pointers, codes not ascending or outside the
- * volume), HVF_E_OVERFLOW, HVF_E_NOMEM, HVF_E_DEVICE, HVF_E_UNSUPPORTED. */
+ * volume), HVF_E_OVERFLOW, HVF_E_NOMEM, HVF_E_DEVICE, HVF_E_UNSUPPORTED (2^31 codes or more). */
 hvf_status hvf_build_device(const char* format_spec, const uint64_t* d_morton, size_t n, void* hip_stream,
                             hvf_volume** out);
 

@@ -14,8 +14,11 @@
 //    de-duplication (Sec. 4.3). Equal content is found by sorting 64-bit content hashes
 //    and confirmed word by word, so a hash collision never merges different nodes;
 //  * depths are placed in order at 64-byte aligned word offsets (SVO pointer arrays right
-//    after their depth) and child references are written as absolute word offsets.
-// Distance-field levels are not built on the device.
+//    after their depth) and child references are written as absolute word offsets;
+//  * a distance-field level stores, for every empty cell of a grid (or block of a brick),
+//    the L1 distance to the nearest occupied one capped at M. L1 distance splits by axis,
+//    so forward and backward relaxations along x, then y, then z, one thread per line and
+//    in place in the output, give the same integers as the host's breadth-first search.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -227,7 +230,8 @@ __global__ void k_dag_ids(const uint32_t* __restrict__ canon, const uint64_t* __
 // block is an aligned cube of side 2^b, so its voxels are one run of codes with equal
 // code >> 3b; the run's first code builds both mask words and stores them.
 __global__ void k_write_bricks(const uint64_t* __restrict__ codes, const uint32_t* __restrict__ rank, size_t n,
-                               int ns, int b, int wx, int wy, uint64_t stride, uint32_t* __restrict__ dst) {
+                               int ns, int b, int wx, int wy, uint64_t stride, uint32_t bwords,
+                               uint32_t* __restrict__ dst) {
   const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
   if (i >= n) return;
   const uint64_t c = codes[i];
@@ -245,9 +249,73 @@ __global__ void k_write_bricks(const uint64_t* __restrict__ codes, const uint32_
     w[bit >> 5] |= 1u << (uint32_t)(bit & 31u);
   }
   const uint64_t node = rank ? rank[i] - 1u : 0u;
-  uint32_t* o = dst + node * stride + 2 * blk;
+  uint32_t* o = dst + node * stride + bwords * blk;
   o[0] = w[0];
   o[1] = w[1];
+}
+
+// ---------------------------------------------------------------- distance fields
+constexpr uint32_t DF_FAR = 1u << 30;  // "no occupied cell yet" during the relaxations
+
+// Every cell (or block) of a distance-field depth: 0 if occupied, DF_FAR if empty. A
+// pointer-grid cell is occupied once a child is marked (k_df_mark); a DF brick block
+// holds its masks in words 0 and 1 and its distance in word 2.
+__global__ void k_df_init(uint32_t* __restrict__ dst, size_t cells, uint32_t words, uint32_t off, int from_masks) {
+  const size_t c = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (c >= cells) return;
+  uint32_t* o = dst + c * words;
+  o[off] = (from_masks && (o[0] | o[1]) != 0u) ? 0u : DF_FAR;
+}
+
+__global__ void k_df_mark(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ par, size_t nc, int w0,
+                          int w1, int root, uint64_t cells, uint32_t* __restrict__ dst) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  const uint64_t k = ckey[j];
+  const uint64_t local = root ? k : (k & ((1ull << (3 * w0)) - 1ull));
+  const uint64_t cell = coord_of(local) | (coord_of(local >> 1) << w0) | (coord_of(local >> 2) << (w0 + w1));
+  dst[(uint64_t)(par ? par[j] : 0u) * cells + cell] = 0u;
+}
+
+// One line per thread: the cells of a node with all coordinates fixed but axis a, at a
+// step of `step` cells; d = min(d, neighbour + 1) forward, then backward.
+__global__ void k_df_relax(uint32_t* __restrict__ dst, size_t lines, uint32_t len, uint64_t step, uint64_t lo_mask,
+                           int lo_bits, uint32_t words, uint32_t off) {
+  const size_t l = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (l >= lines) return;
+  // line l: its cells differ only in the axis-a coordinate; the coordinates below axis a
+  // are the low lo_bits bits of l, those above it the rest, shifted past axis a.
+  const uint64_t first = (l & lo_mask) | ((l >> lo_bits) << (lo_bits + __builtin_ctzll((unsigned long long)len)));
+  uint32_t* o = dst + first * words + off;
+  const uint64_t st = step * words;
+  uint32_t prev = o[0];
+  for (uint32_t i = 1; i < len; ++i) {
+    uint32_t v = o[i * st];
+    if (prev + 1u < v) {
+      v = prev + 1u;
+      o[i * st] = v;
+    }
+    prev = v;
+  }
+  for (uint32_t i = len - 1; i-- > 0;) {
+    uint32_t v = o[i * st];
+    if (prev + 1u < v) {
+      v = prev + 1u;
+      o[i * st] = v;
+    }
+    prev = v;
+  }
+}
+
+// Final words: a DF pointer-grid cell that is empty becomes DF_EMPTY | min(M, d) (occupied
+// cells keep 0 until their pointer is written); a DF brick block's word 2 becomes min(M, d).
+__global__ void k_df_finish(uint32_t* __restrict__ dst, size_t cells, uint32_t words, uint32_t off, uint32_t cap,
+                            int grid) {
+  const size_t c = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (c >= cells) return;
+  uint32_t* o = dst + c * words + off;
+  const uint32_t d = *o < cap ? *o : cap;
+  *o = grid ? (d ? (DF_EMPTY | d) : 0u) : d;
 }
 
 // Raw pointer grids: the cell of each child holds its absolute word offset (0 = empty).
@@ -424,8 +492,18 @@ class DeviceBuilder {
   }
 
   static bool is_brick(const DepthInfo& di) {
-    return di.nk == NK_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD);
+    return di.nk == NK_BLOCKS || di.nk == NK_DF_BLOCKS || (di.nk == NK_CELLS && di.hk == HK_MASKLOAD);
   }
+  static bool is_grid(const DepthInfo& di) { return di.nk == NK_RAW_PTR || di.nk == NK_DF_PTR; }
+  // Words per node: a brick's blocks (2 words each, 4 with a distance), a grid's cells.
+  static uint64_t node_words(const DepthInfo& di) {
+    const int sw = di.w[0] + di.w[1] + di.w[2];
+    if (di.nk == NK_DF_BLOCKS) return 4ull << sw;
+    if (di.nk == NK_BLOCKS) return 2ull << sw;
+    if (is_brick(di)) return 2ull;
+    return 1ull << sw;
+  }
+  void relax_df(uint32_t* dst, size_t nodes, const int w[3], uint32_t words, uint32_t off);
   static bool is_octree(const DepthInfo& di) {
     return di.nk == NK_SVO_INNER || di.nk == NK_DAG_INNER || di.nk == NK_OCT_PTR || di.nk == NK_OCT_FINAL;
   }
@@ -480,6 +558,22 @@ bool DeviceBuilder::dedup(int i, std::vector<DepthState>& D, bool has_children) 
   return true;
 }
 
+// Forward and backward relaxations along x, then y, then z over every node's grid of
+// 2^w[0] x 2^w[1] x 2^w[2] cells (x fastest), `words` words per cell, distance at `off`.
+void DeviceBuilder::relax_df(uint32_t* dst, size_t nodes, const int w[3], uint32_t words, uint32_t off) {
+  const size_t cells = nodes << (w[0] + w[1] + w[2]);
+  int lo = 0;
+  for (int a = 0; a < 3; ++a) {
+    const uint32_t len = 1u << w[a];
+    if (len > 1u) {
+      const size_t lines = cells >> w[a];
+      hipLaunchKernelGGL(k_df_relax, dim3(grid_for(lines)), dim3(TB), 0, s_, dst, lines, len, 1ull << lo,
+                         (1ull << lo) - 1ull, lo, words, off);
+    }
+    lo += w[a];
+  }
+}
+
 hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   const int nd = (int)L.d.size();
   std::vector<DepthState> D(nd);
@@ -493,12 +587,12 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   if (herr & 1u) return fail(HVF_E_INPUT, "Morton codes must be strictly ascending"), st_;
   if (herr & 2u) return fail(HVF_E_INPUT, "Morton code outside the volume"), st_;
   // Nodes of more than 2^31 words are out of range of the traversal's 32-bit offsets.
+  bool df_ptr = false;
   for (const DepthInfo& di : L.d) {
-    const int sw = di.w[0] + di.w[1] + di.w[2];
-    const uint64_t node_words = is_brick(di) ? (2ull << (di.nk == NK_BLOCKS ? sw : 0)) : (1ull << sw);
-    if ((di.nk == NK_RAW_PTR || is_brick(di)) && node_words >= (1ull << 31))
+    if ((is_grid(di) || is_brick(di)) && node_words(di) >= (1ull << 31))
       return fail(HVF_E_OVERFLOW, "a single node of this format needs 2^31 words or more, beyond 32-bit word offsets"),
              st_;
+    df_ptr = df_ptr || di.nk == NK_DF_PTR;
   }
   // 2. node keys, bottom-up. The deepest stored depth takes its nodes from the codes (and
   //    keeps every code's node rank: bricks and final octree masks are filled per voxel).
@@ -564,9 +658,8 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     const DepthInfo& di = L.d[i];
     DepthState& q = D[i];
     const bool kids = i < dl;  // children at depth i + 1 (else voxels)
-    if (is_brick(di) || di.nk == NK_RAW_PTR) {
-      const int sw = di.w[0] + di.w[1] + di.w[2];
-      const uint64_t per = is_brick(di) ? (2ull << (di.nk == NK_BLOCKS ? sw : 0)) : (1ull << sw);
+    if (is_brick(di) || is_grid(di)) {
+      const uint64_t per = node_words(di);
       q.words = q.n * per;
       q.stored = q.n;
       if (q.words >= (1ull << 32)) return fail(HVF_E_OVERFLOW, "format needs 2^32 words or more"), st_;
@@ -606,8 +699,11 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     auxb[i] = cur;
     cur += D[i].aux;
   }
-  if (cur >= (1ull << 32))
-    return fail(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond 32-bit word offsets"), st_;
+  if (cur >= (df_ptr ? (1ull << 31) : (1ull << 32)))
+    return fail(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
+                                    "-bit word offsets" +
+                                    (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : "")),
+           st_;
   const size_t total = (size_t)cur + HVF_BUFFER_PAD_WORDS;
   if (!hip(hipMalloc(&buf_, total * sizeof(uint32_t)), "hipMalloc of the word buffer") ||
       !hip(hipMemsetAsync(buf_, 0, total * sizeof(uint32_t), s_), "hipMemsetAsync"))
@@ -619,14 +715,30 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     uint32_t* dst = buf_ + base[i];
     const uint32_t nb = (i + 1 < nd) ? (uint32_t)base[i + 1] : 0u;
     if (is_brick(di)) {
-      const int wx = di.nk == NK_BLOCKS ? di.w[0] : 0, wy = di.nk == NK_BLOCKS ? di.w[1] : 0;
-      const int wz = di.nk == NK_BLOCKS ? di.w[2] : 0;
-      const uint64_t stride = 2ull << (wx + wy + wz);
+      const bool blocks = di.nk == NK_BLOCKS || di.nk == NK_DF_BLOCKS;
+      const int wx = blocks ? di.w[0] : 0, wy = blocks ? di.w[1] : 0;
+      const uint32_t bwords = di.nk == NK_DF_BLOCKS ? 4u : 2u;
       hipLaunchKernelGGL(k_write_bricks, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, i == 0 ? nullptr : code_rank,
-                         n_, q.ns, L.brick_b, wx, wy, stride, dst);
-    } else if (di.nk == NK_RAW_PTR) {
+                         n_, q.ns, L.brick_b, wx, wy, node_words(di), bwords, dst);
+      if (di.nk == NK_DF_BLOCKS) {
+        const size_t cells = q.n << (di.w[0] + di.w[1] + di.w[2]);
+        hipLaunchKernelGGL(k_df_init, dim3(grid_for(cells)), dim3(TB), 0, s_, dst, cells, 4u, 2u, 1);
+        relax_df(dst, q.n, di.w, 4u, 2u);
+        hipLaunchKernelGGL(k_df_finish, dim3(grid_for(cells)), dim3(TB), 0, s_, dst, cells, 4u, 2u,
+                           (uint32_t)S.lv[di.level].maxd, 0);
+      }
+    } else if (is_grid(di)) {
       const DepthState& c = D[i + 1];
       const uint64_t cells = 1ull << (di.w[0] + di.w[1] + di.w[2]);
+      if (di.nk == NK_DF_PTR) {
+        const size_t all = q.n * cells;
+        hipLaunchKernelGGL(k_df_init, dim3(grid_for(all)), dim3(TB), 0, s_, dst, all, 1u, 0u, 0);
+        hipLaunchKernelGGL(k_df_mark, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, i == 0 ? nullptr : c.parent, c.n,
+                           di.w[0], di.w[1], i == 0 ? 1 : 0, cells, dst);
+        relax_df(dst, q.n, di.w, 1u, 0u);
+        hipLaunchKernelGGL(k_df_finish, dim3(grid_for(all)), dim3(TB), 0, s_, dst, all, 1u, 0u,
+                           (uint32_t)S.lv[di.level].maxd, 1);
+      }
       hipLaunchKernelGGL(k_write_raw, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, i == 0 ? nullptr : c.parent, c.id,
                          c.n, di.w[0], di.w[1], i == 0 ? 1 : 0, cells, nb, dst);
     } else if (di.hk == HK_SVO) {
@@ -685,8 +797,6 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   std::string err;
   hvf_status st = hvf::parse_spec(format_spec, spec, err);
   if (st != HVF_OK) return devbuild_fail(st, err);
-  for (const hvf::LevelSpec& lv : spec.lv)
-    if (lv.maxd) return devbuild_fail(HVF_E_UNSUPPORTED, "distance-field levels are built on the host only");
   if (n && !d_morton) return devbuild_fail(HVF_E_INPUT, "null Morton code array");
   if (n > (size_t)INT_MAX) return devbuild_fail(HVF_E_UNSUPPORTED, "a device construction takes fewer than 2^31 codes");
   hvf_volume* v = new (std::nothrow) hvf_volume();

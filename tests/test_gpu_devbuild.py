@@ -10,7 +10,7 @@ import pytest
 import oracle
 import workloads as W
 from tests.gpu_util import compare, gpu_trace
-from tests.test_oracle_pins import EDGE_CASES, EDGE_SPECS, EDGE_VOX, SPECS_8, codes_of
+from tests.test_oracle_pins import DF_SPECS, EDGE_CASES, EDGE_SPECS, EDGE_VOX, SPECS_8, codes_of
 from workloads import configs as C
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +44,7 @@ def same_volume(H, spec, codes):
     return host, dev
 
 
-@pytest.mark.parametrize("spec", SPECS_8)
+@pytest.mark.parametrize("spec", SPECS_8 + DF_SPECS)
 def test_every_type_sequence_words(H, spec):
     for seed, p in ((1, 0.05), (2, 0.2), (3, 0.6), (4, 1.0)):
         same_volume(H, spec, W.scene_bernoulli(seed, 3, 3, 3, p))
@@ -52,7 +52,8 @@ def test_every_type_sequence_words(H, spec):
 
 @pytest.mark.parametrize("spec", ["R(1,0,2) R(2,2,2)", "R(3,2,4)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)",
                                   "R(0,0,0) R(2,2,2)", "R(2,1,0) G(2) --whole-level-dedup", "R(1,1,1)", "S(1)",
-                                  "G(1)", "R(0,1,2) R(1,1,1)"])
+                                  "G(1)", "R(0,1,2) R(1,1,1)", "D(3,2,4,5) R(1,1,1)", "D(3,2,4,3)", "D(1,0,2,2) S(2)",
+                                  "D(2,1,0,9) D(2,2,2,1)"])
 def test_noncubic_and_tiny_tops(H, spec):
     ex = H.Volume(spec).info()["extent_log2"]
     for seed, p in ((5, 0.1), (6, 0.5)):
@@ -80,7 +81,16 @@ def test_scenes_256(H):
 
 def test_surface_512_formats(H):
     codes = C.scene(C.SURF512)
-    for spec in C.SURF512["specs"]:
+    for spec in C.SURF512["specs"] + C.SURF512_DF:
+        same_volume(H, spec, codes)
+
+
+def test_distance_field_caps_and_sparse_scene(H):
+    """Distances that hit the cap and distances far below it, in grids and in bricks."""
+    xyz = np.array([[0, 0, 0], [63, 63, 63], [5, 40, 17], [33, 2, 60]], np.uint32)
+    codes = np.sort(W.morton_encode(xyz))
+    for spec in ["D(6,6,6,99)", "D(6,6,6,1)", "D(3,3,3,40) D(3,3,3,7)", "D(2,2,2,5) D(2,2,2,5) D(2,2,2,5)",
+                 "G(2) D(4,4,4,12)", "D(4,4,4,20) G(2) --whole-level-dedup"]:
         same_volume(H, spec, codes)
 
 
@@ -94,7 +104,7 @@ def test_trace_device_built_against_oracle(H):
         assert compare(got, ref, spec) == 0
 
 
-@pytest.mark.parametrize("spec", EDGE_SPECS)
+@pytest.mark.parametrize("spec", EDGE_SPECS + ["D(3,3,3,6)", "D(1,1,1,3) R(2,2,2)", "S(1) D(2,2,2,6)"])
 def test_edge_suite_device_built(H, spec):
     codes = codes_of(EDGE_VOX)
     rays = np.concatenate([r for r, _ in EDGE_CASES])
@@ -124,9 +134,6 @@ def test_errors(H):
     with pytest.raises(H.HvfError) as e:
         H.Volume.from_device("R(3,3,3)", dev_codes(dup))
     assert e.value.name == "HVF_E_INPUT"
-    with pytest.raises(H.HvfError) as e:
-        H.Volume.from_device("D(3,3,3,4)", dev_codes(codes))
-    assert e.value.name == "HVF_E_UNSUPPORTED"
     with pytest.raises(H.HvfError) as e:
         H.Volume.from_device("Q(3)", dev_codes(codes))
     assert e.value.name == "HVF_E_SPEC"
