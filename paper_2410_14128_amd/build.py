@@ -27,18 +27,29 @@ def flags():
 
 
 def build(verbose: bool = False) -> str:
-    """Always recompiles (this is the does-it-build check); returns the library path."""
+    """Always recompiles (this is the does-it-build check); returns the library path. The
+    sources compile concurrently (at most 4 compiler processes)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     objs = []
+    cmds = []
     builddir = os.path.join(HERE, "_build")
     os.makedirs(builddir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(builddir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([HIPCC] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # Longest compiles first, so the pool finishes together.
+    order = sorted(range(len(cmds)), key=lambda i: SOURCES[i] not in ("hvf_trace.hip", "hvf_devbuild.hip"))
+    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as pool:
+        futs = []
+        for i in order:
+            if verbose:
+                print(" ".join(cmds[i]), flush=True)
+            futs.append(pool.submit(subprocess.check_call, cmds[i]))
+        for f in futs:
+            f.result()
     tmp = SO + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
