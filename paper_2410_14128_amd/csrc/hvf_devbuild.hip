@@ -437,8 +437,10 @@ class DeviceBuilder {
   T* alloc(size_t count) {
     const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
     if (bytes > left_) {
-      // Chunks of about 40 bytes per code: enough for the deepest depths' arrays at once.
-      const size_t size = std::max(bytes, (size_t)40 * n_ + ((size_t)8 << 20));
+      // Chunks of about 40 bytes per code (enough for the deepest depths' arrays at once), at
+      // most 1 GiB unless one array needs more.
+      const size_t hint = std::min((size_t)40 * n_ + ((size_t)8 << 20), (size_t)1 << 30);
+      const size_t size = std::max(bytes, hint);
       void* p = nullptr;
       if (!hip(hipMalloc(&p, size), "hipMalloc of construction temporaries")) return nullptr;
       chunks_.push_back(p);
