@@ -534,6 +534,19 @@ __device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
 
 __device__ __forceinline__ int4 miss_hit() { return make_int4(-1, -1, -1, __float_as_int(INFINITY)); }
 
+// A launch reads each ray once and writes each hit once: streaming (non-temporal) accesses
+// keep these arrays from evicting the format's nodes from L2.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ray_half(const float4* rays, size_t k) {
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(rays) + k);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void put_hit(int4* hits, size_t k, int4 h) {
+  const i32x4 v = {h.x, h.y, h.z, h.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(hits) + k);
+}
+
 // The whole walk of one ray: its result (a miss if it never hits).
 template <uint32_t FAM>
 __device__ __forceinline__ int4 trace_one(const Fmt& fm, uint2* stk, const float4 r0, const float4 r1) {
@@ -588,9 +601,9 @@ __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const f
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
-  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  hits[i] = F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
-                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1);
+  const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
+  put_hit(hits, i, F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
+                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1));
 }
 
 // First pass of the split schedule: trace_kernel with a step budget. Rays that finish
@@ -606,12 +619,12 @@ __global__ __launch_bounds__(BLOCK) void trace_budget_kernel(const DevFormat F, 
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
-  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
   float rest;
   const int4 out = F.lds_words ? trace_budget<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1, budget, &rest)
                                : trace_budget<FAM>(fm, stk_all + threadIdx.x, r0, r1, budget, &rest);
   const bool cut = rest >= 0.0f;
-  if (!cut) hits[i] = out;
+  if (!cut) put_hit(hits, i, out);
   push_survivor(cut, i, rest, surv, nsurv);
 }
 
@@ -651,7 +664,7 @@ __device__ __forceinline__ void split_loop(const DevFormat& F, const Fmt& fm, ui
       const uint2 sv = surv[sidx];
       ray = sv.x;
       const float tc = __uint_as_float(sv.y);
-      const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
+      const float4 r0 = ray_half(rays, 2 * (size_t)ray), r1 = ray_half(rays, 2 * (size_t)ray + 1);
       Walk w;
       Plain mem;
       if (setup(r0, r1, fm.ext, w.R)) {
@@ -665,7 +678,7 @@ __device__ __forceinline__ void split_loop(const DevFormat& F, const Fmt& fm, ui
     }
     const uint64_t gm = (__ballot(out.x != -1) >> g0) & gmask;  // segments with a result
     const uint32_t first = gm ? (uint32_t)(__ffsll((unsigned long long)gm) - 1) : 0u;
-    if (sidx < ns && k == first) hits[ray] = out;
+    if (sidx < ns && k == first) put_hit(hits, ray, out);
   }
 }
 
@@ -710,9 +723,9 @@ __device__ __forceinline__ void persistent_loop(const Fmt& fm, uint2* stk, const
         if (id < n) {
           ray = id;
           out = miss_hit();
-          const float4 r0 = rays[2 * (size_t)id], r1 = rays[2 * (size_t)id + 1];
+          const float4 r0 = ray_half(rays, 2 * (size_t)id), r1 = ray_half(rays, 2 * (size_t)id + 1);
           active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
-          if (!active) hits[id] = out;
+          if (!active) put_hit(hits, id, out);
         }
       }
     }
@@ -720,7 +733,7 @@ __device__ __forceinline__ void persistent_loop(const Fmt& fm, uint2* stk, const
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
         if (w.template step<FAM>(fm, stk, out, mem) == DONE) {
-          hits[ray] = out;
+          put_hit(hits, ray, out);
           active = false;
           break;
         }
@@ -763,9 +776,9 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
   const uint32_t k = blockIdx.x * BLOCK + threadIdx.x;
   if (k >= n || key[k] == 0xFFFFFFFFu) return;  // rays that miss the root box were answered
   const uint32_t i = perm[k];
-  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-  hits[i] = F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
-                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1);
+  const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
+  put_hit(hits, i, F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
+                        : trace_one<FAM>(fm, stk_all + threadIdx.x, r0, r1));
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
@@ -786,7 +799,7 @@ __global__ __launch_bounds__(BLOCK) void ray_key_kernel(const DevFormat F, const
                                                         uint32_t* __restrict__ key, uint32_t* __restrict__ idx) {
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
-  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
   Ray R;
   uint32_t k = 0xFFFFFFFFu;
   if (setup(r0, r1, F.ext, R)) {
@@ -803,7 +816,7 @@ __global__ __launch_bounds__(BLOCK) void ray_key_kernel(const DevFormat F, const
     k = (R.neg << 29) | (m >> 1);
     if (k == 0xFFFFFFFFu) k = 0xFFFFFFFEu;
   } else {
-    hits[i] = miss_hit();
+    put_hit(hits, i, miss_hit());
   }
   key[i] = k;
   idx[i] = i;
@@ -879,10 +892,10 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
           hits = reinterpret_cast<int4*>(it.hits);
           ray = id - it.first;
           const float4* rays = reinterpret_cast<const float4*>(it.rays);
-          const float4 r0 = rays[2 * (size_t)ray], r1 = rays[2 * (size_t)ray + 1];
+          const float4 r0 = ray_half(rays, 2 * (size_t)ray), r1 = ray_half(rays, 2 * (size_t)ray + 1);
           out = miss_hit();
           active = setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
-          if (!active) hits[ray] = out;
+          if (!active) put_hit(hits, ray, out);
         }
       }
     }
@@ -890,7 +903,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
     if (active) {
       for (uint32_t k = 0; k < inner; ++k) {
         if (w.template step<FAM>(fm, stk, out, mem) == DONE) {
-          hits[ray] = out;
+          put_hit(hits, ray, out);
           active = false;
           break;
         }
@@ -913,7 +926,7 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= n) return;
-  const float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+  const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
   int4 out = miss_hit();
   Walk w;
   Counting mem{log + (size_t)i * cap, cap, 0u};
@@ -921,7 +934,7 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   if (setup(r0, r1, F.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN)
     while (w.template step<FAM_ALL>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
-  hits[i] = out;
+  put_hit(hits, i, out);
   count[i] = mem.k;
   if (nsteps) nsteps[i] = w.steps;
 }
