@@ -148,13 +148,17 @@ constexpr uint32_t FAM_ALL = 0x1FFu | (0x1Fu << 16);
 constexpr uint32_t FAM_NODF = FAM_ALL & ~(fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS));
 constexpr uint32_t FAM_BRICK = fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) | fam_hk(HK_RAW) | fam_hk(HK_MASK) |
                                fam_hk(HK_MASKLOAD);
-constexpr uint32_t FAMILIES[] = {FAM_BRICK,     FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE,
-                                 FAM_RAW_OCTREE, FAM_DF_BRICK,  FAM_DF_OCTREE, FAM_NODF,      FAM_ALL};
-constexpr int NUM_FAMILIES = 10;
+// SVO and SVDAG levels mixed above a brick.
+constexpr uint32_t FAM_OCT_BRICK = FAM_DAG_BRICK | FAM_SVO_BRICK;
+constexpr uint32_t FAMILIES[] = {FAM_BRICK,    FAM_DAG_BRICK, FAM_SVO_BRICK,  FAM_RAW_BRICK, FAM_OCTREE,   FAM_RAW_OCTREE,
+                                 FAM_DF_BRICK, FAM_DF_OCTREE, FAM_OCT_BRICK, FAM_NODF,      FAM_ALL};
+constexpr int NUM_FAMILIES = 11;
 // Families whose kernels take every depth to be cubic (w equal on the three axes: the root
 // is an octree level, and levels below the first are cubic), and the one whose depths all
 // have w = 1 (octree levels only). family_of assigns them only to layouts that are.
-constexpr bool fam_cubic(uint32_t f) { return f == FAM_DAG_BRICK || f == FAM_SVO_BRICK || f == FAM_OCTREE; }
+constexpr bool fam_cubic(uint32_t f) {
+  return f == FAM_DAG_BRICK || f == FAM_SVO_BRICK || f == FAM_OCTREE || f == FAM_OCT_BRICK;
+}
 constexpr bool fam_w1(uint32_t f) { return f == FAM_OCTREE; }
 
 // Index into FAMILIES of the first family covering the layout.

@@ -967,7 +967,8 @@ size_t stack_lds_bytes(const DevFormat& F) {
     case 5: LAUNCH(FAM_RAW_OCTREE); break;   \
     case 6: LAUNCH(FAM_DF_BRICK); break;     \
     case 7: LAUNCH(FAM_DF_OCTREE); break;    \
-    case 8: LAUNCH(FAM_NODF); break;         \
+    case 8: LAUNCH(FAM_OCT_BRICK); break;    \
+    case 9: LAUNCH(FAM_NODF); break;         \
     default: LAUNCH(FAM_ALL); break;         \
   }
 
