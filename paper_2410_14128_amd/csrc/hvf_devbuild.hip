@@ -396,6 +396,8 @@ class DeviceBuilder {
   DeviceBuilder(const Spec& s, const Layout& l, const uint64_t* codes, size_t n, hipStream_t st)
       : S(s), L(l), codes_(codes), n_(n), s_(st) {}
   ~DeviceBuilder() {
+    // After an error, kernels launched before it may still use the temporaries.
+    (void)hipStreamSynchronize(s_);
     for (void* p : chunks_) (void)hipFree(p);
     if (buf_) (void)hipFree(buf_);
   }
@@ -426,6 +428,11 @@ class DeviceBuilder {
       err_ = m;
     }
     return false;
+  }
+  // Record an error and return its status (for `return stop(...)` in run()).
+  hvf_status stop(hvf_status s, const std::string& m) {
+    fail(s, m);
+    return st_;
   }
   bool hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return true;
@@ -586,14 +593,13 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, S.ext[0], S.ext[1], S.ext[2], err);
   uint32_t herr = 0;
   if (!launched("validate") || !fetch(err, herr)) return st_;
-  if (herr & 1u) return fail(HVF_E_INPUT, "Morton codes must be strictly ascending"), st_;
-  if (herr & 2u) return fail(HVF_E_INPUT, "Morton code outside the volume"), st_;
+  if (herr & 1u) return stop(HVF_E_INPUT, "Morton codes must be strictly ascending");
+  if (herr & 2u) return stop(HVF_E_INPUT, "Morton code outside the volume");
   // Nodes of more than 2^31 words are out of range of the traversal's 32-bit offsets.
   bool df_ptr = false;
   for (const DepthInfo& di : L.d) {
     if ((is_grid(di) || is_brick(di)) && node_words(di) >= (1ull << 31))
-      return fail(HVF_E_OVERFLOW, "a single node of this format needs 2^31 words or more, beyond 32-bit word offsets"),
-             st_;
+      return stop(HVF_E_OVERFLOW, "a single node of this format needs 2^31 words or more, beyond 32-bit word offsets");
     df_ptr = df_ptr || di.nk == NK_DF_PTR;
   }
   // 2. node keys, bottom-up. The deepest stored depth takes its nodes from the codes (and
@@ -664,13 +670,13 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
       const uint64_t per = node_words(di);
       q.words = q.n * per;
       q.stored = q.n;
-      if (q.words >= (1ull << 32)) return fail(HVF_E_OVERFLOW, "format needs 2^32 words or more"), st_;
+      if (q.words >= (1ull << 32)) return stop(HVF_E_OVERFLOW, "format needs 2^32 words or more");
       if (!(q.id = alloc<uint32_t>(q.n))) return st_;
       hipLaunchKernelGGL(k_stride_ids, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.id, q.n, (uint32_t)per);
       if (!launched("ids")) return st_;
       continue;
     }
-    if (!is_octree(di)) return fail(HVF_E_UNSUPPORTED, "node kind not built on the device"), st_;
+    if (!is_octree(di)) return stop(HVF_E_UNSUPPORTED, "node kind not built on the device");
     if (!(q.masks = alloc<uint32_t>(q.n))) return st_;
     const int deepest = di.nk == NK_OCT_FINAL || di.nk == NK_OCT_PTR;
     if (kids)
@@ -689,7 +695,7 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     } else if (!dedup(i, D, kids)) {
       return st_;
     }
-    if (q.words >= (1ull << 32)) return fail(HVF_E_OVERFLOW, "format needs 2^32 words or more"), st_;
+    if (q.words >= (1ull << 32)) return stop(HVF_E_OVERFLOW, "format needs 2^32 words or more");
   }
   // 5. placement: depths in order, each at a 64-byte boundary, pointer arrays after them
   std::vector<uint64_t> base(nd), auxb(nd);
@@ -702,10 +708,9 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     cur += D[i].aux;
   }
   if (cur >= (df_ptr ? (1ull << 31) : (1ull << 32)))
-    return fail(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
+    return stop(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
                                     "-bit word offsets" +
-                                    (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : "")),
-           st_;
+                                    (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : ""));
   const size_t total = (size_t)cur + HVF_BUFFER_PAD_WORDS;
   if (!hip(hipMalloc(&buf_, total * sizeof(uint32_t)), "hipMalloc of the word buffer") ||
       !hip(hipMemsetAsync(buf_, 0, total * sizeof(uint32_t), s_), "hipMemsetAsync"))
