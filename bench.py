@@ -404,7 +404,9 @@ def run_surface2048(args, torch, H, W, C):
         plain = H.schedule()
         sched_p = H.schedule_dict(v.autotune(d_held)) if not args.no_tune else H.schedule_dict(plain)
         ms_p, _ = time_launches([lambda: v.trace(d_prim, h)], args.steps, args.warmup)
-        sched_b = H.schedule_dict(v.autotune(torch.from_numpy(bh).cuda())) if not args.no_tune else sched_p
+        # Tune on as many held-out bounce rays as the timed launch traces (the held-out view
+        # has more hits than view 0, and a schedule's gain depends on the launch size).
+        sched_b = H.schedule_dict(v.autotune(torch.from_numpy(bh[:len(b)].copy()).cuda())) if not args.no_tune else sched_p
         ms_b, _ = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
         # untuned comparison after the timed launches (a profile of those stays unmixed)
         ms_p0, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
