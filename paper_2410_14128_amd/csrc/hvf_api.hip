@@ -20,6 +20,7 @@ hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray
 hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid);
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                               uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s);
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                         const hvf_schedule& sc, hipStream_t s);
@@ -88,6 +89,7 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
 
 hvf_status hvf_upload(hvf_volume* v, void* stream) {
   if (!v) return fail(HVF_E_INPUT, "null volume");
+  std::lock_guard<std::mutex> g(v->dev_mu);
   if (v->dbuf) return HVF_OK;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -143,31 +145,43 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   const int family = hvf::family_of(v->layout);
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.split) {
-    const size_t need = 2 + 2 * n;
-    if (need > v->dsplit_words) {
-      if (v->dsplit) (void)hipFree(v->dsplit);
-      v->dsplit = nullptr;
-      v->dsplit_words = 0;
-      hipError_t e = hipMalloc(&v->dsplit, need * sizeof(uint32_t));
-      if (e != hipSuccess) {
-        v->dsplit = nullptr;
-        return hip_fail(e, "hipMalloc of the split survivor list");
+    const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split);
+    // The legacy default stream runs its calls in order, so they share the volume's survivor
+    // list; a call there that finds the list held by another host thread, and every call on
+    // another stream, takes stream-ordered scratch of its own.
+    if (s == nullptr) {
+      std::unique_lock<std::mutex> g(v->split_mu, std::try_to_lock);
+      if (g.owns_lock()) {
+        const size_t need = 2 + 2 * n;
+        if (need > v->split_words) {
+          if (v->split_buf) (void)hipFreeAsync(v->split_buf, s);
+          v->split_buf = nullptr;
+          v->split_words = 0;
+          const hipError_t e = hvf::scratch_alloc(reinterpret_cast<void**>(&v->split_buf), need * sizeof(uint32_t), s);
+          if (e != hipSuccess) {
+            v->split_buf = nullptr;
+            return hip_fail(e, "allocation of the split schedule's survivor list");
+          }
+          v->split_words = need;
+        }
+        return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, v->split_buf, s);
       }
-      v->dsplit_words = need;
     }
-    return hvf::launch_trace_split(F, family, d_rays, n, d_hits, (uint32_t)sc.split_budget,
-                                   (uint32_t)__builtin_ctz((unsigned)sc.split), v->dsplit, s);
+    return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, nullptr, s);
   }
   uint32_t* counter = nullptr;
   if (sc.persistent) {
-    if (!v->dcounters) {
-      hipError_t e = hipMalloc(&v->dcounters, HVF_NUM_COUNTERS * 2 * sizeof(uint32_t));
-      if (e != hipSuccess) {
-        v->dcounters = nullptr;
-        return hip_fail(e, "hipMalloc of ray counters");
+    {
+      std::lock_guard<std::mutex> g(v->dev_mu);
+      if (!v->dcounters) {
+        hipError_t e = hipMalloc(&v->dcounters, HVF_NUM_COUNTERS * 2 * sizeof(uint32_t));
+        if (e != hipSuccess) {
+          v->dcounters = nullptr;
+          return hip_fail(e, "hipMalloc of ray counters");
+        }
       }
     }
-    counter = v->dcounters + 2 * (v->counter_next++ % HVF_NUM_COUNTERS);
+    counter = v->dcounters + 2 * (v->counter_next.fetch_add(1) % HVF_NUM_COUNTERS);
   }
   if (!sc.persistent) return hvf::launch_trace(F, family, d_rays, n, d_hits, s);
   unsigned grid = 0;
@@ -508,13 +522,13 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
 
 void hvf_free(hvf_volume* v) {
   if (!v) return;
-  if (v->dbuf || v->dcounters || v->dsplit) {
+  if (v->dbuf || v->dcounters || v->split_buf) {
     int cur = 0;
     const bool other = hipGetDevice(&cur) == hipSuccess && v->device >= 0 && cur != v->device;
     if (other) (void)hipSetDevice(v->device);
+    if (v->split_buf) (void)hipFreeAsync(v->split_buf, nullptr);  // after the calls that used it
     if (v->dbuf) (void)hipFree(v->dbuf);
     if (v->dcounters) (void)hipFree(v->dcounters);
-    if (v->dsplit) (void)hipFree(v->dsplit);
     if (other) (void)hipSetDevice(cur);
   }
   delete v;

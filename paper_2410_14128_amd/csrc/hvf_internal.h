@@ -1,6 +1,7 @@
 // Internal declarations shared by the host builder, the C-ABI glue and the HIP kernels.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -192,10 +193,16 @@ struct hvf_volume {
   uint32_t* dbuf = nullptr;  // device copy of built.words
   int device = -1;
   hvf_schedule sched{0, 16, 8, 0, 4, 0, 0, 0};
-  uint32_t* dcounters = nullptr;  // device ray counters for persistent launches
-  unsigned counter_next = 0;
-  uint32_t* dsplit = nullptr;  // split schedule: 2 counters + survivor list (grown on demand)
-  size_t dsplit_words = 0;
+  uint32_t* dcounters = nullptr;  // device ray counters for persistent launches (a ring)
+  std::atomic<unsigned> counter_next{0};
+  // Guards the lazily made device copy and counters against concurrent first traces.
+  std::mutex dev_mu;
+  // Split schedule on the legacy default stream: one survivor list reused by every call
+  // there (that stream orders them), grown on demand, held by split_mu while a call
+  // enqueues its kernels. Calls on other streams allocate their own.
+  std::mutex split_mu;
+  uint32_t* split_buf = nullptr;
+  size_t split_words = 0;
   // A volume built on the device keeps built.words empty until a caller reads the host
   // copy (hvf_words, hvf_save); host_words() downloads it then, once, under host_mu.
   mutable std::mutex host_mu;

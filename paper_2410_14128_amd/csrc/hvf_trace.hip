@@ -992,8 +992,11 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
 // The split schedule: trace_budget_kernel over all rays, then trace_split_kernel over the
-// survivors on a device-filling grid. scratch: the survivor count and a spare word (zeroed
-// here), then room for n survivors (8 bytes each), 8-byte aligned.
+// survivors on a device-filling grid. Scratch: the survivor count and a spare word (zeroed
+// here), then room for n survivors (8 bytes each), 8-byte aligned; the caller's buffer of
+// at least 2 + 2n words, else one allocated for this call on s and freed after it.
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
+
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                               uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s) {
   if (n == 0) return HVF_OK;
@@ -1016,10 +1019,21 @@ hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_r
       per_cu < 1)
     per_cu = 1;
   const unsigned grid2 = (unsigned)(g_cu_count * per_cu);
+  const bool own = scratch == nullptr;
+  if (own) {
+    const hipError_t e = scratch_alloc(reinterpret_cast<void**>(&scratch), (2 + 2 * n) * sizeof(uint32_t), s);
+    if (e != hipSuccess) {
+      hvf_set_error(std::string("allocation of the split schedule's survivor list: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE;
+    }
+  }
   uint32_t* nsurv = scratch;
   uint2* surv = reinterpret_cast<uint2*>(scratch + 2);
   hvf_status st = launch_fill_u32(scratch, 0u, 2, s);
-  if (st != HVF_OK) return st;
+  if (st != HVF_OK) {
+    if (own) (void)hipFreeAsync(scratch, s);
+    return st;
+  }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
   const float4* r = reinterpret_cast<const float4*>(d_rays);
   int4* h = reinterpret_cast<int4*>(d_hits);
@@ -1029,13 +1043,16 @@ hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_r
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_BUDGET)
 #undef HVF_LAUNCH_BUDGET
   st = launch_check("budgeted trace");
-  if (st != HVF_OK) return st;
+  if (st == HVF_OK) {
 #define HVF_LAUNCH_SPLIT(FAMV)                                                                                    \
   hipLaunchKernelGGL(trace_split_kernel<FAMV>, dim3(grid2), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, surv, nsurv, \
                      klog2)
-  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_SPLIT)
+    HVF_FAMILY_SWITCH(family, HVF_LAUNCH_SPLIT)
 #undef HVF_LAUNCH_SPLIT
-  return launch_check("split trace");
+    st = launch_check("split trace");
+  }
+  if (own) (void)hipFreeAsync(scratch, s);
+  return st;
 }
 
 // Blocks of the persistent kernel per CU (at most blocks_per_cu if > 0) times CUs.
@@ -1126,16 +1143,23 @@ hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s)
   return launch_check("fill");
 }
 
-namespace {
-// Device scratch for ray sorting, grown on demand and reused (one sorted trace at a time
-// per process; calls are serialised by this lock on the host side).
-struct SortScratch {
-  std::mutex mu;
-  void* buf = nullptr;
-  size_t bytes = 0;
-};
-SortScratch g_sort;
-}  // namespace
+// Scratch of one call from the stream-ordered allocator: freed on the call's stream after
+// its kernels, so calls on other streams never share it and concurrent traces of one
+// volume are safe. The device's default pool keeps freed blocks for the next call (its
+// release threshold is raised once per device).
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s) {
+  static std::once_flag pool_once[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64)
+    std::call_once(pool_once[dev], [dev] {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      }
+    });
+  return hipMallocAsync(p, bytes, s);
+}
 
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                         const hvf_schedule& sc, hipStream_t s) {
@@ -1143,7 +1167,6 @@ hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, s
     hvf_set_error("at most 2^31 - 1 rays per sorted call");
     return HVF_E_INPUT;
   }
-  std::lock_guard<std::mutex> lock(g_sort.mu);
   const size_t arr = ((n * sizeof(uint32_t) + 255) / 256) * 256;
   size_t temp = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, temp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
@@ -1152,19 +1175,13 @@ hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, s
     hvf_set_error("radix sort size query failed");
     return HVF_E_DEVICE;
   }
-  const size_t need = 4 * arr + temp;
-  if (need > g_sort.bytes) {
-    if (g_sort.buf) (void)hipFree(g_sort.buf);
-    g_sort.buf = nullptr;
-    g_sort.bytes = 0;
-    const hipError_t e = hipMalloc(&g_sort.buf, need);
-    if (e != hipSuccess) {
-      hvf_set_error(std::string("hipMalloc of sort scratch: ") + hipGetErrorString(e));
-      return e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE;
-    }
-    g_sort.bytes = need;
+  void* buf = nullptr;
+  const hipError_t e = scratch_alloc(&buf, 4 * arr + temp, s);
+  if (e != hipSuccess) {
+    hvf_set_error(std::string("allocation of sort scratch: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE;
   }
-  char* base = (char*)g_sort.buf;
+  char* base = (char*)buf;
   uint32_t* key_in = (uint32_t*)base;
   uint32_t* idx_in = (uint32_t*)(base + arr);
   uint32_t* key_out = (uint32_t*)(base + 2 * arr);
@@ -1174,20 +1191,24 @@ hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, s
   hipLaunchKernelGGL(ray_key_kernel, dim3(grid), dim3(BLOCK), 0, s, F, reinterpret_cast<const float4*>(d_rays),
                      reinterpret_cast<int4*>(d_hits), (uint32_t)n, sc.sort_bits, key_in, idx_in);
   hvf_status st = launch_check("ray key");
-  if (st != HVF_OK) return st;
-  if (hipcub::DeviceRadixSort::SortPairs(tmp, temp, key_in, key_out, idx_in, idx_out, (int)n, 0, 32, s) !=
-      hipSuccess) {
+  if (st == HVF_OK &&
+      hipcub::DeviceRadixSort::SortPairs(tmp, temp, key_in, key_out, idx_in, idx_out, (int)n, 0, 32, s) !=
+          hipSuccess) {
     hvf_set_error("radix sort failed");
-    return HVF_E_DEVICE;
+    st = HVF_E_DEVICE;
   }
-  const float4* r = reinterpret_cast<const float4*>(d_rays);
-  int4* h = reinterpret_cast<int4*>(d_hits);
-#define HVF_LAUNCH_INDEXED(FAMV) \
+  if (st == HVF_OK) {
+    const float4* r = reinterpret_cast<const float4*>(d_rays);
+    int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_INDEXED(FAMV)                                                                                      \
   hipLaunchKernelGGL(trace_indexed_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
                      idx_out, key_out)
-  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_INDEXED)
+    HVF_FAMILY_SWITCH(family, HVF_LAUNCH_INDEXED)
 #undef HVF_LAUNCH_INDEXED
-  return launch_check("sorted trace");
+    st = launch_check("sorted trace");
+  }
+  (void)hipFreeAsync(buf, s);
+  return st;
 }
 
 hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,

@@ -173,3 +173,69 @@ def test_distance_field_sparse_scene(H, spec):
     got = gpu_trace(H.Volume(spec, codes), rays)
     ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
     assert compare(got, ref, spec) == 0
+
+
+def test_concurrent_traces_of_one_volume(H):
+    """Sorted, split and persistent traces of one volume in flight together on two streams,
+    from two host threads on streams of their own and from four host threads on the default
+    stream each equal the plain trace."""
+    import threading
+    import torch
+    codes = W.scene_shell(3, 7, 8, 4, 1.4)
+    v = H.Volume("G(4) R(3,3,3) --whole-level-dedup", codes)
+    rays = [torch.from_numpy(np.concatenate([W.camera_rays(s, s % 3, (128,) * 3, 200, 150),
+                                             W.random_rays(s, (128,) * 3, 20000)])).cuda() for s in range(6)]
+    plain = [v.trace(r) for r in rays]
+    torch.cuda.synchronize()
+    scheds = [H.schedule(sort=1, sort_bits=2), H.schedule(split=8, split_budget=4), H.schedule(persistent=1),
+              H.schedule(sort=1, sort_bits=4), H.schedule(split=4, split_budget=2), H.schedule(persistent=1, refill=8)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.full((r.shape[0], 4), 7, dtype=torch.int32, device="cuda") for r in rays]
+    torch.cuda.synchronize()
+    for i, (r, sc) in enumerate(zip(rays, scheds)):
+        with torch.cuda.stream(streams[i % 2]):
+            v.trace(r, outs[i], sched=sc)
+    torch.cuda.synchronize()
+    for i in range(len(rays)):
+        assert torch.equal(outs[i], plain[i]), f"stream case {i}"
+    outs2 = [torch.full((r.shape[0], 4), 7, dtype=torch.int32, device="cuda") for r in rays]
+    torch.cuda.synchronize()
+
+    def worker(k):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            for i in range(k, len(rays), 2):
+                v.trace(rays[i], outs2[i], sched=scheds[i])
+        s.synchronize()
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    for i in range(len(rays)):
+        assert torch.equal(outs2[i], plain[i]), f"thread case {i}"
+    # Split traces on the default stream from four host threads: they share the volume's
+    # survivor list when it is free, take their own scratch when it is held, and the shared
+    # list grows for the larger ray sets mid-way.
+    split = [H.schedule(split=8, split_budget=4), H.schedule(split=4, split_budget=2)]
+    order = [rays[0][:5000], rays[1], rays[2][:777]] + rays[3:]
+    want = [v.trace(r) for r in order]
+    torch.cuda.synchronize()
+    outs3 = [[torch.full((r.shape[0], 4), 7, dtype=torch.int32, device="cuda") for r in order] for _ in range(4)]
+    torch.cuda.synchronize()
+
+    def default_worker(k):
+        for i, r in enumerate(order):
+            v.trace(r, outs3[k][i], sched=split[(i + k) % 2], stream=0)
+
+    ts = [threading.Thread(target=default_worker, args=(k,)) for k in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    for k in range(4):
+        for i in range(len(order)):
+            assert torch.equal(outs3[k][i], want[i]), f"default-stream thread {k} case {i}"
