@@ -95,8 +95,12 @@ typedef struct hvf_info {
  * split = K > 0 (a power of two, 2..64; needs persistent = 0 and sort = 0): every ray walks
  *   at most split_budget steps; a ray still walking then has the rest of its interval,
  *   [t, t1), cut into K segments that K lanes walk side by side from the root in a second
- *   launch, and its result is that of the first segment with one. This shortens the few
- *   long walks that otherwise keep a launch's last waves busy. */
+ *   launch, and its result is that of the first segment with one. K is an upper bound:
+ *   the second launch halves it until the survivors' segments fit its grid's lanes. This shortens the few
+ *   long walks that otherwise keep a launch's last waves busy. With split_rounds = R > 0,
+ *   R restart rounds run in between: the rays still walking restart from the root at
+ *   their t, packed densely, for split_budget, 2 split_budget, ... 2^(R-1) split_budget
+ *   steps each; only the rays still walking after the last round are cut into segments. */
 typedef struct hvf_schedule {
   int32_t persistent;
   int32_t refill;
@@ -111,6 +115,7 @@ typedef struct hvf_schedule {
                           reads them there; HVF_E_INPUT if the prefix is larger */
   int32_t split;        /* 0, or K: see above */
   int32_t split_budget; /* steps of the first launch when split > 0 (1..2^20) */
+  int32_t split_rounds; /* restart rounds of the split schedule (0..6; needs split > 0) */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).

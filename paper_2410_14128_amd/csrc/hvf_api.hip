@@ -19,7 +19,7 @@ hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
 hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid);
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s);
+                              uint32_t budget, uint32_t klog2, uint32_t rounds, uint32_t* scratch, hipStream_t s);
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
@@ -118,7 +118,8 @@ hvf_status check_sched(const hvf_schedule& sc) {
       sc.sort < 0 || sc.sort > 1 || sc.sort_bits < 0 || sc.sort_bits > 16 || sc.blocks_per_cu < 0 ||
       sc.blocks_per_cu > 64 || sc.stack_depth < 0 || sc.stack_depth > HVF_MAX_DEPTH || sc.lds_depths < 0 ||
       sc.lds_depths > HVF_MAX_DEPTH || sc.split < 0 || sc.split > 64 || (sc.split & (sc.split - 1)) != 0 ||
-      sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))))
+      sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))) || sc.split_rounds < 0 ||
+      sc.split_rounds > (int)hvf::HVF_SPLIT_MAX_ROUNDS || (sc.split_rounds && !sc.split))
     return fail(HVF_E_INPUT, "schedule field out of range");
   if (sc.split && (sc.persistent || sc.sort))
     return fail(HVF_E_INPUT, "the split schedule runs without persistent lanes and without sorting");
@@ -145,14 +146,15 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   const int family = hvf::family_of(v->layout);
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.split) {
-    const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split);
+    const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split),
+                   rounds = (uint32_t)sc.split_rounds;
     // The legacy default stream runs its calls in order, so they share the volume's survivor
     // list; a call there that finds the list held by another host thread, and every call on
     // another stream, takes stream-ordered scratch of its own.
     if (s == nullptr) {
       std::unique_lock<std::mutex> g(v->split_mu, std::try_to_lock);
       if (g.owns_lock()) {
-        const size_t need = 2 + 2 * n;
+        const size_t need = hvf::split_scratch_words(n, rounds);
         if (need > v->split_words) {
           if (v->split_buf) (void)hipFreeAsync(v->split_buf, s);
           v->split_buf = nullptr;
@@ -164,10 +166,10 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
           }
           v->split_words = need;
         }
-        return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, v->split_buf, s);
+        return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, rounds, v->split_buf, s);
       }
     }
-    return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, nullptr, s);
+    return hvf::launch_trace_split(F, family, d_rays, n, d_hits, budget, klog2, rounds, nullptr, s);
   }
   uint32_t* counter = nullptr;
   if (sc.persistent) {
@@ -206,8 +208,10 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
     for (int refill : {8, 32})
       for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, bpc, 0, 0});
   for (int bits : {2, 4, 6}) cand.push_back(hvf_schedule{0, 16, 8, 1, bits, 0, 0, 0});
-  for (int k : {4, 8, 16})
-    for (int budget : {32, 64}) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, k, budget});
+  // Split: K is an upper bound (the second launch cuts no more segments than its grid has
+  // lanes), so K = 64 stands for every K the survivor count allows.
+  const int split_cand[][3] = {{4, 64, 0}, {16, 64, 0}, {64, 32, 0}, {64, 64, 0}, {64, 128, 0}, {64, 48, 1}, {64, 64, 1}};
+  for (const auto& c : split_cand) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, c[0], c[1], c[2]});
   hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");

@@ -113,6 +113,15 @@ struct DevFormat {
   uint32_t dinfo[HVF_MAX_DEPTH];
 };
 
+// Split schedule scratch: survivor counters (one per launch that fills a list, the first
+// launch and each restart round), then one survivor list of n entries (8 bytes each), or
+// two used in turn when there are restart rounds.
+constexpr uint32_t HVF_SPLIT_MAX_ROUNDS = 6;
+constexpr size_t HVF_SPLIT_HEAD_WORDS = 8;
+inline size_t split_scratch_words(size_t n, uint32_t rounds) {
+  return HVF_SPLIT_HEAD_WORDS + (rounds ? 4 : 2) * n;
+}
+
 // Largest prefix a schedule may stage in LDS (32 KiB; the node stack takes at most 32 KiB
 // more, so a block stays within 64 KiB).
 constexpr uint32_t HVF_LDS_PREFIX_MAX_WORDS = 8192;

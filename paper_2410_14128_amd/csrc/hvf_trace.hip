@@ -692,10 +692,73 @@ __global__ __launch_bounds__(BLOCK) void trace_split_kernel(const DevFormat F, c
   load_dtab(F, dtab);
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t ns = *nsurv;
+  // K adapts to the survivors: at most the schedule's K, and no more segments than the
+  // grid has lanes (K = 1 for a long list: each survivor's rest walked by one lane).
+  const uint32_t lanes = gridDim.x * BLOCK;
+  uint32_t kl = klog2;
+  while (kl > 0u && (uint64_t)ns << kl > lanes) --kl;
   if (F.lds_words)
-    split_loop<FAM | FAM_PRE>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, klog2);
+    split_loop<FAM | FAM_PRE>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, kl);
   else
-    split_loop<FAM>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, klog2);
+    split_loop<FAM>(F, fm, stk_all + threadIdx.x, rays, hits, surv, ns, kl);
+}
+
+// Restart rounds of the split schedule, between its first and its last launch. Each
+// survivor (ray, t) of the previous launch walks again from the root over [t, t1), which
+// visits the cells the interrupted walk had still to visit, in the same order (see
+// split_loop), for at most `budget` steps; a walk still running then joins the next list.
+// Survivors sit densely in the list, so the waves of a round start full instead of
+// carrying the finished lanes of the previous launch. Lane l of the grid takes survivors
+// l, l + (lanes in the grid), ...; the loop bound is uniform per wave, so push_survivor's
+// ballot sees every lane of the wave.
+template <uint32_t FAM>
+__device__ __forceinline__ void resume_loop(const Fmt& fm, uint2* stk, const float4* __restrict__ rays,
+                                            int4* __restrict__ hits, const uint2* __restrict__ in, uint32_t ns,
+                                            uint32_t budget, uint2* __restrict__ out, uint32_t* __restrict__ nout) {
+  const uint32_t lanes = gridDim.x * BLOCK;
+  for (uint32_t base = blockIdx.x * BLOCK + (threadIdx.x & ~63u); base < ns; base += lanes) {
+    const uint32_t sidx = base + (threadIdx.x & 63u);
+    bool cut = false;
+    uint32_t ray = 0;
+    float rest = -1.0f;
+    if (sidx < ns) {
+      const uint2 sv = in[sidx];
+      ray = sv.x;
+      const float4 r0 = ray_half(rays, 2 * (size_t)ray), r1 = ray_half(rays, 2 * (size_t)ray + 1);
+      int4 res = miss_hit();
+      Walk w;
+      Plain mem;
+      if (setup(r0, r1, fm.ext, w.R)) {
+        w.R.t0 = __uint_as_float(sv.y);
+        if (w.R.t0 < w.R.t1 && w.template start<FAM>(fm, mem) == RUN)
+          while (w.template step<FAM>(fm, stk, res, mem) == RUN)
+            if (w.steps == budget) {
+              rest = w.t;
+              cut = true;
+              break;
+            }
+      }
+      if (!cut) put_hit(hits, ray, res);
+    }
+    push_survivor(cut, ray, rest, out, nout);
+  }
+}
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(BLOCK) void trace_resume_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                             int4* __restrict__ hits, const uint2* __restrict__ in,
+                                                             const uint32_t* __restrict__ nin, uint32_t budget,
+                                                             uint2* __restrict__ out, uint32_t* __restrict__ nout) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
+  load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
+  const uint32_t ns = *nin;
+  if (F.lds_words)
+    resume_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, in, ns, budget, out, nout);
+  else
+    resume_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, in, ns, budget, out, nout);
 }
 
 template <uint32_t FAM>
@@ -991,14 +1054,18 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
 
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
-// The split schedule: trace_budget_kernel over all rays, then trace_split_kernel over the
-// survivors on a device-filling grid. Scratch: the survivor count and a spare word (zeroed
-// here), then room for n survivors (8 bytes each), 8-byte aligned; the caller's buffer of
-// at least 2 + 2n words, else one allocated for this call on s and freed after it.
+// The split schedule: trace_budget_kernel over all rays (budget steps), then `rounds`
+// restart rounds of trace_resume_kernel over the survivors (budgets budget, 2 budget,
+// 4 budget, ...: the walks are capped at budget * 2^r steps in all after round r), then
+// trace_split_kernel over the last survivors; the later launches run on device-filling
+// grids. Scratch: HVF_SPLIT_HEAD_WORDS survivor counters (zeroed here; count r belongs to
+// the list launch r fills), then one or, with rounds, two lists of room for n survivors
+// (8 bytes each) used in turn; split_scratch_words gives the size. The caller's buffer of
+// that size, else one allocated for this call on s and freed after it.
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t budget, uint32_t klog2, uint32_t* scratch, hipStream_t s) {
+                              uint32_t budget, uint32_t klog2, uint32_t rounds, uint32_t* scratch, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 31)) {
     hvf_set_error("at most 2^31 - 1 rays per split call");
@@ -1019,17 +1086,25 @@ hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_r
       per_cu < 1)
     per_cu = 1;
   const unsigned grid2 = (unsigned)(g_cu_count * per_cu);
+  if (rounds > HVF_SPLIT_MAX_ROUNDS || ((uint64_t)budget << (rounds ? rounds - 1 : 0)) >= (1ull << 31)) {
+    hvf_set_error("split schedule: too many restart rounds for the budget");
+    return HVF_E_INPUT;
+  }
   const bool own = scratch == nullptr;
   if (own) {
-    const hipError_t e = scratch_alloc(reinterpret_cast<void**>(&scratch), (2 + 2 * n) * sizeof(uint32_t), s);
+    const hipError_t e =
+        scratch_alloc(reinterpret_cast<void**>(&scratch), split_scratch_words(n, rounds) * sizeof(uint32_t), s);
     if (e != hipSuccess) {
-      hvf_set_error(std::string("allocation of the split schedule's survivor list: ") + hipGetErrorString(e));
+      hvf_set_error(std::string("allocation of the split schedule's survivor lists: ") + hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? HVF_E_NOMEM : HVF_E_DEVICE;
     }
   }
-  uint32_t* nsurv = scratch;
-  uint2* surv = reinterpret_cast<uint2*>(scratch + 2);
-  hvf_status st = launch_fill_u32(scratch, 0u, 2, s);
+  uint32_t* cnt = scratch;
+  uint2* lists[2] = {reinterpret_cast<uint2*>(scratch + HVF_SPLIT_HEAD_WORDS),
+                     reinterpret_cast<uint2*>(scratch + HVF_SPLIT_HEAD_WORDS + 2 * n)};
+  uint32_t* nsurv = cnt;
+  uint2* surv = lists[0];
+  hvf_status st = launch_fill_u32(scratch, 0u, HVF_SPLIT_HEAD_WORDS, s);
   if (st != HVF_OK) {
     if (own) (void)hipFreeAsync(scratch, s);
     return st;
@@ -1043,6 +1118,19 @@ hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_r
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_BUDGET)
 #undef HVF_LAUNCH_BUDGET
   st = launch_check("budgeted trace");
+  for (uint32_t k = 1; k <= rounds && st == HVF_OK; ++k) {
+    const uint32_t bk = budget << (k - 1);
+    uint2* const in = lists[(k - 1) & 1u];
+    uint2* const out = lists[k & 1u];
+#define HVF_LAUNCH_RESUME(FAMV)                                                                                      \
+  hipLaunchKernelGGL(trace_resume_kernel<FAMV>, dim3(grid2), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, in, cnt + k - 1, \
+                     bk, out, cnt + k)
+    HVF_FAMILY_SWITCH(family, HVF_LAUNCH_RESUME)
+#undef HVF_LAUNCH_RESUME
+    st = launch_check("restart round of the split schedule");
+    surv = out;
+    nsurv = cnt + k;
+  }
   if (st == HVF_OK) {
 #define HVF_LAUNCH_SPLIT(FAMV)                                                                                    \
   hipLaunchKernelGGL(trace_split_kernel<FAMV>, dim3(grid2), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, surv, nsurv, \

@@ -98,7 +98,10 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(lds_depths=2, sort=1, sort_bits=4),
              dict(split=2, split_budget=1), dict(split=4, split_budget=3), dict(split=8, split_budget=8),
              dict(split=64, split_budget=2), dict(split=16, split_budget=32), dict(split=32, split_budget=5),
-             dict(split=8, split_budget=4, lds_depths=2), dict(split=4, split_budget=2, stack_depth=2)]
+             dict(split=8, split_budget=4, lds_depths=2), dict(split=4, split_budget=2, stack_depth=2),
+             dict(split=8, split_budget=2, split_rounds=2), dict(split=64, split_budget=1, split_rounds=6),
+             dict(split=2, split_budget=3, split_rounds=1), dict(split=4, split_budget=3, split_rounds=1, lds_depths=2),
+             dict(split=16, split_budget=4, split_rounds=3, stack_depth=2)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
@@ -187,7 +190,7 @@ def test_concurrent_traces_of_one_volume(H):
                                              W.random_rays(s, (128,) * 3, 20000)])).cuda() for s in range(6)]
     plain = [v.trace(r) for r in rays]
     torch.cuda.synchronize()
-    scheds = [H.schedule(sort=1, sort_bits=2), H.schedule(split=8, split_budget=4), H.schedule(persistent=1),
+    scheds = [H.schedule(sort=1, sort_bits=2), H.schedule(split=8, split_budget=4, split_rounds=1), H.schedule(persistent=1),
               H.schedule(sort=1, sort_bits=4), H.schedule(split=4, split_budget=2), H.schedule(persistent=1, refill=8)]
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     outs = [torch.full((r.shape[0], 4), 7, dtype=torch.int32, device="cuda") for r in rays]
@@ -219,7 +222,7 @@ def test_concurrent_traces_of_one_volume(H):
     # Split traces on the default stream from four host threads: they share the volume's
     # survivor list when it is free, take their own scratch when it is held, and the shared
     # list grows for the larger ray sets mid-way.
-    split = [H.schedule(split=8, split_budget=4), H.schedule(split=4, split_budget=2)]
+    split = [H.schedule(split=8, split_budget=4), H.schedule(split=4, split_budget=2, split_rounds=2)]
     order = [rays[0][:5000], rays[1], rays[2][:777]] + rays[3:]
     want = [v.trace(r) for r in order]
     torch.cuda.synchronize()

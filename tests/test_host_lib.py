@@ -227,9 +227,13 @@ def test_schedule_checks_split_fields():
     bad = [H.schedule(split=3, split_budget=8), H.schedule(split=1, split_budget=8), H.schedule(split=128, split_budget=8),
            H.schedule(split=4, split_budget=0), H.schedule(split=4, split_budget=(1 << 20) + 1),
            H.schedule(split=4, split_budget=8, persistent=1), H.schedule(split=4, split_budget=8, sort=1),
-           H.schedule(split=-2, split_budget=8)]
+           H.schedule(split=-2, split_budget=8), H.schedule(split=4, split_budget=8, split_rounds=7),
+           H.schedule(split_rounds=1), H.schedule(split=4, split_budget=8, split_rounds=-1)]
     for sc in bad:
         st = H.lib().hvf_trace_sched(v.handle, None, 1, None, ctypes.byref(sc), None)
         assert H.STATUS[st] == "HVF_E_INPUT", H.schedule_dict(sc)
     assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(split=8, split_budget=64))) == [
         f"trace_budget_kernel<{v.info()['kernel_family']}u>", f"trace_split_kernel<{v.info()['kernel_family']}u>"]
+    fam = v.info()["kernel_family"]
+    assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(split=8, split_budget=64, split_rounds=2))) == [
+        f"trace_budget_kernel<{fam}u>", f"trace_resume_kernel<{fam}u>", f"trace_split_kernel<{fam}u>"]
