@@ -408,7 +408,9 @@ def run_surface2048(args, torch, H, W, C):
         # has more hits than view 0, and a schedule's gain depends on the launch size).
         sched_b = H.schedule_dict(v.autotune(torch.from_numpy(bh[:len(b)].copy()).cuda())) if not args.no_tune else sched_p
         ms_b, _ = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
-        # untuned comparison after the timed launches (a profile of those stays unmixed)
+        frames = run_frames2048(args, torch, H, W, C, v, cfg, b)
+        # untuned comparison after the timed launches (a profile of those stays unmixed; the
+        # one-lane-per-ray launches of both grids are the run's last ones)
         ms_p0, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
         ms_b0, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
         rng = np.random.default_rng(7)
@@ -434,6 +436,7 @@ def run_surface2048(args, torch, H, W, C):
             r["achieved_gbs"] = r["B_ray_sector"] * r["rays"] / (r["ms"] * 1e-3) / 1e9
             r["frac_roofline"] = r["achieved_gbs"] / HBM_PEAK_GBS
             r.update({kk: round(vv, 4) for kk, vv in r.items() if isinstance(vv, float)})
+        rec["incoherent_8_frames"] = frames
         log(f"[bench]   2048 {spec:36s} primary {rec['primary']['mrays_s']:8.1f} Mrays/s "
             f"({rec['primary']['frac_roofline']:.1%}, untuned {rec['primary']['mrays_s_untuned']:.1f}, {sched_p})  "
             f"incoherent {rec['incoherent']['mrays_s']:8.1f} Mrays/s ({rec['incoherent']['frac_roofline']:.1%}, "
@@ -441,6 +444,56 @@ def run_surface2048(args, torch, H, W, C):
         out.append(rec)
         v.close()
     return {"occupancy": len(codes) / n ** 3, "formats": out}
+
+
+def frame_bounces(torch, H, W, C, v, cfg, views, seed0):
+    """Bounce rays of several 1080p frames of the 2048^3 volume, concatenated: each view's
+    primary rays are traced (plain schedule) and one cosine-weighted bounce is drawn per hit
+    with a seed of its own."""
+    out = []
+    for j in views:
+        prim = C.primary_rays(cfg, j)
+        h = v.trace(torch.from_numpy(prim).cuda(), sched=H.schedule())
+        torch.cuda.synchronize()
+        b, _ = W.bounce_rays(seed0 + j, prim, h.cpu().numpy())
+        out.append(b)
+    return np.concatenate(out)
+
+
+def run_frames2048(args, torch, H, W, C, v, cfg, b0):
+    """The bounce rays of 8 frames (8 seeded views; view 0's are the one-frame launch's)
+    traced in one launch, as a wavefront renderer gathers secondary rays over frames or
+    samples: the one-frame launch leaves most of the device idle in its tail. Tuned on 8
+    held-out frames, truncated to the same ray count."""
+    views = cfg["frame_views"]
+    b8 = np.concatenate([b0, frame_bounces(torch, H, W, C, v, cfg, views[1:], cfg["bounce_seed"])])
+    d8 = torch.from_numpy(b8).cuda()
+    h8 = torch.empty((len(b8), 4), dtype=torch.int32, device="cuda")
+    plain = H.schedule()
+    if args.no_tune:
+        sched = H.schedule_dict(plain)
+    else:
+        bt = frame_bounces(torch, H, W, C, v, cfg, cfg["tune_frame_views"], cfg["bounce_seed"] + 1000)[:len(b8)]
+        sched = H.schedule_dict(v.autotune(torch.from_numpy(np.ascontiguousarray(bt)).cuda()))
+        del bt
+    ms, _ = time_launches([lambda: v.trace(d8, h8)], args.steps, args.warmup)
+    ms0, _ = time_launches([lambda: v.trace(d8, h8, sched=plain)], args.steps, args.warmup)
+    if args.sample > 0:
+        rng = np.random.default_rng(8)
+        _, bs, lb, _, _ = byte_model(v, torch.from_numpy(b8[rng.choice(len(b8), min(args.sample, len(b8)),
+                                                                            replace=False)]).cuda())
+    else:
+        bs = lb = float("nan")
+    r = {"frames": len(views), "views": views, "rays": len(b8), "ms": ms, "mrays_s": len(b8) / ms / 1e3,
+         "B_ray_sector": bs, "loads_per_ray": lb, "schedule": sched, "kernel": H.kernel_name(v.info(), sched),
+         "avg_launch_us": ms * 1e3, "mrays_s_untuned": len(b8) / ms0 / 1e3}
+    r["achieved_gbs"] = r["B_ray_sector"] * r["rays"] / (r["ms"] * 1e-3) / 1e9
+    r["frac_roofline"] = r["achieved_gbs"] / HBM_PEAK_GBS
+    r.update({k: round(x, 4) for k, x in r.items() if isinstance(x, float)})
+    log(f"[bench]   2048 incoherent, {len(views)} frames in one launch: {r['mrays_s']:8.1f} Mrays/s "
+        f"({r['frac_roofline']:.1%}, untuned {r['mrays_s_untuned']:.1f}, {sched})")
+    del d8, h8
+    return r
 
 
 def run_bounce2048(args, torch, H, W, C):

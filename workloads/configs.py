@@ -61,7 +61,10 @@ def table_spec(spec: str) -> str:
 # 2048^3 surface volume: 96 spheres + 32 tori; SVDAG top 7 levels -> Raw 16^3 bricks, and
 # SVO -> Raw 8^3; 1080p primary rays plus one cosine-weighted bounce per primary hit.
 SURF2048 = dict(name="surface-2048", log2n=11, seed=3, n_sph=96, n_tor=32, scale=1.2, width=1920, height=1080,
-                views=1, specs=["G(7) R(4,4,4) --whole-level-dedup", "S(8) R(3,3,3)"], bounce_seed=33)
+                views=1, specs=["G(7) R(4,4,4) --whole-level-dedup", "S(8) R(3,3,3)"], bounce_seed=33,
+                # 8 frames whose bounce rays are traced in one launch (view 1 is the autotuner's
+                # held-out view of the one-frame launches), and 8 held-out frames to tune it on
+                frame_views=[0, 2, 3, 4, 5, 6, 7, 8], tune_frame_views=list(range(9, 17)))
 
 
 # Formats of the 2048^3 volume whose construction (host against device) the bench line reports.
