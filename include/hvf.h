@@ -160,10 +160,12 @@ hvf_status hvf_build_device(const char* format_spec, const uint64_t* d_morton, s
 hvf_status hvf_upload(hvf_volume* vol, void* hip_stream);
 
 /* Concurrency: traces of one volume may run concurrently, on any streams and from any
- * host threads, with any schedules (sorting and splitting take per-call scratch from the
- * stream-ordered allocator; at most 64 persistent traces of one volume may be in flight at
- * once). hvf_set_schedule and hvf_autotune must not run concurrently with traces of the
- * same volume. */
+ * host threads, with any schedules. Sorting takes per-call scratch from the stream-ordered
+ * allocator. Splitting on the legacy default stream (NULL) reuses one survivor list per
+ * volume, which that stream's ordering protects; on other streams, or when another host
+ * thread holds the list, it takes per-call scratch as sorting does. At most 64 persistent
+ * traces of one volume may be in flight at once. hvf_set_schedule and hvf_autotune must
+ * not run concurrently with traces of the same volume. */
 
 /* Trace n rays (Sec. 4.2). d_rays, d_hits: device pointers to n hvf_ray / hvf_hit,
  * caller-owned. Asynchronous on hip_stream; the caller synchronises. Uploads the volume
