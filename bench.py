@@ -303,6 +303,62 @@ def run_sweep(args, torch, H, W, C):
     return out
 
 
+def run_sweep_paper(args, torch, H, W, C):
+    """The format sweep in both layouts: every format of the paper's table built in the
+    library's own layout and in the paper's word layout (--paper-layout, RGBA voxel words),
+    each traced with one lane per ray on 1080p primary rays of view 0 (at 2048^3 also their
+    bounce rays). The two layouts' hits are compared bit for bit on every launch."""
+    out = []
+    for log2n, cfg in ((9, C.SURF512), (11, C.SURF2048)):
+        codes = C.scene(cfg)
+        prim = C.primary_rays(cfg, 0)
+        d_prim = torch.from_numpy(prim).cuda()
+        h = torch.empty((len(prim), 4), dtype=torch.int32, device="cuda")
+        h_own = torch.empty_like(h)
+        d_b = hb = hb_own = None
+        plain = H.schedule()
+        for label, k, spec in C.TABLE_FORMATS:
+            if k != log2n:
+                continue
+            sp = C.table_spec(spec)
+            own = H.Volume(sp, codes)
+            t0 = time.time()
+            v = H.Volume(sp + " --paper-layout", codes)
+            tb = time.time() - t0
+            own.trace(d_prim, h_own, sched=plain)
+            ms_own, _ = time_launches([lambda: own.trace(d_prim, h_own, sched=plain)], args.steps, args.warmup)
+            ms, _ = time_launches([lambda: v.trace(d_prim, h, sched=plain)], args.steps, args.warmup)
+            torch.cuda.synchronize()
+            if not torch.equal(h, h_own):
+                raise RuntimeError(f"paper layout and own layout differ on {sp} primary rays")
+            rec = {"label": label, "format": sp, "side": 1 << k, "bytes": own.info()["bytes"],
+                   "paper_bytes": v.info()["bytes"], "paper_build_s": round(tb, 2),
+                   "primary_mrays_s": round(len(prim) / ms_own / 1e3, 1),
+                   "paper_primary_mrays_s": round(len(prim) / ms / 1e3, 1)}
+            if k == 11:
+                if d_b is None:
+                    b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h_own.cpu().numpy())
+                    d_b = torch.from_numpy(b).cuda()
+                    hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+                    hb_own = torch.empty_like(hb)
+                msb_own, _ = time_launches([lambda: own.trace(d_b, hb_own, sched=plain)], args.steps, args.warmup)
+                msb, _ = time_launches([lambda: v.trace(d_b, hb, sched=plain)], args.steps, args.warmup)
+                torch.cuda.synchronize()
+                if not torch.equal(hb, hb_own):
+                    raise RuntimeError(f"paper layout and own layout differ on {sp} bounce rays")
+                rec["bounce_mrays_s"] = round(d_b.shape[0] / msb_own / 1e3, 1)
+                rec["paper_bounce_mrays_s"] = round(d_b.shape[0] / msb / 1e3, 1)
+            log(f"[bench] sweep-paper {label:2d} {sp:44s} own {rec['bytes'] / 2 ** 20:8.1f} MiB "
+                f"{rec['primary_mrays_s']:8.1f}  paper {rec['paper_bytes'] / 2 ** 20:8.1f} MiB "
+                f"{rec['paper_primary_mrays_s']:8.1f} Mrays/s primary"
+                + (f"; bounce own {rec['bounce_mrays_s']:7.1f} paper {rec['paper_bounce_mrays_s']:7.1f}"
+                   if "bounce_mrays_s" in rec else "") + f" (paper build {tb:.1f} s)")
+            out.append(rec)
+            v.close()
+            own.close()
+    return out
+
+
 def run_construction(args, torch, H, C, formats_2048=None):
     """Format construction from sorted Morton codes: the host builder plus the upload of its
     buffer, against hvf_build_device on codes already resident on the device (median of
@@ -707,7 +763,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep", "build",
+    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep",
+                                       "sweep-paper", "build",
                              "restart"],
                     default=None,
                     help="run one workload only (for profiling); prints no bench line")
@@ -741,6 +798,9 @@ def main():
         return
     if args.only == "sweep":
         print(json.dumps({"format_sweep": run_sweep(args, torch, H, W, C)}))
+        return
+    if args.only == "sweep-paper":
+        print(json.dumps({"format_sweep_layouts": run_sweep_paper(args, torch, H, W, C)}))
         return
     if args.only == "batched":
         run_batched(args, torch, H, W, C)

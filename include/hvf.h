@@ -81,6 +81,8 @@ typedef struct hvf_info {
   int32_t level_maxdist[HVF_MAX_LEVELS]; /* DF levels: the maximum stored distance M; else 0 */
   uint32_t kernel_family;               /* template argument of the trace kernels this volume
                                            launches (node/header kinds compiled in) */
+  int32_t paper_layout;                 /* 1: built with --paper-layout (the paper's word
+                                           layout, Sec. 3.3); 0: the library's own layout */
 } hvf_info;
 
 /* How a trace is scheduled on the device. Results never depend on it.

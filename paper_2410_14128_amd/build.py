@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libhvf.so")
-SOURCES = ["hvf_build.cpp", "hvf_api.hip", "hvf_trace.hip", "hvf_batch.hip", "hvf_server.hip", "hvf_devbuild.hip"]
+SOURCES = ["hvf_build.cpp", "hvf_paper.cpp", "hvf_api.hip", "hvf_trace.hip", "hvf_batch.hip", "hvf_server.hip", "hvf_devbuild.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

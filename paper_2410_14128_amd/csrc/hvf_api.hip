@@ -13,7 +13,7 @@
 namespace hvf {
 hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                         hipStream_t s);
-hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
+hvf_status launch_trace_count(const DevFormat& F, bool paper, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
                               uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s);
 hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                                    uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid, hipStream_t s);
@@ -77,8 +77,13 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
   hvf_volume* v = new (std::nothrow) hvf_volume();
   if (!v) return fail(HVF_E_NOMEM, "host allocation failed");
   v->spec = spec;
-  v->layout = hvf::make_layout(spec);
-  st = hvf::build_words(v->spec, v->layout, morton, n, v->built, err);
+  if (spec.paper) {
+    v->layout = hvf::make_paper_layout(spec);
+    st = hvf::build_paper_words(v->spec, v->layout, morton, n, v->built, err);
+  } else {
+    v->layout = hvf::make_layout(spec);
+    st = hvf::build_words(v->spec, v->layout, morton, n, v->built, err);
+  }
   if (st != HVF_OK) {
     delete v;
     return fail(st, err);
@@ -137,6 +142,8 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (!d_rays || !d_hits) return fail(HVF_E_INPUT, "null ray or hit buffer");
   st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
+  if (v->spec.paper && (sc.stack_depth > 0 || sc.lds_depths > 0))
+    return fail(HVF_E_INPUT, "short stacks and staged depths need the library's own layout, not --paper-layout");
   hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
   if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
   if (!hvf::lds_prefix_words(v->layout, v->built, sc.lds_depths, &F.lds_words))
@@ -202,8 +209,9 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
   std::vector<hvf_schedule> cand;
   cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0});
   const int nd = (int)v->layout.d.size();
+  const bool own_layout = !v->spec.paper;  // short stacks and staged depths need it
   for (int sd : {2, 4})
-    if (sd < nd) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, sd, 0});
+    if (own_layout && sd < nd) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, sd, 0});
   for (int bpc : {0, 2, 4})
     for (int refill : {8, 32})
       for (int inner : {4, 16}) cand.push_back(hvf_schedule{1, refill, inner, 0, 4, bpc, 0, 0});
@@ -247,7 +255,7 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
     const hvf_schedule top = cand[r1[0].second];
     uint32_t last = 0;
     int tried = 0;
-    for (int k = nd; k >= 1 && tried < 3; --k) {
+    for (int k = nd; own_layout && k >= 1 && tried < 3; --k) {
       uint32_t w = 0;
       if (!hvf::lds_prefix_words(v->layout, v->built, k, &w) || w == 0 || w == last) continue;
       last = w;
@@ -313,7 +321,8 @@ hvf_status hvf_trace_count(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   hvf_status st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
   const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
-  return hvf::launch_trace_count(F, d_rays, n, d_hits, d_log, cap, d_count, d_steps, (hipStream_t)stream);
+  return hvf::launch_trace_count(F, v->spec.paper, d_rays, n, d_hits, d_log, cap, d_count, d_steps,
+                                 (hipStream_t)stream);
 }
 
 hvf_status hvf_trace_host(hvf_volume* v, const hvf_ray* rays, size_t n, hvf_hit* hits) {
@@ -399,6 +408,7 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
   }
   I.num_voxels = v->built.nvox;
   I.kernel_family = hvf::FAMILIES[hvf::family_of(v->layout)];
+  I.paper_layout = v->spec.paper ? 1 : 0;
   *out = I;
   return HVF_OK;
 }
@@ -512,7 +522,7 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
     hvf_status st = hvf::parse_spec(text.c_str(), v->spec, err);
     ok = (st == HVF_OK);
     if (ok) {
-      v->layout = hvf::make_layout(v->spec);
+      v->layout = v->spec.paper ? hvf::make_paper_layout(v->spec) : hvf::make_layout(v->spec);
       ok = v->layout.d.size() == nd && v->spec.lv.size() == nl;
     }
   }

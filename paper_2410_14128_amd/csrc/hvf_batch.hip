@@ -111,6 +111,11 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
       delete b;
       return fail(HVF_E_INPUT, "null volume or buffer in batch " + std::to_string(i));
     }
+    if (vols[i]->spec.paper) {
+      delete b;
+      return fail(HVF_E_UNSUPPORTED, "batched launches take volumes in the library's own layout (batch " +
+                                         std::to_string(i) + " has --paper-layout)");
+    }
     st = hvf_upload(vols[i], nullptr);
     if (st != HVF_OK) {
       delete b;

@@ -71,6 +71,8 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
         s.wld = true;
       } else if (flag == "--restart-sv" || flag == "-restart-sv") {
         s.restart_sv = true;
+      } else if (flag == "--paper-layout") {
+        s.paper = true;
       } else {
         err = "unknown flag '" + flag + "'";
         return HVF_E_SPEC;
@@ -173,6 +175,17 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
   if (depths > HVF_MAX_DEPTH) {
     err = "more than 16 node depths";
     return HVF_E_SPEC;
+  }
+  if (s.paper) {
+    if (s.restart_sv) {
+      err = "--restart-sv is not supported with --paper-layout";
+      return HVF_E_UNSUPPORTED;
+    }
+    for (const LevelSpec& L : s.lv)
+      if (L.kind == LK_RAW && std::max(L.e[0], std::max(L.e[1], L.e[2])) > 15) {
+        err = "--paper-layout walks a Raw level as one depth: at most 2^15 cells per axis";
+        return HVF_E_SPEC;
+      }
   }
   out = s;
   return HVF_OK;

@@ -26,6 +26,7 @@ struct Spec {
   std::vector<LevelSpec> lv;
   bool wld = false;         // whole-level de-duplication of SVDAG nodes (Sec. 4.3)
   bool restart_sv = false;  // restarting sparse-voxel intersection (Sec. 4.3)
+  bool paper = false;       // --paper-layout: the paper's word layout with RGBA voxels
   int ext[3] = {0, 0, 0};
   std::vector<int> sub;  // sub[k]: log2 side (voxels) of a level-k sub-volume, k >= 1; sub[n] = 0
   std::string text;
@@ -53,8 +54,16 @@ enum NodeKind : int {
   NK_OCT_PTR = 6,    // child pointer word at base + rank (SVDAG nodes; SVO nodes of the
                      // deepest octree depth above the last level)
   NK_OCT_FINAL = 7,  // deepest octree depth of the last level: valid mask = occupancy
-  NK_DAG_INNER = 8   // SVDAG node whose children are SVDAG nodes: a 2-word descriptor
+  NK_DAG_INNER = 8,  // SVDAG node whose children are SVDAG nodes: a 2-word descriptor
                      // (child pointer, child masks) per valid child at base + 2 * rank
+  // Kinds of the paper's own layout (--paper-layout; see make_paper_layout):
+  NK_PRAW_VOX = 9,    // last Raw level: one RGBA word per voxel, 0 = empty
+  NK_PSVO_TERM = 10,  // last SVO depth above the last level: the child's first word (at
+                      // base + 2 * rank) points to the next level's sub-volume
+  NK_PDAG_TERM = 11,  // last SVDAG depth above the last level: the child pointer (at
+                      // base + rank) points to a word that points to the next sub-volume
+  NK_PDF_PTR = 12,    // DF level above the last: (pointer or 0, capped L1 distance) per cell
+  NK_PDF_VOX = 13     // last DF level: (RGBA word or 0, capped L1 distance) per voxel
 };
 constexpr uint32_t DF_EMPTY = 0x80000000u;  // marks an empty cell word of a DF pointer grid
 enum HeaderKind : int {
@@ -81,6 +90,9 @@ struct Layout {
 };
 
 Layout make_layout(const Spec& s);
+// Depths walking the paper's own layout (hvf_paper.cpp): one per Raw/DF level, L per
+// SVO/SVDAG level, with the NK_P* kinds at the levels' last depths.
+Layout make_paper_layout(const Spec& s);
 
 // ------------------------------------------------------------------ built word buffer
 struct Built {
@@ -91,6 +103,10 @@ struct Built {
 
 hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, size_t n, Built& out,
                        std::string& err);
+// The paper's layout (hvf_paper.cpp); depth_nodes / depth_offset stay zero (its nodes are in
+// construction order, not grouped by depth).
+hvf_status build_paper_words(const Spec& s, const Layout& L, const uint64_t* codes, size_t n, Built& out,
+                             std::string& err);
 
 // ------------------------------------------------------------------ device descriptor
 // One packed word per depth: nk | hk << 4 | cs << 8 | wx << 12 | wy << 16 | wz << 20.
@@ -160,9 +176,15 @@ constexpr uint32_t FAM_BRICK = fam_nk(NK_BLOCKS) | fam_nk(NK_CELLS) | fam_hk(HK_
                                fam_hk(HK_MASKLOAD);
 // SVO and SVDAG levels mixed above a brick.
 constexpr uint32_t FAM_OCT_BRICK = FAM_DAG_BRICK | FAM_SVO_BRICK;
-constexpr uint32_t FAMILIES[] = {FAM_BRICK,    FAM_DAG_BRICK, FAM_SVO_BRICK,  FAM_RAW_BRICK, FAM_OCTREE,   FAM_RAW_OCTREE,
-                                 FAM_DF_BRICK, FAM_DF_OCTREE, FAM_OCT_BRICK, FAM_NODF,      FAM_ALL};
-constexpr int NUM_FAMILIES = 11;
+// The paper's own layout (--paper-layout): Raw, DF, SVO and SVDAG levels as the paper
+// stores them. Binary layouts never need its NK_P* kinds, so they never land here.
+constexpr uint32_t FAM_PAPER = fam_nk(NK_RAW_PTR) | fam_nk(NK_PRAW_VOX) | fam_nk(NK_PDF_PTR) | fam_nk(NK_PDF_VOX) |
+                               fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_OCT_FINAL) |
+                               fam_nk(NK_PSVO_TERM) | fam_nk(NK_PDAG_TERM) | fam_hk(HK_RAW) | fam_hk(HK_SVO) |
+                               fam_hk(HK_DAG);
+constexpr uint32_t FAMILIES[] = {FAM_BRICK,    FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE,
+                                 FAM_DF_BRICK, FAM_DF_OCTREE, FAM_OCT_BRICK, FAM_NODF,      FAM_PAPER,  FAM_ALL};
+constexpr int NUM_FAMILIES = 12;
 // Families whose kernels take every depth to be cubic (w equal on the three axes: the root
 // is an octree level, and levels below the first are cubic), and the one whose depths all
 // have w = 1 (octree levels only). family_of assigns them only to layouts that are.

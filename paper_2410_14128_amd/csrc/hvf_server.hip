@@ -348,6 +348,7 @@ hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_ste
 
 hvf_status hvf_server_add_volume(hvf_server* S, hvf_volume* v, int* vol_id) {
   if (!S || !v || !vol_id) return fail(HVF_E_INPUT, "null argument");
+  if (v->spec.paper) return fail(HVF_E_UNSUPPORTED, "the server takes volumes in the library's own layout, not --paper-layout");
   hvf_status st = hvf_upload(v, nullptr);
   if (st != HVF_OK) return st;
   std::lock_guard<std::mutex> lk(S->mu);

@@ -360,9 +360,12 @@ struct Walk {
     uint32_t child = 0u;
     uint2 cm = make_uint2(0u, 0u);
     float tf[3], m;
-    constexpr uint32_t OCT = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_FINAL);
+    constexpr uint32_t OCT = fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_DAG_INNER) | fam_nk(NK_OCT_FINAL) |
+                             fam_nk(NK_PSVO_TERM) | fam_nk(NK_PDAG_TERM);
+    const bool dfk = ((FAM & fam_nk(NK_DF_PTR)) && nk == NK_DF_PTR) || ((FAM & fam_nk(NK_DF_BLOCKS)) && nk == NK_DF_BLOCKS) ||
+                     ((FAM & fam_nk(NK_PDF_PTR)) && nk == NK_PDF_PTR) || ((FAM & fam_nk(NK_PDF_VOX)) && nk == NK_PDF_VOX);
     const uint32_t rank = (FAM & OCT) ? (uint32_t)__popc(valid & ((1u << lin) - 1u)) : 0u;
-    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS)) {
+    if (dfk) {
       // Cell positions at this depth are multiples of 2^cs, so the shift is exact.
       const uint32_t l1 = (uint32_t)(abs(p[0] - a[0]) + abs(p[1] - a[1]) + abs(p[2] - a[2])) >> cs;
       occ = false;
@@ -373,6 +376,12 @@ struct Walk {
           mem.note(base + lin, 1);
           occ = (child & DF_EMPTY) == 0u;
           dist = child & ~DF_EMPTY;
+        } else if ((FAM & (fam_nk(NK_PDF_PTR) | fam_nk(NK_PDF_VOX))) && (nk == NK_PDF_PTR || nk == NK_PDF_VOX)) {
+          const uint2 q = F.template w2<FAM>(base + 2u * lin);  // (terminating integer, distance)
+          mem.note(base + 2u * lin, 2);
+          child = q.x;
+          occ = q.x != 0u;
+          dist = q.y;
         } else {
           const uint4 q = F.template w4<FAM>(base + 4u * lin);
           mem.note(base + 4u * lin, 4);
@@ -392,15 +401,20 @@ struct Walk {
       // cell, a block mask, or the occupied octree child's pointer or (pointer, masks)
       // descriptor. The device buffer ends with spare zero words, so a read that starts at
       // its last word stays inside the allocation.
-      const bool rawk = (FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR;
+      // Each kind is tested only in families that compile it in, so the families of the
+      // library's own layout carry no test for the paper layout's kinds.
+      const bool rawk = ((FAM & fam_nk(NK_RAW_PTR)) && nk == NK_RAW_PTR) ||
+                        ((FAM & fam_nk(NK_PRAW_VOX)) && nk == NK_PRAW_VOX);
       const bool blk = (FAM & fam_nk(NK_BLOCKS)) && nk == NK_BLOCKS;
-      const bool optr = (FAM & fam_nk(NK_OCT_PTR)) && nk == NK_OCT_PTR;
-      const bool dagi = (FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER;
+      const bool optr = ((FAM & fam_nk(NK_OCT_PTR)) && nk == NK_OCT_PTR) ||
+                        ((FAM & fam_nk(NK_PDAG_TERM)) && nk == NK_PDAG_TERM);
+      const bool dagi = ((FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER) ||
+                        ((FAM & fam_nk(NK_PSVO_TERM)) && nk == NK_PSVO_TERM);
       const uint32_t idx = rawk ? lin : (blk ? 2u * lin : (dagi ? 2u * rank : rank));
       uint2 q = make_uint2(0u, 0u);
       if (rawk || blk || ((optr || dagi) && occ)) {
         q = F.template w2<FAM>(base + idx);
-        mem.note(base + idx, (blk || dagi) ? 2u : 1u);
+        mem.note(base + idx, (blk || (FAM & fam_nk(NK_DAG_INNER) && nk == NK_DAG_INNER)) ? 2u : 1u);
       }
       // The far-plane times below do not depend on the read: computing them before its
       // first use lets the load's latency overlap them. The empty asm statement takes them
@@ -412,8 +426,13 @@ struct Walk {
       if (rawk) occ = child != 0u;
       if (blk) occ = (cm.x | cm.y) != 0u;
       if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) child = base + 2u * rank;
+      if ((FAM & fam_nk(NK_PDAG_TERM)) && nk == NK_PDAG_TERM && occ) {  // the leaf word holds the pointer
+        child = F.template w1<FAM>(child);
+        mem.note(q.x, 1);
+      }
     }
-    const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL);
+    const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL) ||
+                     ((FAM & fam_nk(NK_PRAW_VOX)) && nk == NK_PRAW_VOX) || ((FAM & fam_nk(NK_PDF_VOX)) && nk == NK_PDF_VOX);
     if (occ && !fin) {
       if (F.stacked == ALL_STACKED)  // uniform: every depth has a slot, slot = depth
         stk[d * BLOCK] = make_uint2(base, valid);
@@ -430,8 +449,7 @@ struct Walk {
     }
     // Far-plane times of the current cell (computed above on the common path): the advance
     // below needs them, and for an occupied voxel they decide the hit.
-    if ((FAM & (fam_nk(NK_DF_PTR) | fam_nk(NK_DF_BLOCKS))) && (nk == NK_DF_PTR || nk == NK_DF_BLOCKS))
-      far_times(cs, tf, m);
+    if (dfk) far_times(cs, tf, m);
     const int stepv = 1 << cs;
     // An occupied single voxel. The walk's t is always the entry time of its current cell:
     // the root cell is entered at t0, an advance enters the next cell at the crossing time
@@ -977,6 +995,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
 
 // Same traversal as trace_kernel, logging the word index of every format load:
 // log[i * cap + k] for the first cap loads of ray i; count[i] = number of loads.
+template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n,
                                                             uint32_t* __restrict__ log, uint32_t cap,
@@ -994,8 +1013,8 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
   Walk w;
   Counting mem{log + (size_t)i * cap, cap, 0u};
   w.steps = 0;
-  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM_ALL>(fm, mem) == RUN)
-    while (w.template step<FAM_ALL>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
+  if (setup(r0, r1, F.ext, w.R) && w.template start<FAM>(fm, mem) == RUN)
+    while (w.template step<FAM>(fm, stk_all + threadIdx.x, out, mem) == RUN) {
     }
   put_hit(hits, i, out);
   count[i] = mem.k;
@@ -1032,6 +1051,7 @@ size_t stack_lds_bytes(const DevFormat& F) {
     case 7: LAUNCH(FAM_DF_OCTREE); break;    \
     case 8: LAUNCH(FAM_OCT_BRICK); break;    \
     case 9: LAUNCH(FAM_NODF); break;         \
+    case 10: LAUNCH(FAM_PAPER); break;       \
     default: LAUNCH(FAM_ALL); break;         \
   }
 
@@ -1299,17 +1319,23 @@ hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, s
   return st;
 }
 
-hvf_status launch_trace_count(const DevFormat& F, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
-                              uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s) {
+// The generic family walks every layout of the library's own; the paper's layout has its own.
+hvf_status launch_trace_count(const DevFormat& F, bool paper, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                              uint32_t* d_log, uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32)) {
     hvf_set_error("at most 2^32 - 1 rays per call");
     return HVF_E_INPUT;
   }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-  hipLaunchKernelGGL(trace_count_kernel, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
-                     reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log, cap,
-                     d_count, d_steps);
+  if (paper)
+    hipLaunchKernelGGL(trace_count_kernel<FAM_PAPER>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                       reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log,
+                       cap, d_count, d_steps);
+  else
+    hipLaunchKernelGGL(trace_count_kernel<FAM_ALL>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                       reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log,
+                       cap, d_count, d_steps);
   return launch_check("counting trace");
 }
 
