@@ -130,10 +130,18 @@ typedef struct hvf_schedule {
  *   --restart-sv: restarting sparse-voxel intersection (Sec. 4.3): inside SVO/SVDAG levels
  *   no per-lane node stack is kept; after leaving a node the walk descends again from the
  *   level's root along the current position. Results are unchanged.
+ *   --paper-layout: store the format in the paper's own word layout (Sec. 3.3, 4.1) instead
+ *   of the library's: each level's child sub-volumes written before it, in Morton order of
+ *   the cells; Raw cells and SVO/SVDAG leaves hold terminating integers (a pointer, or an
+ *   occupied voxel's RGBA word 0xFFFFFFFF); an SVO node is (pointer to its children, masks),
+ *   an SVDAG node its masks followed by one pointer per child; a DF cell is (terminating
+ *   integer, capped distance). Results are unchanged; the buffer is larger for Raw- and
+ *   SVO-final formats and smaller for deep SVDAGs. Not with --restart-sv (HVF_E_UNSUPPORTED),
+ *   nor with short stacks or staged LDS depths, batches, the server or hvf_build_device.
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
  *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
  * out: receives a new handle owned by the caller (release with hvf_free).
- * Errors: HVF_E_SPEC, HVF_E_INPUT, HVF_E_OVERFLOW, HVF_E_NOMEM.
+ * Errors: HVF_E_SPEC, HVF_E_INPUT, HVF_E_OVERFLOW, HVF_E_NOMEM, HVF_E_UNSUPPORTED.
  * Makes no HIP call. */
 hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, hvf_volume** out);
 

@@ -293,7 +293,7 @@ hvf_status build_paper_words(const Spec& s, const Layout& L, const uint64_t* cod
   } catch (const TooBig&) {
     out = Built{};
     err = "the format exceeds 2^32 words (16 GiB, the paper's limit)";
-    return HVF_E_UNSUPPORTED;
+    return HVF_E_OVERFLOW;
   } catch (const std::bad_alloc&) {
     out = Built{};
     err = "host allocation failed";
