@@ -137,7 +137,8 @@ typedef struct hvf_schedule {
  *   an SVDAG node its masks followed by one pointer per child; a DF cell is (terminating
  *   integer, capped distance). Results are unchanged; the buffer is larger for Raw- and
  *   SVO-final formats and smaller for deep SVDAGs. Not with --restart-sv (HVF_E_UNSUPPORTED),
- *   nor with short stacks or staged LDS depths, batches, the server or hvf_build_device.
+ *   short stacks or staged LDS depths (HVF_E_INPUT) or hvf_build_device; batches and the
+ *   server take such volumes, alone or mixed with the library's layout.
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
  *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
  * out: receives a new handle owned by the caller (release with hvf_free).

@@ -10,9 +10,9 @@
 
 namespace hvf {
 hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo, uint32_t nitems, uint32_t total,
-                              int max_depth, bool df, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
+                              int max_depth, int kinds, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
                               hipStream_t s);
-hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu, unsigned* grid);
+hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_cu, unsigned* grid);
 }  // namespace hvf
 
 struct hvf_batch {
@@ -23,7 +23,7 @@ struct hvf_batch {
   uint32_t* d_counter = nullptr;
   uint32_t total = 0;
   int max_depth = 1;
-  bool df = false;  // some batch has a distance-field level: launch the all-kinds kernel
+  int kinds = 0;  // the widest kind set of its volumes (hvf::batch_kinds): picks the kernel
   hvf_batch_opts opts{16, 8, 0, 1};
   unsigned grid = 0;
   hipStream_t cap = nullptr;  // private stream used for graph capture
@@ -57,7 +57,7 @@ void drop_graph(hvf_batch* b) {
 }
 
 hvf_status launch(hvf_batch* b, hipStream_t s) {
-  return hvf::launch_trace_batch(b->d_items, b->d_dinfo, (uint32_t)b->items.size(), b->total, b->max_depth, b->df,
+  return hvf::launch_trace_batch(b->d_items, b->d_dinfo, (uint32_t)b->items.size(), b->total, b->max_depth, b->kinds,
                                  b->d_counter, (uint32_t)b->opts.refill, (uint32_t)b->opts.inner, b->grid, s);
 }
 
@@ -84,7 +84,7 @@ hvf_status capture(hvf_batch* b) {
 }
 
 hvf_status configure(hvf_batch* b) {
-  hvf_status st = hvf::batch_grid((uint32_t)b->items.size(), b->max_depth, b->df, b->opts.blocks_per_cu, &b->grid);
+  hvf_status st = hvf::batch_grid((uint32_t)b->items.size(), b->max_depth, b->kinds, b->opts.blocks_per_cu, &b->grid);
   if (st != HVF_OK) return st;
   if (b->opts.use_graph) return capture(b);
   drop_graph(b);
@@ -111,11 +111,6 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
       delete b;
       return fail(HVF_E_INPUT, "null volume or buffer in batch " + std::to_string(i));
     }
-    if (vols[i]->spec.paper) {
-      delete b;
-      return fail(HVF_E_UNSUPPORTED, "batched launches take volumes in the library's own layout (batch " +
-                                         std::to_string(i) + " has --paper-layout)");
-    }
     st = hvf_upload(vols[i], nullptr);
     if (st != HVF_OK) {
       delete b;
@@ -133,7 +128,7 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     it.ndepth = F.ndepth;
     it.stacked = F.stacked;
     b->max_depth = std::max(b->max_depth, F.ndepth);
-    b->df = b->df || hvf::has_df(vols[i]->layout);
+    b->kinds = std::max(b->kinds, hvf::batch_kinds(vols[i]->spec, vols[i]->layout));
     b->items.push_back(it);
     b->dinfo.insert(b->dinfo.end(), F.dinfo, F.dinfo + HVF_MAX_DEPTH);
     total += n[i];

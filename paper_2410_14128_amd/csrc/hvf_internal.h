@@ -185,6 +185,8 @@ constexpr uint32_t FAM_PAPER = fam_nk(NK_RAW_PTR) | fam_nk(NK_PRAW_VOX) | fam_nk
 constexpr uint32_t FAMILIES[] = {FAM_BRICK,    FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE,
                                  FAM_DF_BRICK, FAM_DF_OCTREE, FAM_OCT_BRICK, FAM_NODF,      FAM_PAPER,  FAM_ALL};
 constexpr int NUM_FAMILIES = 12;
+// Batched launches mixing both layouts.
+constexpr uint32_t FAM_ANY = FAM_ALL | FAM_PAPER;
 // Families whose kernels take every depth to be cubic (w equal on the three axes: the root
 // is an octree level, and levels below the first are cubic), and the one whose depths all
 // have w = 1 (octree levels only). family_of assigns them only to layouts that are.
@@ -197,6 +199,9 @@ constexpr bool fam_w1(uint32_t f) { return f == FAM_OCTREE; }
 int family_of(const Layout& L);
 // Whether the layout has a distance-field depth.
 bool has_df(const Layout& L);
+// Kind set of a volume for the batched kernel: 2 in the paper's layout, 1 with a
+// distance-field depth, else 0.
+inline int batch_kinds(const Spec& s, const Layout& L) { return s.paper ? 2 : (has_df(L) ? 1 : 0); }
 
 // One batch of the batched launch: a volume and its ray / hit arrays. Rays of all
 // batches form one index space; batch b owns indices [first, first + n).

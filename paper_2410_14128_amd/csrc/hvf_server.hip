@@ -30,9 +30,9 @@
 
 namespace hvf {
 hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo, uint32_t nitems, uint32_t total,
-                              int max_depth, bool df, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
+                              int max_depth, int kinds, uint32_t* d_counter, uint32_t refill, uint32_t inner, unsigned grid,
                               hipStream_t s);
-hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu, unsigned* grid);
+hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_cu, unsigned* grid);
 }  // namespace hvf
 
 namespace {
@@ -160,11 +160,11 @@ hvf_status launch_step(hvf_server* S, Step& st) {
   const size_t m = st.reqs.size();
   uint64_t total = 0;
   int max_depth = 1;
-  bool df = false;
+  int kinds = 0;
   for (size_t i = 0; i < m; ++i) {
     Request& r = *st.reqs[i];
     hvf_volume* v = S->vols[r.vol];
-    df = df || hvf::has_df(v->layout);
+    kinds = std::max(kinds, hvf::batch_kinds(v->spec, v->layout));
     const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
     uint8_t* hr = S->h_arena + r.off;
     if (r.n && !r.src_pinned) std::memcpy(hr, r.src, r.n * sizeof(hvf_ray));
@@ -196,10 +196,10 @@ hvf_status launch_step(hvf_server* S, Step& st) {
     e = hipMemcpyAsync(st.d_dinfo, st.h_dinfo, m * HVF_MAX_DEPTH * sizeof(uint32_t), hipMemcpyHostToDevice, st.stream);
   if (e != hipSuccess) return fail(HVF_E_DEVICE, std::string("server upload: ") + hipGetErrorString(e));
   unsigned grid = 0;
-  hvf_status s = hvf::batch_grid((uint32_t)m, max_depth, df, S->opts.blocks_per_cu, &grid);
+  hvf_status s = hvf::batch_grid((uint32_t)m, max_depth, kinds, S->opts.blocks_per_cu, &grid);
   if (s != HVF_OK) return s;
   if (total)
-    s = hvf::launch_trace_batch(st.d_items, st.d_dinfo, (uint32_t)m, (uint32_t)total, max_depth, df, st.d_counter,
+    s = hvf::launch_trace_batch(st.d_items, st.d_dinfo, (uint32_t)m, (uint32_t)total, max_depth, kinds, st.d_counter,
                                 (uint32_t)S->opts.refill, (uint32_t)S->opts.inner, grid, st.stream);
   if (s != HVF_OK) return s;
   for (size_t i = 0; i < m && e == hipSuccess; ++i) {
@@ -348,7 +348,6 @@ hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_ste
 
 hvf_status hvf_server_add_volume(hvf_server* S, hvf_volume* v, int* vol_id) {
   if (!S || !v || !vol_id) return fail(HVF_E_INPUT, "null argument");
-  if (v->spec.paper) return fail(HVF_E_UNSUPPORTED, "the server takes volumes in the library's own layout, not --paper-layout");
   hvf_status st = hvf_upload(v, nullptr);
   if (st != HVF_OK) return st;
   std::lock_guard<std::mutex> lk(S->mu);

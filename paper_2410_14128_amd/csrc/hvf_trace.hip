@@ -1206,7 +1206,9 @@ size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
   return words * 4 + (size_t)max_depth * BLOCK * sizeof(uint2);
 }
 
-hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu, unsigned* grid) {
+// kinds: 0 = the library's layout without distance-field levels, 1 = with them, 2 = some
+// volume in the paper's word layout (the batched kernel is compiled for that kind set).
+hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_cu, unsigned* grid) {
   if (g_cu_count < 0) {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -1217,11 +1219,11 @@ hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu
     g_cu_count = prop.multiProcessorCount;
   }
   int per_cu = 0;
+  const size_t lds = batch_lds_bytes(nitems, max_depth);
   const hipError_t oe =
-      df ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ALL>, BLOCK,
-                                                        batch_lds_bytes(nitems, max_depth))
-         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_NODF>, BLOCK,
-                                                        batch_lds_bytes(nitems, max_depth));
+      kinds == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ANY>, BLOCK, lds)
+      : kinds == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ALL>, BLOCK, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_NODF>, BLOCK, lds);
   if (oe != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -1231,12 +1233,15 @@ hvf_status batch_grid(uint32_t nitems, int max_depth, bool df, int blocks_per_cu
 }
 
 hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo, uint32_t nitems, uint32_t total,
-                              int max_depth, bool df, uint32_t* d_counter, uint32_t refill, uint32_t inner,
+                              int max_depth, int kinds, uint32_t* d_counter, uint32_t refill, uint32_t inner,
                               unsigned grid, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, d_counter, 0u, (size_t)1);
   hvf_status st = launch_check("fill");
   if (st != HVF_OK) return st;
-  if (df)
+  if (kinds == 2)
+    hipLaunchKernelGGL(trace_batch_kernel<FAM_ANY>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
+                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
+  else if (kinds == 1)
     hipLaunchKernelGGL(trace_batch_kernel<FAM_ALL>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
                        d_items, d_dinfo, nitems, total, d_counter, refill, inner);
   else

@@ -97,13 +97,33 @@ def test_paper_layout_counting_and_refusals(H):
     sc = v.autotune(d)  # skips the schedules this layout refuses
     assert sc.stack_depth == 0 and sc.lds_depths == 0
     with pytest.raises(H.HvfError) as e:
-        H.Batch([v], [d])
-    assert e.value.name == "HVF_E_UNSUPPORTED"
-    srv = H.Server(1 << 26)
-    with pytest.raises(H.HvfError) as e:
-        srv.add_volume(v)
-    assert e.value.name == "HVF_E_UNSUPPORTED"
-    srv.close()
-    with pytest.raises(H.HvfError) as e:
         H.Volume.from_device("G(7) --paper-layout", torch.from_numpy(codes.view(np.int64)).cuda())
     assert e.value.name == "HVF_E_UNSUPPORTED"
+
+
+def test_paper_layout_batched_and_served(H):
+    """Volumes in the paper's layout, alone and mixed with the library's own layout (DF
+    levels included), in one batched launch and through the server: each batch's hits equal
+    its volume's own trace."""
+    import torch
+    codes = W.scene_shell(3, 7, 8, 4, 1.4)
+    specs = ["G(4) R(3,3,3) --whole-level-dedup --paper-layout", "R(2,2,2) S(2) D(3,3,3,5) --paper-layout",
+             "S(3) G(4) --paper-layout", "G(4) R(3,3,3) --whole-level-dedup", "D(2,2,2,4) S(5)"]
+    vols = [H.Volume(sp, codes) for sp in specs]
+    rays = [torch.from_numpy(W.random_rays(10 + i, (128,) * 3, 3000 + 997 * i)).cuda() for i in range(len(vols))]
+    want = [v.trace(r) for v, r in zip(vols, rays)]
+    torch.cuda.synchronize()
+    for group in (vols[:3], vols):
+        b = H.Batch(group, rays[:len(group)])
+        hits = b.run()
+        torch.cuda.synchronize()
+        for i, h in enumerate(hits):
+            assert torch.equal(h, want[i]), (len(group), specs[i])
+        b.close()
+    srv = H.Server(1 << 26, max_slots=8, max_steps=2)
+    ids = [srv.add_volume(v) for v in vols]
+    rid = [srv.submit(ids[i], rays[i].cpu().numpy()) for i in range(len(vols))]
+    for i, r in enumerate(rid):
+        got = srv.wait(r)[0]
+        assert np.array_equal(got, want[i].cpu().numpy()), specs[i]
+    srv.close()
