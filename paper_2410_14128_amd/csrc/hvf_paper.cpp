@@ -193,8 +193,8 @@ class PaperBuilder {
   // three one-axis passes of d = min(d, neighbour + 1), each forwards then backwards.
   static std::vector<uint32_t> with_distance(const std::vector<uint32_t>& cells, int64_t nx, int64_t ny, int64_t nz,
                                              uint32_t cap) {
-    const int64_t far = nx + ny + nz;
-    std::vector<int64_t> d(cells.size());
+    const int32_t far = (int32_t)(nx + ny + nz);  // above any L1 distance in the grid (sides <= 2^15)
+    std::vector<int32_t> d(cells.size());
     for (size_t i = 0; i < cells.size(); ++i) d[i] = cells[i] ? 0 : far;
     const int64_t stride[3] = {1, nx, nx * ny}, len[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a) {
@@ -203,11 +203,11 @@ class PaperBuilder {
         for (int64_t v = 0; v < len[b2]; ++v) {
           const int64_t base = u * stride[b1] + v * stride[b2];
           for (int64_t i = 1; i < len[a]; ++i) {
-            int64_t& c = d[base + i * stride[a]];
+            int32_t& c = d[base + i * stride[a]];
             c = std::min(c, d[base + (i - 1) * stride[a]] + 1);
           }
           for (int64_t i = len[a] - 2; i >= 0; --i) {
-            int64_t& c = d[base + i * stride[a]];
+            int32_t& c = d[base + i * stride[a]];
             c = std::min(c, d[base + (i + 1) * stride[a]] + 1);
           }
         }
@@ -215,7 +215,7 @@ class PaperBuilder {
     std::vector<uint32_t> out(2 * cells.size());
     for (size_t i = 0; i < cells.size(); ++i) {
       out[2 * i] = cells[i];
-      out[2 * i + 1] = (uint32_t)std::min<int64_t>(d[i], cap);
+      out[2 * i + 1] = std::min<uint32_t>((uint32_t)d[i], cap);
     }
     return out;
   }
