@@ -843,6 +843,181 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
     persistent_loop<FAM>(fm, stk, rays, hits, n, counter, refill, inner);
 }
 
+// ---------------------------------------------------------------- work stealing in a wave
+// One lane per ray, and the lanes whose walks have ended take over parts of the walks still
+// running in their wave. Every `period` steps (a power of two) a wave looks at its running
+// walks. A walk whose rest [t, t1) is longer than the time `tv` the ray needs to cross
+// `minlen` voxels along its fastest axis is cut into K equal parts in t (K a power of two,
+// at most `kmax`, as many as the idle lanes allow): the walk keeps part 0 and K - 1 idle
+// lanes walk parts 1..K-1 from the root. This is exact for the same reasons as the split
+// schedule (a walk over [a, b) tests every cell entered before b, and the mid-plane descent
+// from the root at time a lands in the cell holding the ray at a; see split_loop). A ray's
+// result is its hit of least t over all its parts: a part reports a cell it starts inside at
+// its own start time, which the part before it reports at the cell's true entry time, and a
+// cell's entry time identifies it. So each ray keeps its least hit key in LDS (an atomic min
+// over the parts' reports), and at the end its own lane writes it; the voxel of a hit
+// another lane found is recovered by the mid-plane descent from the root at the hit time,
+// which lands in the cell entered at that time. A part stops as soon as its ray holds a hit
+// no later than its current t (it cannot report an earlier one). Walks that hold the first
+// part of their own lane's ray are cut first. Lanes past the last ray of the grid help too.
+
+// Orderable key of a time: key(a) < key(b) iff a < b (non-NaN a, b); 0 and all ones are the
+// keys of two NaNs, used as markers: a tripped step guard and "no hit yet".
+constexpr uint32_t KEY_GUARD = 0u;
+constexpr uint32_t KEY_NOHIT = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t time_key(float t) {
+  const uint32_t b = __float_as_uint(t);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_time(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// The voxel holding the ray at time t: the mid-plane descent from the root at t.
+__device__ __forceinline__ int4 voxel_at(const Ray& R, const int32_t ext[3], float t) {
+  int p[3] = {0, 0, 0};
+  for (int b = max(ext[0], max(ext[1], ext[2])) - 1; b >= 0; --b) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (b >= ext[a]) continue;
+      const int mid = p[a] + (1 << b);
+      const bool up = (R.T(a, mid) <= t) != R.is_neg(a);
+      p[a] = up ? mid : p[a];
+    }
+  }
+  return make_int4(p[0], p[1], p[2], __float_as_int(t));
+}
+
+// Time for the ray to cross `minlen` voxels along its fastest axis (parallel axes carry
+// 1/d = +inf and drop out of the min).
+__device__ __forceinline__ float cross_time(const Ray& R, float minlen) {
+  return minlen * fmin_fx(fmin_fx(fabsf(R.inv[0]), fabsf(R.inv[1])), fabsf(R.inv[2]));
+}
+
+// best, tbl: this wave's 64-word LDS arrays (least hit key per ray of the wave; the donor
+// lane of each helper slot).
+template <uint32_t FAM>
+__device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const float4* __restrict__ rays,
+                                           int4* __restrict__ hits, uint32_t i, uint32_t n, uint32_t period,
+                                           float minlen, uint32_t kmax, uint32_t* best, uint32_t* tbl) {
+  const uint32_t lane = __lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  Walk w{};
+  Plain mem;
+  int4 out = miss_hit();
+  int4 own = miss_hit();  // the earliest hit of this lane's own ray found by this lane
+  uint32_t home = lane;   // the lane (of this wave) whose ray the current part belongs to
+  float tv = 0.0f;
+  best[lane] = KEY_NOHIT;
+  bool run = false;
+  if (i < n) {
+    const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
+    run = setup(r0, r1, fm.ext, w.R) && w.template start<FAM>(fm, mem) == RUN;
+    tv = cross_time(w.R, minlen);
+  }
+  for (uint32_t it = 1;; ++it) {
+    if (run && w.template step<FAM>(fm, stk, out, mem) == DONE) {
+      run = false;
+      if (out.x != -1) {  // a hit, or the step guard (-2)
+        const uint32_t k = out.x == -2 ? KEY_GUARD : time_key(__int_as_float(out.w));
+        atomicMin(&best[home], k);
+        if (home == lane && out.x >= 0 && (own.x < 0 || k < time_key(__int_as_float(own.w)))) own = out;
+      }
+      out = miss_hit();
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if ((it & (period - 1u)) != 0u) {
+      if (__ballot(run) == 0ull) break;
+      continue;
+    }
+    if (run && best[home] <= time_key(w.t)) run = false;  // an earlier part already hit
+    const uint64_t rm = __ballot(run);
+    if (rm == 0ull) break;
+    const uint32_t nidle = 64u - (uint32_t)__popcll(rm);
+    const bool want = run && (w.R.t1 - w.t) > tv;
+    const uint64_t wh = __ballot(want && home == lane), wo = __ballot(want && home != lane);
+    const uint32_t nh = (uint32_t)__popcll(wh), nw = nh + (uint32_t)__popcll(wo);
+    if (nw == 0u || nidle == 0u) continue;
+    // m helpers for each of the first ndon donors: m + 1 a power of two, at most kmax.
+    const uint32_t per = nidle / nw;
+    const uint32_t m = per == 0u ? 1u : min((1u << (31 - __clz(per + 1u))), kmax) - 1u;
+    const uint32_t ndon = per == 0u ? nidle : nw;
+    const uint32_t drank = home == lane ? (uint32_t)__popcll(wh & below) : nh + (uint32_t)__popcll(wo & below);
+    const uint32_t irank = (uint32_t)__popcll(~rm & below);
+    const bool donor = want && drank < ndon, recv = !run && irank < ndon * m;
+    if (donor)
+      for (uint32_t q = 0; q < m; ++q) tbl[drank * m + q] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int src = recv ? (int)tbl[irank] : (int)lane;
+    // Every lane of the wave is active here, so each shuffle reads its source lane.
+    float q[8];
+    q[0] = __shfl(w.R.o[0], src);
+    q[1] = __shfl(w.R.o[1], src);
+    q[2] = __shfl(w.R.o[2], src);
+    q[3] = __shfl(w.R.inv[0], src);
+    q[4] = __shfl(w.R.inv[1], src);
+    q[5] = __shfl(w.R.inv[2], src);
+    q[6] = __shfl(w.t, src);
+    q[7] = __shfl(w.R.t1, src);
+    const uint32_t np = __shfl(w.R.neg | (w.R.par << 3), src);
+    const uint32_t hh = __shfl(home, src);
+    const uint32_t K = m + 1u;
+    if (donor) w.R.t1 = split_time(w.t, w.R.t1, 1u, K);
+    if (recv) {
+      const uint32_t part = irank % m + 1u;
+      w.R.o[0] = q[0];
+      w.R.o[1] = q[1];
+      w.R.o[2] = q[2];
+      w.R.inv[0] = q[3];
+      w.R.inv[1] = q[4];
+      w.R.inv[2] = q[5];
+      w.R.neg = np & 7u;
+      w.R.par = np >> 3;
+      w.R.t0 = split_time(q[6], q[7], part, K);
+      w.R.t1 = split_time(q[6], q[7], part + 1u, K);
+      home = hh;
+      tv = cross_time(w.R, minlen);
+      run = w.R.t0 < w.R.t1 && w.template start<FAM>(fm, mem) == RUN;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (i >= n) return;
+  const uint32_t k = best[lane];
+  int4 res = miss_hit();
+  if (k == KEY_GUARD) {
+    res = make_int4(-2, -2, -2, 0);
+  } else if (k != KEY_NOHIT) {
+    if (own.x >= 0 && time_key(__int_as_float(own.w)) == k) {
+      res = own;
+    } else {  // found by another lane: the voxel entered at the hit time
+      const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
+      Ray R;
+      (void)setup(r0, r1, fm.ext, R);
+      res = voxel_at(R, fm.ext, key_time(k));
+    }
+  }
+  put_hit(hits, i, res);
+}
+
+template <uint32_t FAM>
+__global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
+                                                            int4* __restrict__ hits, uint32_t n, uint32_t period,
+                                                            float minlen, uint32_t kmax) {
+  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
+  extern __shared__ uint2 stk_all[];
+  const uint32_t* pre = stage_prefix(F, stk_all);
+  load_dtab(F, dtab);
+  const Fmt fm = fmt_of(F, dtab, pre);
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x, w0 = threadIdx.x & ~63u;
+  if (F.lds_words)
+    steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, kmax, best_all + w0,
+                              tbl_all + w0);
+  else
+    steal_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, kmax, best_all + w0, tbl_all + w0);
+}
+
 // One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F, const float4* __restrict__ rays,
@@ -1070,6 +1245,24 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_TRACE)
 #undef HVF_LAUNCH_TRACE
   return launch_check("trace");
+}
+
+hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                              uint32_t period, float minlen, uint32_t kmax, hipStream_t s) {
+  if (n == 0) return HVF_OK;
+  if (n >= (1ull << 32) - BLOCK) {
+    hvf_set_error("at most 2^32 - 257 rays per stealing call");
+    return HVF_E_INPUT;
+  }
+  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  const float4* r = reinterpret_cast<const float4*>(d_rays);
+  int4* h = reinterpret_cast<int4*>(d_hits);
+#define HVF_LAUNCH_STEAL(FAMV)                                                                                  \
+  hipLaunchKernelGGL(trace_steal_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
+                     period, minlen, kmax)
+  HVF_FAMILY_SWITCH(family, HVF_LAUNCH_STEAL)
+#undef HVF_LAUNCH_STEAL
+  return launch_check("stealing trace");
 }
 
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);

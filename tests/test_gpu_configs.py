@@ -136,6 +136,33 @@ def test_surface2048_split_schedule(H, surf2048, sd):
         assert compare(g.cpu().numpy(), ref, f"split {sd} {what}") == 0
 
 
+@pytest.mark.parametrize("sd", [dict(steal=1, steal_len=8, steal_parts=2), dict(steal=4, steal_len=16, steal_parts=64),
+                                dict(steal=8, steal_len=64, steal_parts=4),
+                                dict(steal=4, steal_len=8, steal_parts=2, lds_depths=3)], ids=lambda d: str(d))
+def test_surface2048_steal_schedule(H, surf2048, sd):
+    """Whole 1080p frames, primary and bounce rays, traced with walks split among the idle
+    lanes of each wave equal the plain schedule bit for bit, and sampled rays the oracle."""
+    import torch
+    cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
+    vol = H.Volume("G(7) R(4,4,4) --whole-level-dedup", codes)
+    sc = H.schedule(**sd)
+    plain = _trace_full(vol, prim)
+    got = vol.trace(torch.from_numpy(prim).cuda(), sched=sc)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got, plain)
+    assert compare(got[idx], ref_p, f"steal {sd} primary") == 0
+    b_full, _ = W.bounce_rays(cfg["bounce_seed"], prim, plain)
+    bp = _trace_full(vol, b_full)
+    bs = vol.trace(torch.from_numpy(b_full).cuda(), sched=sc)
+    torch.cuda.synchronize()
+    assert np.array_equal(bs.cpu().numpy(), bp)
+    for rays, ref, what in ((bounce, ref_b, "bounce"), (rnd, ref_r, "random")):
+        g = vol.trace(torch.from_numpy(rays).cuda(), sched=sc)
+        torch.cuda.synchronize()
+        assert compare(g.cpu().numpy(), ref, f"steal {sd} {what}") == 0
+
+
 def test_counting_variant_matches_plain(H, surf512):
     import torch
     cfg, codes, views = surf512

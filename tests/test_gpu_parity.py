@@ -101,7 +101,11 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(split=8, split_budget=4, lds_depths=2), dict(split=4, split_budget=2, stack_depth=2),
              dict(split=8, split_budget=2, split_rounds=2), dict(split=64, split_budget=1, split_rounds=6),
              dict(split=2, split_budget=3, split_rounds=1), dict(split=4, split_budget=3, split_rounds=1, lds_depths=2),
-             dict(split=16, split_budget=4, split_rounds=3, stack_depth=2)]
+             dict(split=16, split_budget=4, split_rounds=3, stack_depth=2),
+             dict(steal=1, steal_len=1, steal_parts=2), dict(steal=2, steal_len=3, steal_parts=64),
+             dict(steal=8, steal_len=16, steal_parts=4), dict(steal=64, steal_len=1, steal_parts=8),
+             dict(steal=4, steal_len=1, steal_parts=16, lds_depths=2), dict(steal=1, steal_len=2, steal_parts=2, stack_depth=2),
+             dict(steal=16, steal_len=1 << 20, steal_parts=2)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
