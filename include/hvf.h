@@ -104,14 +104,14 @@ typedef struct hvf_info {
  *   their t, packed densely, for split_budget, 2 split_budget, ... 2^(R-1) split_budget
  *   steps each; only the rays still walking after the last round are cut into segments.
  * steal = P > 0 (a power of two, 1..64; needs persistent = 0, sort = 0 and split = 0): one
- *   lane per ray, and every P steps each wave hands the lanes whose walks have ended parts
- *   of the walks still running in the wave. A walk whose rest [t, t1) is longer than the
- *   time the ray takes to cross steal_len voxels (1..2^20) along its fastest axis is cut
- *   into up to steal_parts (a power of two, 2..64) equal parts in t, as many as the idle
- *   lanes allow: it keeps the first and idle lanes walk the others from the root. A ray's
- *   result is its parts' hit of least t, kept per ray in LDS; parts behind a hit stop.
- *   Lanes past the last ray of a launch help too. This keeps lanes busy while a wave's
- *   longest walks finish. */
+ *   lane per ray, and every P steps each wave hands the lanes whose walks have ended the
+ *   rest of walks still running in the wave. A walk whose rest [t, t1) is longer than the
+ *   time the ray takes to cross steal_len voxels (1..2^20) along its fastest axis forks at
+ *   the exit time e of one of its ancestor nodes: it keeps [t, e), and an idle lane
+ *   continues the walk from e exactly as the walk would have, with a copy of its node
+ *   stack, so no step is walked twice. A ray's result is its parts' hit of least t, kept
+ *   per ray in LDS; parts behind a hit stop. Lanes past the last ray of a launch help too.
+ *   This keeps lanes busy while a wave's longest walks finish. */
 typedef struct hvf_schedule {
   int32_t persistent;
   int32_t refill;
@@ -128,8 +128,7 @@ typedef struct hvf_schedule {
   int32_t split_budget; /* steps of the first launch when split > 0 (1..2^20) */
   int32_t split_rounds; /* restart rounds of the split schedule (0..6; needs split > 0) */
   int32_t steal;        /* 0, or P: see above */
-  int32_t steal_len;    /* voxels; shorter rests are not cut (steal > 0) */
-  int32_t steal_parts;  /* most parts one cut makes (steal > 0) */
+  int32_t steal_len;    /* voxels; shorter rests are not forked (steal > 0) */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).
@@ -206,8 +205,8 @@ hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
 
 /* Autotune: time candidate schedules (one lane per ray; short stacks of 2 and 4 depths;
  * persistent at full, 2 or 4 blocks per CU with refill thresholds 8/32 and 4 or 16 steps
- * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; four
- * stealing schedules), then the best with the deepest LDS prefixes that fit, on the
+ * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; stealing
+ * every 2, 4 or 8 steps for rests over 8 voxels, and every 4 steps over 32), then the best with the deepest LDS prefixes that fit, on the
  * caller's device ray sample; pick the fastest, store it as the volume's schedule and copy
  * it to *out (may be NULL). d_hits_scratch: n device hits, overwritten. Synchronises
  * hip_stream. Results never depend on the schedule chosen. */

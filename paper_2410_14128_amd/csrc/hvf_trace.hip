@@ -479,6 +479,36 @@ struct Walk {
     return RUN;
   }
 
+  // Exit time of the ancestor node at depth k (1 <= k <= d) of the current cell: the least
+  // far-plane time of that node's cell, of side 2^cs(k - 1). Also the walk's position just
+  // after leaving it (q: that cell advanced along every axis crossing at the exit time, as
+  // an advance does) and the depth nd < k of the deepest node holding the new cell (from
+  // the pop table). Only meaningful when the exit time is below t1 (the new cell is then
+  // inside the root).
+  __device__ __forceinline__ float node_exit(const Fmt& F, int k, int q[3], int& nd) const {
+    const int cs = di_cs(F.dtab[k - 1]);
+    const int side = 1 << cs, mask = ~(side - 1);
+    float tf[3];
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = p[a] & mask;
+      tf[a] = R.T(a, R.is_neg(a) ? c[a] : c[a] + side);
+    }
+    const float m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
+    uint32_t dd = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int np = c[a] + (R.is_neg(a) ? -side : side);
+      const bool mv = (tf[a] == m);
+      dd |= mv ? (uint32_t)(np ^ c[a]) : 0u;
+      q[a] = mv ? np : c[a];
+    }
+    const int hb = 31 - __clz(dd);
+    nd = min(k - 1, (int)((F.pop_lut >> (4 * hb)) & 15u));
+    return m;
+  }
+
   // Leave the current node for its ancestor at depth nd < d that contains the new cell:
   // restore the deepest stacked ancestor r <= nd, then descend again along p (every
   // ancestor of the current cell exists, so each child on the way is occupied).
@@ -844,22 +874,22 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
 }
 
 // ---------------------------------------------------------------- work stealing in a wave
-// One lane per ray, and the lanes whose walks have ended take over parts of the walks still
+// One lane per ray, and the lanes whose walks have ended take over the rest of walks still
 // running in their wave. Every `period` steps (a power of two) a wave looks at its running
-// walks. A walk whose rest [t, t1) is longer than the time `tv` the ray needs to cross
-// `minlen` voxels along its fastest axis is cut into K equal parts in t (K a power of two,
-// at most `kmax`, as many as the idle lanes allow): the walk keeps part 0 and K - 1 idle
-// lanes walk parts 1..K-1 from the root. This is exact for the same reasons as the split
-// schedule (a walk over [a, b) tests every cell entered before b, and the mid-plane descent
-// from the root at time a lands in the cell holding the ray at a; see split_loop). A ray's
-// result is its hit of least t over all its parts: a part reports a cell it starts inside at
-// its own start time, which the part before it reports at the cell's true entry time, and a
-// cell's entry time identifies it. So each ray keeps its least hit key in LDS (an atomic min
-// over the parts' reports), and at the end its own lane writes it; the voxel of a hit
-// another lane found is recovered by the mid-plane descent from the root at the hit time,
-// which lands in the cell entered at that time. A part stops as soon as its ray holds a hit
-// no later than its current t (it cannot report an earlier one). Walks that hold the first
-// part of their own lane's ray are cut first. Lanes past the last ray of the grid help too.
+// walks. A walk (its part [t, t1) of a ray) whose rest is longer than the time `tv` the ray
+// needs to cross `minlen` voxels along its fastest axis forks at the exit time e of one of
+// its ancestor nodes (the shallowest one it has not tried, that ends before t1): the walk
+// keeps [t, e) and an idle lane continues the walk exactly as the walk itself would after
+// leaving that node: at time e, in the cell beyond it, under the deepest node holding that
+// cell, with the donor's node stack for the depths above (copied from the donor's LDS
+// column). No step is walked twice. A ray's result is the hit of least t over its parts (the
+// parts visit disjoint runs of the walk's cells, each reporting true entry times), so each
+// ray keeps its least hit key in LDS (an atomic min over the parts' reports) and at the end
+// its own lane writes it; the voxel of a hit another lane found is recovered by the
+// mid-plane descent from the root at the hit time, which lands in the cell entered at that
+// time. A part stops as soon as its ray holds a hit no later than its current t (it cannot
+// report an earlier one). Walks of their own lane's ray are forked first. Lanes past the last
+// ray of the grid help too.
 
 // Orderable key of a time: key(a) < key(b) iff a < b (non-NaN a, b); 0 and all ones are the
 // keys of two NaNs, used as markers: a tripped step guard and "no hit yet".
@@ -895,11 +925,11 @@ __device__ __forceinline__ float cross_time(const Ray& R, float minlen) {
 }
 
 // best, tbl: this wave's 64-word LDS arrays (least hit key per ray of the wave; the donor
-// lane of each helper slot).
+// lane of each helper).
 template <uint32_t FAM>
 __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const float4* __restrict__ rays,
                                            int4* __restrict__ hits, uint32_t i, uint32_t n, uint32_t period,
-                                           float minlen, uint32_t kmax, uint32_t* best, uint32_t* tbl) {
+                                           float minlen, uint32_t* best, uint32_t* tbl) {
   const uint32_t lane = __lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   Walk w{};
@@ -907,6 +937,7 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
   int4 out = miss_hit();
   int4 own = miss_hit();  // the earliest hit of this lane's own ray found by this lane
   uint32_t home = lane;   // the lane (of this wave) whose ray the current part belongs to
+  int kf = 1;             // shallowest ancestor depth this part may still fork at
   float tv = 0.0f;
   best[lane] = KEY_NOHIT;
   bool run = false;
@@ -934,51 +965,76 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
     const uint64_t rm = __ballot(run);
     if (rm == 0ull) break;
     const uint32_t nidle = 64u - (uint32_t)__popcll(rm);
-    const bool want = run && (w.R.t1 - w.t) > tv;
+    if (nidle == 0u) continue;
+    bool want = false;
+    float e = 0.0f;
+    int q[3] = {0, 0, 0}, nd = 0;
+    const int k = min(kf, w.d);  // an ancestor: the nodes above it are on the donor's stack
+    if (run && k >= 1 && (w.R.t1 - w.t) > tv) {
+      e = w.node_exit(fm, k, q, nd);
+      want = e < w.R.t1;
+      if (!want) kf = k + 1;  // that node reaches t1: try the next depth next time
+    }
     const uint64_t wh = __ballot(want && home == lane), wo = __ballot(want && home != lane);
     const uint32_t nh = (uint32_t)__popcll(wh), nw = nh + (uint32_t)__popcll(wo);
-    if (nw == 0u || nidle == 0u) continue;
-    // m helpers for each of the first ndon donors: m + 1 a power of two, at most kmax.
-    const uint32_t per = nidle / nw;
-    const uint32_t m = per == 0u ? 1u : min((1u << (31 - __clz(per + 1u))), kmax) - 1u;
-    const uint32_t ndon = per == 0u ? nidle : nw;
+    if (nw == 0u) continue;
+    const uint32_t pairs = min(nw, nidle);
     const uint32_t drank = home == lane ? (uint32_t)__popcll(wh & below) : nh + (uint32_t)__popcll(wo & below);
     const uint32_t irank = (uint32_t)__popcll(~rm & below);
-    const bool donor = want && drank < ndon, recv = !run && irank < ndon * m;
-    if (donor)
-      for (uint32_t q = 0; q < m; ++q) tbl[drank * m + q] = lane;
+    const bool donor = want && drank < pairs, recv = !run && irank < pairs;
+    if (donor) tbl[drank] = lane;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int src = recv ? (int)tbl[irank] : (int)lane;
     // Every lane of the wave is active here, so each shuffle reads its source lane.
-    float q[8];
-    q[0] = __shfl(w.R.o[0], src);
-    q[1] = __shfl(w.R.o[1], src);
-    q[2] = __shfl(w.R.o[2], src);
-    q[3] = __shfl(w.R.inv[0], src);
-    q[4] = __shfl(w.R.inv[1], src);
-    q[5] = __shfl(w.R.inv[2], src);
-    q[6] = __shfl(w.t, src);
-    q[7] = __shfl(w.R.t1, src);
-    const uint32_t np = __shfl(w.R.neg | (w.R.par << 3), src);
-    const uint32_t hh = __shfl(home, src);
-    const uint32_t K = m + 1u;
-    if (donor) w.R.t1 = split_time(w.t, w.R.t1, 1u, K);
+    float f[8];
+    f[0] = __shfl(w.R.o[0], src);
+    f[1] = __shfl(w.R.o[1], src);
+    f[2] = __shfl(w.R.o[2], src);
+    f[3] = __shfl(w.R.inv[0], src);
+    f[4] = __shfl(w.R.inv[1], src);
+    f[5] = __shfl(w.R.inv[2], src);
+    f[6] = __shfl(w.R.t1, src);
+    f[7] = __shfl(e, src);
+    int g[6];
+    g[0] = __shfl(q[0], src);
+    g[1] = __shfl(q[1], src);
+    g[2] = __shfl(q[2], src);
+    g[3] = __shfl(nd, src);
+    g[4] = __shfl(k, src);
+    g[5] = __shfl((int)(w.R.neg | (w.R.par << 3) | (home << 6)), src);
+    if (donor) {
+      w.R.t1 = e;
+      kf = k + 1;
+    }
     if (recv) {
-      const uint32_t part = irank % m + 1u;
-      w.R.o[0] = q[0];
-      w.R.o[1] = q[1];
-      w.R.o[2] = q[2];
-      w.R.inv[0] = q[3];
-      w.R.inv[1] = q[4];
-      w.R.inv[2] = q[5];
-      w.R.neg = np & 7u;
-      w.R.par = np >> 3;
-      w.R.t0 = split_time(q[6], q[7], part, K);
-      w.R.t1 = split_time(q[6], q[7], part + 1u, K);
-      home = hh;
+      w.R.o[0] = f[0];
+      w.R.o[1] = f[1];
+      w.R.o[2] = f[2];
+      w.R.inv[0] = f[3];
+      w.R.inv[1] = f[4];
+      w.R.inv[2] = f[5];
+      w.R.t0 = f[7];
+      w.R.t1 = f[6];
+      w.R.neg = (uint32_t)g[5] & 7u;
+      w.R.par = ((uint32_t)g[5] >> 3) & 7u;
+      home = (uint32_t)g[5] >> 6;
+      kf = g[4];
       tv = cross_time(w.R, minlen);
-      run = w.R.t0 < w.R.t1 && w.template start<FAM>(fm, mem) == RUN;
+      // The donor's node stack for every depth at or above nd, then the walk state just
+      // after leaving the donor's node: pop_to restores the node at depth nd.
+      const int nn = g[3];
+      const uint32_t ns = fm.stacked == ALL_STACKED ? (uint32_t)nn + 1u : slot_of(fm.stacked, nn + 1);
+      const uint2* dstk = stk - lane + (uint32_t)src;
+      for (uint32_t j = 0; j < ns; ++j) stk[j * BLOCK] = dstk[j * BLOCK];
+      w.t = f[7];
+      w.p[0] = g[0];
+      w.p[1] = g[1];
+      w.p[2] = g[2];
+      w.d = nn + 1;
+      w.steps = 0;
+      w.template pop_to<FAM>(fm, stk, nn, mem);
+      run = true;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1003,7 +1059,7 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n, uint32_t period,
-                                                            float minlen, uint32_t kmax) {
+                                                            float minlen) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
   extern __shared__ uint2 stk_all[];
@@ -1012,10 +1068,10 @@ __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, c
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x, w0 = threadIdx.x & ~63u;
   if (F.lds_words)
-    steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, kmax, best_all + w0,
+    steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, best_all + w0,
                               tbl_all + w0);
   else
-    steal_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, kmax, best_all + w0, tbl_all + w0);
+    steal_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, best_all + w0, tbl_all + w0);
 }
 
 // One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
@@ -1248,7 +1304,7 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
 }
 
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, uint32_t kmax, hipStream_t s) {
+                              uint32_t period, float minlen, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32) - BLOCK) {
     hvf_set_error("at most 2^32 - 257 rays per stealing call");
@@ -1259,7 +1315,7 @@ hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_r
   int4* h = reinterpret_cast<int4*>(d_hits);
 #define HVF_LAUNCH_STEAL(FAMV)                                                                                  \
   hipLaunchKernelGGL(trace_steal_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
-                     period, minlen, kmax)
+                     period, minlen)
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_STEAL)
 #undef HVF_LAUNCH_STEAL
   return launch_check("stealing trace");

@@ -136,9 +136,9 @@ def test_surface2048_split_schedule(H, surf2048, sd):
         assert compare(g.cpu().numpy(), ref, f"split {sd} {what}") == 0
 
 
-@pytest.mark.parametrize("sd", [dict(steal=1, steal_len=8, steal_parts=2), dict(steal=4, steal_len=16, steal_parts=64),
-                                dict(steal=8, steal_len=64, steal_parts=4),
-                                dict(steal=4, steal_len=8, steal_parts=2, lds_depths=3)], ids=lambda d: str(d))
+@pytest.mark.parametrize("sd", [dict(steal=1, steal_len=8), dict(steal=4, steal_len=16),
+                                dict(steal=8, steal_len=64),
+                                dict(steal=4, steal_len=8, lds_depths=3)], ids=lambda d: str(d))
 def test_surface2048_steal_schedule(H, surf2048, sd):
     """Whole 1080p frames, primary and bounce rays, traced with walks split among the idle
     lanes of each wave equal the plain schedule bit for bit, and sampled rays the oracle."""

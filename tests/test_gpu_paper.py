@@ -64,7 +64,8 @@ def test_paper_layout_surface_512(H):
 
 
 @pytest.mark.parametrize("sd", [dict(persistent=1, refill=8, inner=4), dict(sort=1, sort_bits=3),
-                                dict(split=8, split_budget=3), dict(split=64, split_budget=2, split_rounds=2)],
+                                dict(split=8, split_budget=3), dict(split=64, split_budget=2, split_rounds=2),
+                                dict(steal=1, steal_len=1), dict(steal=4, steal_len=8)],
                          ids=lambda d: str(d))
 def test_paper_layout_schedules(H, sd):
     import torch

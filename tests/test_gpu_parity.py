@@ -102,10 +102,10 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(split=8, split_budget=2, split_rounds=2), dict(split=64, split_budget=1, split_rounds=6),
              dict(split=2, split_budget=3, split_rounds=1), dict(split=4, split_budget=3, split_rounds=1, lds_depths=2),
              dict(split=16, split_budget=4, split_rounds=3, stack_depth=2),
-             dict(steal=1, steal_len=1, steal_parts=2), dict(steal=2, steal_len=3, steal_parts=64),
-             dict(steal=8, steal_len=16, steal_parts=4), dict(steal=64, steal_len=1, steal_parts=8),
-             dict(steal=4, steal_len=1, steal_parts=16, lds_depths=2), dict(steal=1, steal_len=2, steal_parts=2, stack_depth=2),
-             dict(steal=16, steal_len=1 << 20, steal_parts=2)]
+             dict(steal=1, steal_len=1), dict(steal=2, steal_len=3),
+             dict(steal=8, steal_len=16), dict(steal=64, steal_len=1),
+             dict(steal=4, steal_len=1, lds_depths=2), dict(steal=1, steal_len=2, stack_depth=2),
+             dict(steal=16, steal_len=1 << 20)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
@@ -150,6 +150,24 @@ def test_autotune_keeps_results(H):
     got = gpu_trace(v, rays)
     ref = oracle.Volume(spec, codes).trace(rays, nthreads=8)
     assert compare(got, ref, f"autotuned {H.schedule_dict(sc)}") == 0
+
+
+@pytest.mark.parametrize("spec", ["G(4) R(3,3,3) --whole-level-dedup --restart-sv", "S(2) G(2) R(2,2,2) --restart-sv",
+                                  "D(3,3,3,6) S(4)", "R(2,2,2) R(2,2,2) R(3,3,3)"])
+def test_steal_forks_keep_results(H, spec):
+    """Forked walks (stealing) with restart-sv stacks, distance fields and Raw pointer grids
+    give the plain schedule's hits bit for bit, at every check period."""
+    import torch
+    small = spec.startswith("S(2) G(2)")  # the only 64^3 format of this list
+    codes, ext = (W.scene_solid_noise(5), (64,) * 3) if small else (W.scene_shell(5, 7, 8, 4, 1.4), (128,) * 3)
+    rays = np.concatenate([W.random_rays(5, ext, 20000), W.camera_rays(5, 1, ext, 96, 64),
+                           np.concatenate([r for r, _ in EDGE_CASES])])
+    v = H.Volume(spec, codes)
+    d = torch.from_numpy(rays).cuda()
+    plain = v.trace(d).cpu().numpy()
+    for sd in (dict(steal=1, steal_len=1), dict(steal=2, steal_len=4), dict(steal=4, steal_len=1, stack_depth=3)):
+        got = v.trace(d, sched=H.schedule(**sd)).cpu().numpy()
+        assert np.array_equal(got, plain), f"{spec} {sd}"
 
 
 @pytest.mark.parametrize("spec", [sp + " --restart-sv" for sp in SPECS_8 if "--" not in sp] +

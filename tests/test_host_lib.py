@@ -229,13 +229,11 @@ def test_schedule_checks_split_fields():
            H.schedule(split=4, split_budget=8, persistent=1), H.schedule(split=4, split_budget=8, sort=1),
            H.schedule(split=-2, split_budget=8), H.schedule(split=4, split_budget=8, split_rounds=7),
            H.schedule(split_rounds=1), H.schedule(split=4, split_budget=8, split_rounds=-1),
-           H.schedule(steal=3, steal_len=8, steal_parts=2), H.schedule(steal=128, steal_len=8, steal_parts=2),
-           H.schedule(steal=-4, steal_len=8, steal_parts=2), H.schedule(steal=4, steal_len=0, steal_parts=2),
-           H.schedule(steal=4, steal_len=(1 << 20) + 1, steal_parts=2), H.schedule(steal=4, steal_len=8, steal_parts=1),
-           H.schedule(steal=4, steal_len=8, steal_parts=3), H.schedule(steal=4, steal_len=8, steal_parts=128),
-           H.schedule(steal=4, steal_len=8, steal_parts=2, persistent=1),
-           H.schedule(steal=4, steal_len=8, steal_parts=2, sort=1),
-           H.schedule(steal=4, steal_len=8, steal_parts=2, split=4, split_budget=8)]
+           H.schedule(steal=3, steal_len=8), H.schedule(steal=128, steal_len=8),
+           H.schedule(steal=-4, steal_len=8), H.schedule(steal=4, steal_len=0),
+           H.schedule(steal=4, steal_len=(1 << 20) + 1), H.schedule(steal=4, steal_len=8, persistent=1),
+           H.schedule(steal=4, steal_len=8, sort=1),
+           H.schedule(steal=4, steal_len=8, split=4, split_budget=8)]
     for sc in bad:
         st = H.lib().hvf_trace_sched(v.handle, None, 1, None, ctypes.byref(sc), None)
         assert H.STATUS[st] == "HVF_E_INPUT", H.schedule_dict(sc)
@@ -244,5 +242,5 @@ def test_schedule_checks_split_fields():
     fam = v.info()["kernel_family"]
     assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(split=8, split_budget=64, split_rounds=2))) == [
         f"trace_budget_kernel<{fam}u>", f"trace_resume_kernel<{fam}u>", f"trace_split_kernel<{fam}u>"]
-    assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(steal=4, steal_len=8, steal_parts=2))) == [
+    assert H.kernel_names(v.info(), H.schedule_dict(H.schedule(steal=4, steal_len=8))) == [
         f"trace_steal_kernel<{fam}u>"]
