@@ -104,8 +104,8 @@ typedef struct hvf_info {
  *   their t, packed densely, for split_budget, 2 split_budget, ... 2^(R-1) split_budget
  *   steps each; only the rays still walking after the last round are cut into segments.
  * steal = P > 0 (a power of two, 1..64; needs persistent = 0, sort = 0 and split = 0): one
- *   lane per ray, and every P steps each wave hands the lanes whose walks have ended the
- *   rest of walks still running in the wave. A walk whose rest [t, t1) is longer than the
+ *   lane per ray, and every P steps each wave with at least steal_idle (1..64) idle lanes
+ *   hands them the rest of walks still running in the wave. A walk whose rest [t, t1) is longer than the
  *   time the ray takes to cross steal_len voxels (1..2^20) along its fastest axis forks at
  *   the exit time e of one of its ancestor nodes: it keeps [t, e), and an idle lane
  *   continues the walk from e exactly as the walk would have, with a copy of its node
@@ -129,6 +129,7 @@ typedef struct hvf_schedule {
   int32_t split_rounds; /* restart rounds of the split schedule (0..6; needs split > 0) */
   int32_t steal;        /* 0, or P: see above */
   int32_t steal_len;    /* voxels; shorter rests are not forked (steal > 0) */
+  int32_t steal_idle;   /* idle lanes a wave needs before it forks walks (steal > 0) */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).
@@ -205,8 +206,8 @@ hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
 
 /* Autotune: time candidate schedules (one lane per ray; short stacks of 2 and 4 depths;
  * persistent at full, 2 or 4 blocks per CU with refill thresholds 8/32 and 4 or 16 steps
- * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; stealing
- * every 2, 4 or 8 steps for rests over 8 voxels, and every 4 steps over 32), then the best with the deepest LDS prefixes that fit, on the
+ * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; five
+ * stealing schedules), then the best with the deepest LDS prefixes that fit, on the
  * caller's device ray sample; pick the fastest, store it as the volume's schedule and copy
  * it to *out (may be NULL). d_hits_scratch: n device hits, overwritten. Synchronises
  * hip_stream. Results never depend on the schedule chosen. */

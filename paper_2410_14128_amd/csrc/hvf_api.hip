@@ -21,7 +21,7 @@ hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                               uint32_t budget, uint32_t klog2, uint32_t rounds, uint32_t* scratch, hipStream_t s);
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, hipStream_t s);
+                              uint32_t period, float minlen, uint32_t min_idle, hipStream_t s);
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
@@ -127,7 +127,7 @@ hvf_status check_sched(const hvf_schedule& sc) {
       sc.lds_depths > HVF_MAX_DEPTH || sc.split < 0 || sc.split > 64 || (sc.split & (sc.split - 1)) != 0 ||
       sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))) || sc.split_rounds < 0 ||
       sc.split_rounds > (int)hvf::HVF_SPLIT_MAX_ROUNDS || (sc.split_rounds && !sc.split) || sc.steal < 0 ||
-      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20))))
+      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20) || sc.steal_idle < 1 || sc.steal_idle > 64)))
     return fail(HVF_E_INPUT, "schedule field out of range");
   if (sc.split && (sc.persistent || sc.sort))
     return fail(HVF_E_INPUT, "the split schedule runs without persistent lanes and without sorting");
@@ -158,7 +158,8 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   const int family = hvf::family_of(v->layout);
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.steal)
-    return hvf::launch_trace_steal(F, family, d_rays, n, d_hits, (uint32_t)sc.steal, (float)sc.steal_len, s);
+    return hvf::launch_trace_steal(F, family, d_rays, n, d_hits, (uint32_t)sc.steal, (float)sc.steal_len,
+                                   (uint32_t)sc.steal_idle, s);
   if (sc.split) {
     const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split),
                    rounds = (uint32_t)sc.split_rounds;
@@ -227,9 +228,10 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
   // lanes), so K = 64 stands for every K the survivor count allows.
   const int split_cand[][3] = {{4, 64, 0}, {16, 64, 0}, {64, 32, 0}, {64, 64, 0}, {64, 128, 0}, {64, 48, 1}, {64, 64, 1}};
   for (const auto& c : split_cand) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, c[0], c[1], c[2]});
-  // Stealing: (period, length in voxels).
-  const int steal_cand[][2] = {{2, 8}, {4, 8}, {8, 8}, {4, 32}};
-  for (const auto& c : steal_cand) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, c[0], c[1]});
+  // Stealing: (period, length in voxels, idle lanes).
+  const int steal_cand[][3] = {{1, 2, 16}, {2, 2, 8}, {2, 8, 1}, {4, 8, 1}, {1, 8, 32}};
+  for (const auto& c : steal_cand)
+    cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, c[0], c[1], c[2]});
   hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");

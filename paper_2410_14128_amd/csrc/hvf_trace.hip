@@ -875,8 +875,8 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
 
 // ---------------------------------------------------------------- work stealing in a wave
 // One lane per ray, and the lanes whose walks have ended take over the rest of walks still
-// running in their wave. Every `period` steps (a power of two) a wave looks at its running
-// walks. A walk (its part [t, t1) of a ray) whose rest is longer than the time `tv` the ray
+// running in their wave. Every `period` steps (a power of two) a wave with at least
+// `min_idle` idle lanes looks at its running walks. A walk (its part [t, t1) of a ray) whose rest is longer than the time `tv` the ray
 // needs to cross `minlen` voxels along its fastest axis forks at the exit time e of one of
 // its ancestor nodes (the shallowest one it has not tried, that ends before t1): the walk
 // keeps [t, e) and an idle lane continues the walk exactly as the walk itself would after
@@ -929,7 +929,7 @@ __device__ __forceinline__ float cross_time(const Ray& R, float minlen) {
 template <uint32_t FAM>
 __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const float4* __restrict__ rays,
                                            int4* __restrict__ hits, uint32_t i, uint32_t n, uint32_t period,
-                                           float minlen, uint32_t* best, uint32_t* tbl) {
+                                           float minlen, uint32_t min_idle, uint32_t* best, uint32_t* tbl) {
   const uint32_t lane = __lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   Walk w{};
@@ -965,7 +965,7 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
     const uint64_t rm = __ballot(run);
     if (rm == 0ull) break;
     const uint32_t nidle = 64u - (uint32_t)__popcll(rm);
-    if (nidle == 0u) continue;
+    if (nidle < min_idle) continue;
     bool want = false;
     float e = 0.0f;
     int q[3] = {0, 0, 0}, nd = 0;
@@ -1059,7 +1059,7 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n, uint32_t period,
-                                                            float minlen) {
+                                                            float minlen, uint32_t min_idle) {
   __shared__ uint32_t dtab[HVF_MAX_DEPTH];
   __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
   extern __shared__ uint2 stk_all[];
@@ -1068,10 +1068,11 @@ __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, c
   const Fmt fm = fmt_of(F, dtab, pre);
   const uint32_t i = blockIdx.x * BLOCK + threadIdx.x, w0 = threadIdx.x & ~63u;
   if (F.lds_words)
-    steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, best_all + w0,
+    steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, min_idle, best_all + w0,
                               tbl_all + w0);
   else
-    steal_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, best_all + w0, tbl_all + w0);
+    steal_loop<FAM>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, min_idle, best_all + w0,
+                    tbl_all + w0);
 }
 
 // One lane per ray, rays taken in the order perm[] gives (results at each ray's index).
@@ -1304,7 +1305,7 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
 }
 
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, hipStream_t s) {
+                              uint32_t period, float minlen, uint32_t min_idle, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32) - BLOCK) {
     hvf_set_error("at most 2^32 - 257 rays per stealing call");
@@ -1315,7 +1316,7 @@ hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_r
   int4* h = reinterpret_cast<int4*>(d_hits);
 #define HVF_LAUNCH_STEAL(FAMV)                                                                                  \
   hipLaunchKernelGGL(trace_steal_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
-                     period, minlen)
+                     period, minlen, min_idle)
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_STEAL)
 #undef HVF_LAUNCH_STEAL
   return launch_check("stealing trace");

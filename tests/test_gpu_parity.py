@@ -105,7 +105,8 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(steal=1, steal_len=1), dict(steal=2, steal_len=3),
              dict(steal=8, steal_len=16), dict(steal=64, steal_len=1),
              dict(steal=4, steal_len=1, lds_depths=2), dict(steal=1, steal_len=2, stack_depth=2),
-             dict(steal=16, steal_len=1 << 20)]
+             dict(steal=16, steal_len=1 << 20), dict(steal=1, steal_len=1, steal_idle=16),
+             dict(steal=2, steal_len=2, steal_idle=64)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))

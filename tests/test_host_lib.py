@@ -232,6 +232,7 @@ def test_schedule_checks_split_fields():
            H.schedule(steal=3, steal_len=8), H.schedule(steal=128, steal_len=8),
            H.schedule(steal=-4, steal_len=8), H.schedule(steal=4, steal_len=0),
            H.schedule(steal=4, steal_len=(1 << 20) + 1), H.schedule(steal=4, steal_len=8, persistent=1),
+           H.schedule(steal=4, steal_len=8, steal_idle=0), H.schedule(steal=4, steal_len=8, steal_idle=65),
            H.schedule(steal=4, steal_len=8, sort=1),
            H.schedule(steal=4, steal_len=8, split=4, split_budget=8)]
     for sc in bad:
