@@ -115,6 +115,116 @@ def time_launches(fn_list, steps, warmup):
     return total_ms / steps, per
 
 
+SCHEDULE_BOUNCE = os.path.join(ROOT, "workloads", "schedule_bounce2048.json")
+
+
+def run_headline(args, torch, H, W, C):
+    """The bench step: one trace call over the bounce (incoherent) rays of one 1920x1080 frame
+    of the 2048^3 surface volume in G(7) R(4,4,4) --whole-level-dedup, rays and hits resident
+    in HBM. The primary frame is traced once (plain schedule, untimed) to derive the bounce
+    rays. The schedule comes from the committed autotuner result unless --retune (then the
+    autotuner picks it on the bounce rays of a held-out view, truncated to the same count).
+    Roofline of the call's kernel: algorithmic bytes per launch (B_ray, sector model, from the
+    counting kernel on a seeded sample of the same rays, times the rays) over its mean launch
+    time from HIP events on the launch stream."""
+    cfg = C.SURF2048
+    n = 1 << cfg["log2n"]
+    t0 = time.time()
+    codes = C.scene(cfg)
+    spec = cfg["specs"][0]
+    log(f"[bench] headline: 2048^3 scene {len(codes)} voxels ({len(codes) / n ** 3:.4%}) in {time.time() - t0:.1f}s")
+    prim = C.primary_rays(cfg, 0)
+    v = H.Volume(spec, codes)
+    v.upload()
+    plain = H.schedule()
+    h = v.trace(torch.from_numpy(prim).cuda(), sched=plain)
+    torch.cuda.synchronize()
+    b, _ = W.bounce_rays(cfg["bounce_seed"], prim, h.cpu().numpy())
+    del h
+    d_b = torch.from_numpy(b).cuda()
+    hb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+    fixed = {} if (args.retune or args.no_tune) else load_schedules(SCHEDULE_BOUNCE)
+    if args.no_tune:
+        sched = H.schedule_dict(plain)
+    elif spec in fixed:
+        v.set_schedule(H.schedule(**fixed[spec]))
+        sched = H.schedule_dict(v.get_schedule())
+    else:
+        held = C.primary_rays(cfg, 1)
+        hh = v.trace(torch.from_numpy(held).cuda(), sched=plain)
+        torch.cuda.synchronize()
+        bt, _ = W.bounce_rays(cfg["bounce_seed"] + 1, held, hh.cpu().numpy())
+        sched = H.schedule_dict(v.autotune(torch.from_numpy(np.ascontiguousarray(bt[:len(b)])).cuda()))
+        del hh, bt
+    source = ("autotuned on a held-out view's bounce rays" if not fixed else
+              f"from {os.path.relpath(SCHEDULE_BOUNCE, ROOT)}")
+    log(f"[bench] headline: {len(b)} bounce rays, schedule {sched} ({source}); warmup {args.warmup}, "
+        f"timing {args.steps} steps")
+    ms, per = time_launches([lambda: v.trace(d_b, hb)], args.steps, args.warmup)
+    ref = v.trace(d_b, sched=plain)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(hb, ref))
+    value = len(b) / (ms * 1e-3) / 1e6
+    info = v.info()
+    kernel = H.kernel_name(info, sched)
+    if args.sample > 0:
+        rng = np.random.default_rng(4242)
+        smp = torch.from_numpy(b[np.sort(rng.choice(len(b), min(args.sample, len(b)), replace=False))]).cuda()
+        bw, bs, loads, over, _ = byte_model(v, smp)
+    else:
+        bw = bs = loads = float("nan")
+        over = 0
+    avg_ms = per[0]
+    bytes_launch = bs * len(b)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    fin = bool(np.isfinite(achieved))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if fin else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4) if fin else None,
+                "traffic": traffic_from_profile("headline-bounce-2048", kernel),
+                "kernel": kernel, "launches_per_step": 1, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": round(bytes_launch) if fin else None,
+                "B_ray_sector": round(bs, 1), "B_ray_word": round(bw, 1), "loads_per_ray": round(loads, 1),
+                "log_overflow_rays": over, "grid_threads": ((len(b) + 255) // 256) * 256,
+                "roof_mrays_s": round(HBM_PEAK_GBS * 1e9 / bs / 1e6, 1) if fin else None}
+    log(f"[bench] headline: {ms * 1e3:.1f} us per step, {value:.1f} Mrays/s; {kernel} {avg_ms * 1e3:.1f} us, "
+        f"B_ray {bs:.0f} B, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of HBM roofline); "
+        f"hits identical to the plain schedule: {same}")
+    out = {"value": value, "ms": ms, "rays": len(b), "roofline": roofline, "schedule": sched,
+           "schedule_source": source, "identical_to_plain": same, "format": spec, "format_bytes": info["bytes"],
+           "occupancy": len(codes) / n ** 3, "bounce": b}
+    v.close()
+    return out
+
+
+def run_small(args, torch, H, W, C):
+    """The small case: 64^3 solid spheres with 5% noise in R(2,2,2) S(2) R(2,2,2), one 256x256
+    view of primary rays, autotuned on a held-out view of the same size."""
+    cfg = C.SMALL
+    codes = C.scene(cfg)
+    rays = C.primary_rays(cfg, 0)
+    v = H.Volume(cfg["spec"], codes)
+    v.upload()
+    d = torch.from_numpy(rays).cuda()
+    hits = torch.empty((len(rays), 4), dtype=torch.int32, device="cuda")
+    sched = (H.schedule_dict(v.get_schedule()) if args.no_tune else
+             H.schedule_dict(v.autotune(torch.from_numpy(C.primary_rays(cfg, 1)).cuda())))
+    ms, per = time_launches([lambda: v.trace(d, hits)], args.steps, args.warmup)
+    if args.sample > 0:
+        bw, bs, loads, _, _ = byte_model(v, d)
+    else:
+        bw = bs = loads = float("nan")
+    r = {"format": cfg["spec"], "rays": len(rays), "ms": ms, "mrays_s": len(rays) / (ms * 1e-3) / 1e6,
+         "B_ray_sector": bs, "B_ray_word": bw, "loads_per_ray": loads, "schedule": sched,
+         "kernel": H.kernel_name(v.info(), sched), "format_bytes": v.info()["bytes"],
+         "occupancy": len(codes) / 64 ** 3}
+    r["frac_roofline"] = r["mrays_s"] * 1e6 * bs / (HBM_PEAK_GBS * 1e9)
+    r.update({k: round(x, 4) for k, x in r.items() if isinstance(x, float)})
+    log(f"[bench] small-64 {cfg['spec']}: {r['mrays_s']:.1f} Mrays/s ({r['frac_roofline']:.1%}, B_ray {bs:.0f} B, "
+        f"{sched})")
+    v.close()
+    return r
+
+
 def run_surface512(args, torch, H, W, C):
     cfg = C.SURF512
     n = 1 << cfg["log2n"]
@@ -731,49 +841,89 @@ def run_served(args, torch, H, W, C):
     sat = burst["requests_per_s"]
     log(f"[bench] served: closed-loop saturation {sat:.0f} requests/s, {burst['mrays_s']} Mrays/s")
     levels = {}
+    arrivals = {}
     for frac in (0.5, 0.8, 0.95):
         gaps = rng.exponential(1.0 / (frac * sat), size=nreq)
-        arr = np.cumsum(gaps) - gaps[0]
-        levels[str(frac)] = run(arr, args.serve_slots, 3)
+        arrivals[frac] = np.cumsum(gaps) - gaps[0]
+        levels[str(frac)] = run(arrivals[frac], args.serve_slots, 3)
         log(f"[bench] served @ {frac:.2f} S: p50 {levels[str(frac)]['p50_ms']} ms, p99 {levels[str(frac)]['p99_ms']} ms, "
             f"{levels[str(frac)]['mrays_s']} Mrays/s")
-    gaps = rng.exponential(1.0 / (0.8 * sat), size=nreq)
-    arr = np.cumsum(gaps) - gaps[0]
-    fifo = run(arr, 1, 1)
+    fifo = run(arrivals[0.8], 1, 1)  # the same arrival trace as the 0.8 S level
     log(f"[bench] served FIFO one-at-a-time @ 0.80 S: p50 {fifo['p50_ms']} ms, p99 {fifo['p99_ms']} ms, "
         f"{fifo['mrays_s']} Mrays/s")
     for v in vols:
         v.close()
     return {"volumes": len(vols), "saturation_requests_per_s": sat, "closed_loop": burst, "poisson": levels,
-            "fifo_at_0.8": fifo, "budget_mib": args.serve_budget, "slots": args.serve_slots}
+            "fifo_at_0.8": fifo, "budget_mib": args.serve_budget, "slots": args.serve_slots,
+            "requests_per_level": args.serve_requests, "warmup_requests_per_level": args.serve_warmup}
 
 
-def cpu_baseline(res512, C, budget_rays):
-    """The oracle, as it stands, on a bounded sample of the 512^3 workload."""
+def host_cpu():
+    """CPU model, logical CPU count and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def start_oracle_build(C):
+    """Build the oracle's volume of the headline format in a background thread (the oracle's
+    build is a long single-threaded host computation; ctypes releases the GIL while it runs,
+    so the GPU legs proceed meanwhile). Returns a function that waits and yields
+    (volume, build seconds)."""
+    import threading
     import oracle
-    cfg = C.SURF512
-    nthreads = min(16, os.cpu_count() or 1)
-    rng = np.random.default_rng(99)
-    total_rays, t_all, t_one = 0, 0.0, 0.0
-    per_fmt = max(1, budget_rays // (len(cfg["specs"]) * len(res512["views"])))
-    for spec in cfg["specs"]:
+    cfg = C.SURF2048
+    box = {}
+
+    def work():
         t0 = time.time()
-        ov = oracle.Volume(spec, res512["codes"])
-        log(f"[bench] oracle build {spec}: {time.time() - t0:.1f}s (not timed)")
-        for r in res512["views"]:
-            smp = r[np.sort(rng.choice(len(r), per_fmt, replace=False))]
-            t0 = time.perf_counter()
-            ov.trace(smp, nthreads=nthreads)
-            t_all += time.perf_counter() - t0
-            t0 = time.perf_counter()
-            ov.trace(smp[: max(1, per_fmt // 8)], nthreads=1)
-            t_one += (time.perf_counter() - t0) * 8
-            total_rays += len(smp)
-        del ov
-    return {"value": round(total_rays / t_all / 1e6, 4), "unit": "Mrays/s", "cores": nthreads, "kind": "oracle",
-            "value_1core": round(total_rays / t_one / 1e6, 4),
-            "sample": f"{per_fmt} random pixels per view x 4 views x {len(cfg['specs'])} formats of the 512^3 "
-                      f"workload ({total_rays} rays); oracle built in the same formats; static thread split"}
+        box["vol"] = oracle.Volume(cfg["specs"][0], C.scene(cfg))
+        box["s"] = time.time() - t0
+
+    th = threading.Thread(target=work, daemon=True)
+    th.start()
+
+    def wait():
+        th.join()
+        return box["vol"], box["s"]
+    return wait
+
+
+def cpu_baseline(wait_oracle, rays):
+    """The oracle, as it stands, on the headline workload: the same format and the same bounce
+    rays, every usable host core (the oracle's static thread split), median of three runs;
+    one core on every 8th ray, scaled. The build is not timed."""
+    ov, build_s = wait_oracle()
+    model, nproc, usable = host_cpu()
+    t_all = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ov.trace(rays, nthreads=usable)
+        t_all.append(time.perf_counter() - t0)
+    one = rays[::8]
+    t_one = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ov.trace(one, nthreads=1)
+        t_one.append(time.perf_counter() - t0)
+    v_all = len(rays) / float(np.median(t_all)) / 1e6
+    v_one = len(one) / float(np.median(t_one)) / 1e6
+    log(f"[bench] oracle on {usable} of {nproc} host CPUs ({model}): {v_all:.3f} Mrays/s; one core {v_one:.3f}; "
+        f"oracle build {build_s:.0f} s (not timed)")
+    return {"value": round(v_all, 4), "unit": "Mrays/s", "cores": usable, "kind": "oracle",
+            "value_1core": round(v_one, 4), "nproc": nproc, "cpu_model": model,
+            "sample": f"all {len(rays)} bounce rays of the headline frame (one core: every 8th ray), oracle built in "
+                      f"the same format (build {build_s:.0f} s, not timed); median of 3 runs; static thread split"}
 
 
 def main():
@@ -782,12 +932,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sample", type=int, default=16384, help="rays per view for the byte model")
-    ap.add_argument("--cpu-rays", type=int, default=200000, help="oracle sample size (rays)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-2048", action="store_true")
+    ap.add_argument("--no-2048", action="store_true", help="skip the 2048^3 leg (both formats, 8 frames)")
+    ap.add_argument("--no-512", action="store_true", help="skip the 512^3 leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (one lane per ray)")
     ap.add_argument("--retune", action="store_true",
-                    help="autotune the 512^3 formats even when a schedule file is present")
+                    help="autotune the headline and the 512^3 formats even when a schedule file is present")
     ap.add_argument("--schedules", default=SCHEDULES_512,
                     help="per-format 512^3 schedules (a bench JSON line; default: the committed autotuner results)")
     ap.add_argument("--untuned", action="store_true", help="also time the 512^3 formats with the plain schedule")
@@ -797,13 +947,12 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-df", action="store_true", help="skip the distance-field format leg")
     ap.add_argument("--no-build", action="store_true", help="skip the construction (host vs device) leg")
-    ap.add_argument("--serve-requests", type=int, default=600)
-    ap.add_argument("--serve-warmup", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-budget", type=int, default=4096, help="server memory budget, MiB")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--only", choices=["surface512", "surface2048", "bounce2048", "batched", "served", "df", "sweep",
-                                       "sweep-paper", "build",
-                             "restart"],
+    ap.add_argument("--only", choices=["headline", "small", "surface512", "surface2048", "bounce2048", "batched",
+                                       "served", "df", "sweep", "sweep-paper", "build", "restart"],
                     default=None,
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
@@ -852,41 +1001,49 @@ def main():
     if args.only == "served":
         print(json.dumps(run_served(args, torch, H, W, C)))
         return
-    res = run_surface512(args, torch, H, W, C)
-    if args.only == "surface512":
+    if args.only == "headline":
+        run_headline(args, torch, H, W, C)
         return
-    df = None
-    if not args.no_df:
-        df = run_df512(args, torch, H, C, res)
-    if args.only == "df":
+    if args.only == "small":
+        print(json.dumps({"small_64": run_small(args, torch, H, W, C)}))
         return
-    extra = None
-    if not args.no_2048:
-        extra = run_surface2048(args, torch, H, W, C)
-    batched = None
-    if not args.no_batched:
-        batched = run_batched(args, torch, H, W, C)
-    served = None
-    if not args.no_served:
-        served = run_served(args, torch, H, W, C)
-    construction = None
-    if not args.no_build:
-        construction = run_construction(args, torch, H, C, formats_2048=C.BUILD_2048)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(res, C, args.cpu_rays)
+    if args.only in ("surface512", "df"):
+        res = run_surface512(args, torch, H, W, C)
+        if args.only == "df":
+            run_df512(args, torch, H, C, res)
+        return
+    wait_oracle = None if args.no_cpu_baseline else start_oracle_build(C)
+    head = run_headline(args, torch, H, W, C)
+    small = run_small(args, torch, H, W, C)
+    res = None if args.no_512 else run_surface512(args, torch, H, W, C)
+    df = None if (args.no_df or res is None) else run_df512(args, torch, H, C, res)
+    extra = None if args.no_2048 else run_surface2048(args, torch, H, W, C)
+    batched = None if args.no_batched else run_batched(args, torch, H, W, C)
+    served = None if args.no_served else run_served(args, torch, H, W, C)
+    construction = None if args.no_build else run_construction(args, torch, H, C, formats_2048=C.BUILD_2048)
+    cpu = None if wait_oracle is None else cpu_baseline(wait_oracle, head["bounce"])
+    s512 = None
+    if res is not None:
+        s512 = {"mrays_s": round(res["value"], 2), "ms_per_step": round(res["ms"], 3),
+                "rays_per_step": res["rays_per_step"], "occupancy": round(res["occupancy"], 5),
+                "schedules": res["schedules"], "roofline": res["roofline"], "per_format": res["per_format"]}
     line = {
         "metric": "Mrays/s (primary & incoherent) per format; % HBM roofline; p50/p99 ms served",
-        "value": round(res["value"], 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(res["ms"], 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded SDF shell scenes, seeded pinhole cameras)",
-        "config": {"workload": "surface-512: 512^3 shell of 32 spheres + 16 tori, 9 formats x 4 views x 1920x1080 "
-                               "primary rays", "rays_per_step": res["rays_per_step"],
-                   "occupancy": round(res["occupancy"], 5), "formats": C.SURF512["specs"],
-                   "schedules": res["schedules"]},
-        "roofline": res["roofline"],
+        "value": round(head["value"], 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded SDF shell scenes, seeded pinhole cameras, "
+                                                      "seeded cosine-weighted bounces)",
+        "config": {"workload": "surface-2048 incoherent: the bounce rays of one 1920x1080 frame (one cosine-weighted "
+                               "bounce per primary hit) of the 2048^3 shell of 96 spheres + 32 tori, traced through "
+                               "G(7) R(4,4,4) --whole-level-dedup in one call",
+                   "rays_per_step": head["rays"], "format": head["format"], "format_bytes": head["format_bytes"],
+                   "occupancy": round(head["occupancy"], 5), "schedule": head["schedule"],
+                   "schedule_source": head["schedule_source"]},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "per_format": res["per_format"],
+        "identical_to_plain_schedule": head["identical_to_plain"],
+        "small_64": small,
+        "surface_512": s512,
         "surface_2048": extra,
         "distance_field_512": df,
         "batched": batched,
