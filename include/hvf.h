@@ -199,6 +199,22 @@ hvf_status hvf_trace(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* 
 hvf_status hvf_trace_sched(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                            const hvf_schedule* sched, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hvf_trace_sched for a split schedule
+ * (sched->split > 0) whose survivor lists live in a fixed device array of the library
+ * instead of memory allocated per call. The array holds HVF_NOALLOC_MAX_RAYS rays' lists
+ * (about 32 MiB per GPU, kept until the process ends); each GPU the library runs on has
+ * its own. Hits are identical to hvf_trace_sched's with the same schedule.
+ * vol: uploaded already (hvf_upload, or any earlier trace): HVF_E_STATE otherwise, since
+ *   the upload allocates. d_rays, d_hits, n, hip_stream: as for hvf_trace.
+ * Errors: HVF_E_INPUT (null pointers, sched NULL or without split, a schedule field out of
+ * range, n > HVF_NOALLOC_MAX_RAYS), HVF_E_STATE, HVF_E_DEVICE. Makes no allocation: no
+ * hipMalloc, hipFree or allocating library call. Calls that overlap on one GPU (concurrent
+ * streams or host threads) share the array and race; the caller serialises them. */
+#define HVF_NOALLOC_MAX_RAYS (1u << 21)
+hvf_status hvf_trace_split_noalloc(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                                   const hvf_schedule* sched, void* hip_stream);
+
 /* Get / set the schedule hvf_trace uses for this volume (initially one lane per ray).
  * Not thread-safe against concurrent traces of the same volume. */
 hvf_status hvf_get_schedule(const hvf_volume* vol, hvf_schedule* out);

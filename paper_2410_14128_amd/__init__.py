@@ -113,6 +113,9 @@ class hvf_serve_stats(ctypes.Structure):
 _lib = None
 
 
+NOALLOC_MAX_RAYS = 1 << 21  # HVF_NOALLOC_MAX_RAYS
+
+
 def lib():
     """Load libhvf.so (built by ``paper_2410_14128_amd.build``); raises if it is missing."""
     global _lib
@@ -132,6 +135,8 @@ def lib():
         L.hvf_trace.argtypes = [vp, vp, sz, vp, vp]
         L.hvf_trace_sched.restype = i32
         L.hvf_trace_sched.argtypes = [vp, vp, sz, vp, ctypes.POINTER(hvf_schedule), vp]
+        L.hvf_trace_split_noalloc.restype = i32
+        L.hvf_trace_split_noalloc.argtypes = [vp, vp, sz, vp, ctypes.POINTER(hvf_schedule), vp]
         L.hvf_get_schedule.restype = i32
         L.hvf_get_schedule.argtypes = [vp, ctypes.POINTER(hvf_schedule)]
         L.hvf_set_schedule.restype = i32
@@ -305,6 +310,17 @@ class Volume:
         else:
             _check(lib().hvf_trace_sched(self._h, rays.data_ptr(), n, hits.data_ptr(), ctypes.byref(sched),
                                          _stream_ptr(stream)))
+        return hits
+
+    def trace_split_noalloc(self, rays, hits, sched: hvf_schedule, stream=None):
+        """hvf_trace_split_noalloc: a split-schedule trace whose scratch is the library's fixed
+        device array (no allocation; the volume must be uploaded). Returns ``hits``."""
+        import torch
+        assert rays.is_cuda and rays.dtype == torch.float32 and rays.shape[-1] == 8 and rays.is_contiguous()
+        n = rays.shape[0]
+        assert hits.is_cuda and hits.dtype == torch.int32 and hits.shape == (n, 4) and hits.is_contiguous()
+        _check(lib().hvf_trace_split_noalloc(self._h, rays.data_ptr(), n, hits.data_ptr(), ctypes.byref(sched),
+                                             _stream_ptr(stream)))
         return hits
 
     def autotune(self, sample_rays, stream=None) -> hvf_schedule:

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -208,6 +209,61 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (st != HVF_OK) return st;
   return hvf::launch_trace_persistent(F, family, d_rays, n, d_hits, counter, (uint32_t)sc.refill, (uint32_t)sc.inner,
                                       grid, s);
+}
+
+// The allocation-free split trace: survivor lists in a fixed device array. Host code never
+// passes the array's name to a kernel: each device's address comes from hipGetSymbolAddress
+// on its first call there, with that device current.
+namespace {
+constexpr size_t NOALLOC_WORDS = hvf::HVF_SPLIT_HEAD_WORDS + 4 * (size_t)HVF_NOALLOC_MAX_RAYS;
+__device__ __align__(256) uint32_t scratch[NOALLOC_WORDS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::once_flag g_noalloc_once[NOALLOC_MAX_DEVICES];
+uint32_t* g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+hipError_t g_noalloc_err[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+hvf_status hvf_trace_split_noalloc(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
+                                   const hvf_schedule* sched, void* stream) {
+  if (!v) return fail(HVF_E_INPUT, "null volume");
+  if (!sched || sched->split == 0) return fail(HVF_E_INPUT, "the allocation-free trace needs a split schedule");
+  const hvf_schedule sc = *sched;
+  hvf_status st = check_sched(sc);
+  if (st != HVF_OK) return st;
+  if (n > HVF_NOALLOC_MAX_RAYS)
+    return fail(HVF_E_INPUT, "the allocation-free trace takes at most " + std::to_string(HVF_NOALLOC_MAX_RAYS) +
+                                 " rays per call, got " + std::to_string(n));
+  if (n == 0) return HVF_OK;
+  if (!d_rays || !d_hits) return fail(HVF_E_INPUT, "null ray or hit buffer");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> g(v->dev_mu);
+    if (!v->dbuf) return fail(HVF_E_STATE, "the allocation-free trace needs an uploaded volume (hvf_upload)");
+  }
+  if (v->device != dev) return fail(HVF_E_STATE, "the volume was uploaded to another device");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(HVF_E_DEVICE, "device index out of range");
+  std::call_once(g_noalloc_once[dev], [dev] {
+    void* p = nullptr;
+    g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_ptr[dev] = g_noalloc_err[dev] == hipSuccess ? static_cast<uint32_t*>(p) : nullptr;
+  });
+  if (g_noalloc_err[dev] != hipSuccess || !g_noalloc_ptr[dev])
+    return hip_fail(g_noalloc_err[dev] != hipSuccess ? g_noalloc_err[dev] : hipErrorInvalidSymbol,
+                    "hipGetSymbolAddress of the allocation-free scratch");
+  if (v->spec.paper && (sc.stack_depth > 0 || sc.lds_depths > 0))
+    return fail(HVF_E_INPUT, "short stacks and staged depths need the library's own layout, not --paper-layout");
+  hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
+  if (!hvf::lds_prefix_words(v->layout, v->built, sc.lds_depths, &F.lds_words))
+    return fail(HVF_E_INPUT, "the top " + std::to_string(sc.lds_depths) + " depths exceed the LDS prefix limit of " +
+                                 std::to_string(hvf::HVF_LDS_PREFIX_MAX_WORDS) + " words");
+  static_assert(hvf::HVF_SPLIT_HEAD_WORDS + 4 * (size_t)HVF_NOALLOC_MAX_RAYS == NOALLOC_WORDS, "scratch size");
+  // split_scratch_words(n, rounds) <= NOALLOC_WORDS for every n <= HVF_NOALLOC_MAX_RAYS.
+  const uint32_t klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split);
+  return hvf::launch_trace_split(F, hvf::family_of(v->layout), d_rays, n, d_hits, (uint32_t)sc.split_budget, klog2,
+                                 (uint32_t)sc.split_rounds, g_noalloc_ptr[dev], (hipStream_t)stream);
 }
 
 hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hit* d_hits, hvf_schedule* out,
