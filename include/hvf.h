@@ -304,6 +304,8 @@ hvf_status hvf_server_add_volume(hvf_server* s, hvf_volume* vol, int* vol_id);
  * request can never fit the budget. */
 hvf_status hvf_server_submit(hvf_server* s, int vol_id, const hvf_ray* rays, size_t n, hvf_hit* hits,
                              uint64_t* req_id);
+/* *done = 1 once the request has completed; its status is returned then (a request whose
+ * step failed on the device completes with that error and never writes its hits). */
 hvf_status hvf_server_poll(hvf_server* s, uint64_t req_id, int* done, double* latency_ms);
 /* Results of a completed request submitted with hits == NULL (valid until released). */
 hvf_status hvf_server_result(hvf_server* s, uint64_t req_id, const hvf_hit** hits);
@@ -312,6 +314,10 @@ hvf_status hvf_server_release(hvf_server* s, uint64_t req_id);
 hvf_status hvf_server_wait(hvf_server* s, uint64_t req_id, double* latency_ms);
 /* Wait until every submitted request has completed. */
 hvf_status hvf_server_drain(hvf_server* s);
+/* Testing the error path: the next n steps (n >= 0) fail at launch, before any device work,
+ * as a step whose upload or launch fails does. Their requests complete with HVF_E_DEVICE,
+ * their memory and slots are returned, and the server refuses new requests afterwards. */
+hvf_status hvf_server_fail_steps(hvf_server* s, int n);
 hvf_status hvf_server_stats(hvf_server* s, hvf_serve_stats* out);
 /* Finish queued work, then release the server (not the volumes). NULL is ignored. */
 void hvf_server_destroy(hvf_server* s);
@@ -334,8 +340,13 @@ hvf_status hvf_info_get(const hvf_volume* vol, hvf_info* out);
 /* Copy the word buffer (host copy) into words[0..cap); *n_words receives its length. */
 hvf_status hvf_words(const hvf_volume* vol, uint32_t* words, size_t cap, size_t* n_words);
 
-/* Save / load a built volume (header with magic, spec, word count and checksum, then the
- * words). hvf_load returns a new handle owned by the caller. */
+/* Save / load a built volume: the construction's output file (Sec. 4.1 writes the built
+ * format to an output file that the renderer then loads). The file holds a magic, the
+ * spec, the word count, the per-depth and per-level statistics, the words and an FNV-1a
+ * checksum. hvf_load returns a new handle owned by the caller. It refuses (HVF_E_INPUT) a
+ * file whose checksum, spec or statistics do not match, and one in which any word index
+ * a walk can read (a pointer, child descriptor, cell or block of any node reachable from
+ * the root) or any depth offset lies past the buffer, so no kernel reads outside it. */
 hvf_status hvf_save(const hvf_volume* vol, const char* path);
 hvf_status hvf_load(const char* path, hvf_volume** out);
 

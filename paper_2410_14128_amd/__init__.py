@@ -167,6 +167,8 @@ def lib():
         L.hvf_server_release.argtypes = [vp, ctypes.c_uint64]
         L.hvf_server_drain.restype = i32
         L.hvf_server_drain.argtypes = [vp]
+        L.hvf_server_fail_steps.restype = i32
+        L.hvf_server_fail_steps.argtypes = [vp, ctypes.c_int]
         L.hvf_server_stats.restype = i32
         L.hvf_server_stats.argtypes = [vp, ctypes.POINTER(hvf_serve_stats)]
         L.hvf_server_destroy.restype = None

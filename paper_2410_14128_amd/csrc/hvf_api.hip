@@ -592,6 +592,7 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
     if (ok) {
       v->layout = v->spec.paper ? hvf::make_paper_layout(v->spec) : hvf::make_layout(v->spec);
       ok = v->layout.d.size() == nd && v->spec.lv.size() == nl;
+      if (ok) ok = hvf::validate_words(v->layout, v->built, err);
     }
   }
   if (!ok) {

@@ -179,8 +179,11 @@ hvf_status hvf_batch_autotune(hvf_batch* b, void* stream, hvf_batch_opts* out) {
     for (int inner : {2, 8, 32})
       for (int bpc : {0, 4}) cand.push_back(hvf_batch_opts{refill, inner, bpc, keep.use_graph});
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+  if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
     return fail(HVF_E_DEVICE, "hipEventCreate failed");
+  }
   float best = 1e30f;
   hvf_batch_opts pick = keep;
   hvf_status st = HVF_OK;

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cstring>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "hvf_internal.h"
 
@@ -286,6 +287,124 @@ bool lds_prefix_words(const Layout& L, const Built& B, int lds_depths, uint32_t*
   }
   if (w > HVF_LDS_PREFIX_MAX_WORDS) return false;
   *words = (uint32_t)w;
+  return true;
+}
+
+namespace {
+// Depth-first pass over every node a walk can reach, checking each word index it reads.
+struct Validator {
+  const Layout& L;
+  const std::vector<uint32_t>& w;
+  std::unordered_set<uint64_t> seen;
+  std::string err;
+  bool in(uint64_t ix) {
+    if (ix < w.size()) return true;
+    err = "word index " + std::to_string(ix) + " past the buffer (" + std::to_string(w.size()) + " words)";
+    return false;
+  }
+  // The node at depth d that the walk enters at pointer ptr; (hb, hv): the header its parent
+  // read (HK_MASK depths).
+  bool node(size_t d, uint64_t ptr, uint32_t hb, uint32_t hv) {
+    if (d >= L.d.size()) {
+      err = "a pointer below the last depth";
+      return false;
+    }
+    const DepthInfo& D = L.d[d];
+    if (!seen.insert(((uint64_t)d << 40) | ptr).second) return true;
+    uint64_t base = ptr;
+    uint32_t valid = 0;
+    switch (D.hk) {
+      case HK_SVO:
+        if (!in(ptr + 1)) return false;
+        base = w[ptr];
+        valid = w[ptr + 1] & 0xFFu;
+        break;
+      case HK_DAG:
+        if (!in(ptr)) return false;
+        base = ptr + 1;
+        valid = w[ptr] & 0xFFu;
+        break;
+      case HK_MASK:
+        base = hb;
+        valid = hv;
+        break;
+      case HK_MASKLOAD:
+        return in(ptr + 1);
+      default:
+        break;
+    }
+    const uint64_t cells = 1ull << (D.w[0] + D.w[1] + D.w[2]);
+    uint32_t rank = 0;
+    for (uint64_t lin = 0; lin < cells; ++lin) {
+      const bool oct = D.nk >= NK_SVO_INNER && D.nk != NK_PRAW_VOX && D.nk != NK_PDF_PTR && D.nk != NK_PDF_VOX;
+      if (oct && !((valid >> lin) & 1u)) continue;
+      switch (D.nk) {
+        case NK_RAW_PTR:
+          if (!in(base + lin)) return false;
+          if (w[base + lin] && !node(d + 1, w[base + lin], 0, 0)) return false;
+          break;
+        case NK_DF_PTR:
+          if (!in(base + lin)) return false;
+          if (!(w[base + lin] & DF_EMPTY) && !node(d + 1, w[base + lin], 0, 0)) return false;
+          break;
+        case NK_BLOCKS:
+        case NK_PRAW_VOX:
+          if (!in(base + (D.nk == NK_BLOCKS ? 2 : 1) * lin + (D.nk == NK_BLOCKS ? 1 : 0))) return false;
+          break;
+        case NK_DF_BLOCKS:
+          if (!in(base + 4 * lin + 3)) return false;
+          break;
+        case NK_PDF_VOX:
+          if (!in(base + 2 * lin + 1)) return false;
+          break;
+        case NK_PDF_PTR:
+          if (!in(base + 2 * lin + 1)) return false;
+          if (w[base + 2 * lin] && !node(d + 1, w[base + 2 * lin], 0, 0)) return false;
+          break;
+        case NK_SVO_INNER:
+          if (!node(d + 1, base + 2 * rank, 0, 0)) return false;
+          break;
+        case NK_OCT_PTR:
+          if (!in(base + rank) || !node(d + 1, w[base + rank], 0, 0)) return false;
+          break;
+        case NK_DAG_INNER: {
+          if (!in(base + 2 * rank + 1)) return false;
+          const uint32_t c = w[base + 2 * rank];
+          if (!in(c) || !node(d + 1, c, c + 1u, w[base + 2 * rank + 1] & 0xFFu)) return false;
+          break;
+        }
+        case NK_PSVO_TERM:
+          if (!in(base + 2 * rank) || !node(d + 1, w[base + 2 * rank], 0, 0)) return false;
+          break;
+        case NK_PDAG_TERM:
+          if (!in(base + rank) || !in(w[base + rank]) || !node(d + 1, w[w[base + rank]], 0, 0)) return false;
+          break;
+        default:  // NK_CELLS, NK_OCT_FINAL: register tests only
+          return true;
+      }
+      ++rank;
+    }
+    return true;
+  }
+};
+}  // namespace
+
+bool validate_words(const Layout& L, const Built& B, std::string& err) {
+  const uint64_t nw = B.words.size();
+  for (uint64_t off : B.depth_offset)
+    if (off > nw || (off & 15u)) {
+      err = "depth offset " + std::to_string(off) + " is past the buffer or not 16-word aligned";
+      return false;
+    }
+  if (nw == 0) {
+    err = "empty word buffer";
+    return false;
+  }
+  Validator v{L, B.words, {}, {}};
+  if (B.words[0] != 0 && !v.node(0, B.words[0], 0, 0)) {
+    err = v.err;
+    return false;
+  }
   return true;
 }
 

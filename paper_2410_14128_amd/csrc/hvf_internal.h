@@ -147,6 +147,12 @@ constexpr uint32_t HVF_LDS_PREFIX_MAX_WORDS = 8192;
 // depth is staged. Returns false if that exceeds HVF_LDS_PREFIX_MAX_WORDS.
 bool lds_prefix_words(const Layout& L, const Built& B, int lds_depths, uint32_t* words);
 
+// Check a word buffer read from a file before any kernel walks it: every depth offset is
+// inside the buffer and 16-word aligned, and every word index the walk can read from any
+// node it can reach (pointers, child descriptors, cells, blocks) is inside the buffer.
+// False with a message otherwise.
+bool validate_words(const Layout& L, const Built& B, std::string& err);
+
 // Stack-slot mask of a layout: every depth, or with restart-sv only the root depth of each
 // level; stack_depth > 0 further keeps only depths < stack_depth (depth 0 always).
 uint32_t stacked_mask(const Layout& L, bool restart_sv, int stack_depth);

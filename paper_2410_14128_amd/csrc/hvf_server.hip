@@ -138,6 +138,7 @@ struct hvf_server {
   bool have_first = false;
   Clock::time_point t_first, t_last;
   bool stop = false;
+  int fail_steps = 0;  // testing: steps still to fail at launch (hvf_server_fail_steps)
   hvf_status fault = HVF_OK;
   std::string fault_msg;
   std::thread engine;
@@ -274,12 +275,30 @@ void engine_loop(hvf_server* S) {
         st.busy = true;
         S->steps_launched += 1;
         S->max_step_requests = std::max<uint64_t>(S->max_step_requests, take);
+        const bool inject = S->fail_steps > 0;
+        if (inject) --S->fail_steps;
         lk.unlock();
-        const hvf_status s = launch_step(S, st);
+        const hvf_status s = inject ? fail(HVF_E_DEVICE, "injected step failure (hvf_server_fail_steps)")
+                                    : launch_step(S, st);
         lk.lock();
         if (s != HVF_OK) {
+          // Nothing was recorded on done_ev: finish the step's requests here with the
+          // error, after the copies it may have enqueued (their staging ranges are freed).
+          (void)hipStreamSynchronize(st.stream);
+          const auto now = Clock::now();
+          for (auto& rp : st.reqs) {
+            Request& r = *rp;
+            r.status = s;
+            r.t_done = now;
+            r.done = true;
+            if (r.out || r.released) S->arena->release(r.off, req_bytes(r.n));  // else held until released
+            S->slots_used -= 1;
+          }
+          st.reqs.clear();
+          st.busy = false;
           S->fault = s;
           S->fault_msg = hvf_last_error();
+          S->cv_done.notify_all();
         }
         progressed = true;
         break;
@@ -435,6 +454,13 @@ hvf_status hvf_server_release(hvf_server* S, uint64_t req_id) {
   r.released = true;
   S->all.erase(it);
   S->cv.notify_all();
+  return HVF_OK;
+}
+
+hvf_status hvf_server_fail_steps(hvf_server* S, int n) {
+  if (!S || n < 0) return fail(HVF_E_INPUT, "null server or negative count");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->fail_steps = n;
   return HVF_OK;
 }
 

@@ -126,3 +126,33 @@ def test_pinned_rays_and_held_results(H, world):
     st = srv.stats()
     assert st["completed"] == 12 and st["peak_bytes"] <= st["budget_bytes"]
     srv.close()
+
+
+def test_failed_step_completes_its_requests_with_the_error(H, world):
+    """A step that fails at launch (forced from the host) finishes its requests with
+    HVF_E_DEVICE: the wait reports the error instead of stale hits, the caller's hit array
+    is left untouched, the request's memory and slot are returned, and the server then
+    refuses new requests."""
+    vols, reqs = world
+    srv = H.Server(1 << 24, max_slots=8, max_steps=2)
+    vid = srv.add_volume(vols[0][3])
+    rays = np.ascontiguousarray(W.camera_rays(7, 0, (64,) * 3, 32, 32))
+    ok = np.full((len(rays), 4), 7, np.int32)
+    srv.wait(srv.submit(vid, rays, ok))
+    assert np.array_equal(ok, gpu_trace(vols[0][3], rays))
+    srv.fail_steps(1)
+    bad = np.full((len(rays), 4), 7, np.int32)
+    rid = srv.submit(vid, rays, bad)
+    with pytest.raises(H.HvfError) as e:
+        srv.wait(rid)
+    assert e.value.name == "HVF_E_DEVICE"
+    assert (bad == 7).all()
+    with pytest.raises(H.HvfError) as e:
+        srv.poll(rid)
+    assert e.value.name == "HVF_E_DEVICE"
+    with pytest.raises(H.HvfError) as e:
+        srv.submit(vid, rays, bad)
+    assert e.value.name == "HVF_E_DEVICE"
+    st = srv.stats()
+    assert st["completed"] == 1
+    srv.close()

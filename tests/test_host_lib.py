@@ -154,6 +154,62 @@ def test_save_load_roundtrip(tmp_path):
         H.Volume.load(p)
 
 
+def _fnv64(data: bytes, h: int = 1469598103934665603) -> int:
+    """FNV-1a, 64 bits (the volume file's checksum)."""
+    for byte in data:
+        h = ((h ^ byte) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+@pytest.mark.parametrize("spec", ["G(3) R(3,3,3) --whole-level-dedup", "R(2,2,2) S(2) R(2,2,2)",
+                                  "D(3,3,3,4) S(3)", "S(2) G(2) R(2,2,2) --paper-layout",
+                                  "R(3,3,3) G(3) --paper-layout", "D(2,2,2,3) R(4,4,4) --paper-layout"])
+def test_load_rejects_pointers_past_the_buffer(tmp_path, spec):
+    """Loading checks every word index a walk can read (a file with a valid checksum may
+    still be stale or hand-made): each pointer or descriptor word a walk follows, set past
+    the buffer with the checksum recomputed, is refused with HVF_E_INPUT; the untouched
+    file loads."""
+    import struct
+    codes = W.scene_shell(6, 6, 6, 2, 1.4)
+    v = H.Volume(spec, codes)
+    p = str(tmp_path / "v.hvf")
+    v.save(p)
+    raw = open(p, "rb").read()
+    body, words = raw[:-8], v.words()
+    assert struct.unpack("<Q", raw[-8:])[0] == _fnv64(body)
+    H.Volume.load(p)
+    woff = len(body) - 4 * len(words)  # the words are the last field before the checksum
+    # word 0 (the root pointer) and a spread of other words; each is a pointer for some
+    # formats and payload for others, so only count the refusals.
+    cand = [0] + list(np.linspace(1, len(words) - 1, 40).astype(int))
+    refused = 0
+    for k in cand:
+        b = bytearray(body)
+        struct.pack_into("<I", b, woff + 4 * k, 0x7FFFFFF0)
+        q = str(tmp_path / f"bad{k}.hvf")
+        open(q, "wb").write(bytes(b) + struct.pack("<Q", _fnv64(bytes(b))))
+        try:
+            u = H.Volume.load(q)
+        except H.HvfError as e:
+            assert e.name == "HVF_E_INPUT" and "past the buffer" in str(e)
+            refused += 1
+            continue
+        u.close()
+    assert refused >= 1  # the root pointer at least
+    # a depth offset past the buffer (own layout only: the paper layout stores none)
+    if "--paper-layout" not in spec:
+        slen = struct.unpack_from("<Q", body, 8)[0]
+        nd = struct.unpack_from("<Q", body, 8 + 8 + slen + 16)[0]
+        off0 = 8 + 8 + slen + 32 + 8 * nd  # depth_offset[0]
+        b = bytearray(body)
+        struct.pack_into("<Q", b, off0 + 8 * (nd - 1), len(words) + 16)
+        q = str(tmp_path / "badoff.hvf")
+        open(q, "wb").write(bytes(b) + struct.pack("<Q", _fnv64(bytes(b))))
+        with pytest.raises(H.HvfError) as e:
+            H.Volume.load(q)
+        assert e.value.name == "HVF_E_INPUT"
+
+
 def test_gpu_calls_without_device_fail_loudly():
     import torch
     if torch.cuda.is_available():
