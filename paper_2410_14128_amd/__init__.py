@@ -476,6 +476,10 @@ class Server:
             self._keep.pop(req_id)
         return h, lat.value
 
+    def fail_steps(self, n: int):
+        """Testing: make the next n steps fail at launch (hvf_server_fail_steps)."""
+        _check(lib().hvf_server_fail_steps(self._h, n))
+
     def drain(self):
         _check(lib().hvf_server_drain(self._h))
 
