@@ -83,6 +83,10 @@ typedef struct hvf_info {
                                            launches (node/header kinds compiled in) */
   int32_t paper_layout;                 /* 1: built with --paper-layout (the paper's word
                                            layout, Sec. 3.3); 0: the library's own layout */
+  int32_t depth_buffers;                /* 1: per-depth regions: the words of depth d are
+                                           [depth_offset[d], depth_offset[d + 1]) and every
+                                           pointer word p to a node of depth t stands for
+                                           word depth_offset[t] - 16 + p (0 stays "empty") */
 } hvf_info;
 
 /* How a trace is scheduled on the device. Results never depend on it.

@@ -46,7 +46,7 @@ class hvf_info(ctypes.Structure):
         ("depth_offset", ctypes.c_uint64 * HVF_MAX_DEPTH),
         ("num_voxels", ctypes.c_uint64),
         ("level_maxdist", ctypes.c_int32 * HVF_MAX_LEVELS),
-        ("kernel_family", ctypes.c_uint32), ("paper_layout", ctypes.c_int32),
+        ("kernel_family", ctypes.c_uint32), ("paper_layout", ctypes.c_int32), ("depth_buffers", ctypes.c_int32),
     ]
 
 
@@ -283,6 +283,7 @@ class Volume:
             "level_maxdist": [int(I.level_maxdist[k]) for k in range(n)],
             "kernel_family": int(I.kernel_family),
             "paper_layout": bool(I.paper_layout),
+            "depth_buffers": bool(I.depth_buffers),
         }
 
     def words(self) -> np.ndarray:

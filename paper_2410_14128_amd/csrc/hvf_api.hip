@@ -86,6 +86,12 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
   } else {
     v->layout = hvf::make_layout(spec);
     st = hvf::build_words(v->spec, v->layout, morton, n, v->built, err);
+    if (st == HVF_OK && v->built.regions && !v->spec.regions) {
+      // the builder chose per-depth regions (the format needs 2^32 words or more): the spec
+      // says so, so a saved file loads the same way
+      v->spec.regions = true;
+      v->spec.text += " --depth-buffers";
+    }
   }
   if (st != HVF_OK) {
     delete v;
@@ -151,12 +157,13 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (v->spec.paper && (sc.stack_depth > 0 || sc.lds_depths > 0))
     return fail(HVF_E_INPUT, "short stacks and staged depths need the library's own layout, not --paper-layout");
   hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  hvf::set_regions(F, v->built);
   if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
   if (!hvf::lds_prefix_words(v->layout, v->built, sc.lds_depths, &F.lds_words))
     return fail(HVF_E_INPUT, "the top " + std::to_string(sc.lds_depths) + " depths exceed the LDS prefix limit of " +
                                  std::to_string(hvf::HVF_LDS_PREFIX_MAX_WORDS) + " words");
   hipStream_t s = (hipStream_t)stream;
-  const int family = hvf::family_of(v->layout);
+  const int family = hvf::volume_family(v->spec, v->layout);
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.steal)
     return hvf::launch_trace_steal(F, family, d_rays, n, d_hits, (uint32_t)sc.steal, (float)sc.steal_len,
@@ -255,6 +262,7 @@ hvf_status hvf_trace_split_noalloc(hvf_volume* v, const hvf_ray* d_rays, size_t 
   if (v->spec.paper && (sc.stack_depth > 0 || sc.lds_depths > 0))
     return fail(HVF_E_INPUT, "short stacks and staged depths need the library's own layout, not --paper-layout");
   hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  hvf::set_regions(F, v->built);
   if (sc.stack_depth > 0) hvf::set_stacked(F, hvf::stacked_mask(v->layout, v->spec.restart_sv, sc.stack_depth));
   if (!hvf::lds_prefix_words(v->layout, v->built, sc.lds_depths, &F.lds_words))
     return fail(HVF_E_INPUT, "the top " + std::to_string(sc.lds_depths) + " depths exceed the LDS prefix limit of " +
@@ -262,7 +270,7 @@ hvf_status hvf_trace_split_noalloc(hvf_volume* v, const hvf_ray* d_rays, size_t 
   static_assert(hvf::HVF_SPLIT_HEAD_WORDS + 4 * (size_t)HVF_NOALLOC_MAX_RAYS == NOALLOC_WORDS, "scratch size");
   // split_scratch_words(n, rounds) <= NOALLOC_WORDS for every n <= HVF_NOALLOC_MAX_RAYS.
   const uint32_t klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split);
-  return hvf::launch_trace_split(F, hvf::family_of(v->layout), d_rays, n, d_hits, (uint32_t)sc.split_budget, klog2,
+  return hvf::launch_trace_split(F, hvf::volume_family(v->spec, v->layout), d_rays, n, d_hits, (uint32_t)sc.split_budget, klog2,
                                  (uint32_t)sc.split_rounds, g_noalloc_ptr[dev], (hipStream_t)stream);
 }
 
@@ -388,7 +396,10 @@ hvf_status hvf_trace_count(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (!d_rays || !d_hits || !d_count || (cap && !d_log)) return fail(HVF_E_INPUT, "null buffer");
   hvf_status st = hvf_upload(v, stream);
   if (st != HVF_OK) return st;
-  const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
+  hvf::set_regions(F, v->built);
+  if (v->built.regions && v->built.words.size() >= (1ull << 32))
+    return fail(HVF_E_UNSUPPORTED, "the counting trace logs 32-bit word indices: buffers of 2^32 words or more are not counted");
   return hvf::launch_trace_count(F, v->spec.paper, d_rays, n, d_hits, d_log, cap, d_count, d_steps,
                                  (hipStream_t)stream);
 }
@@ -475,7 +486,8 @@ hvf_status hvf_info_get(const hvf_volume* v, hvf_info* out) {
     I.depth_offset[d] = d < v->built.depth_offset.size() ? v->built.depth_offset[d] : 0;
   }
   I.num_voxels = v->built.nvox;
-  I.kernel_family = hvf::FAMILIES[hvf::family_of(v->layout)];
+  I.kernel_family = hvf::family_value(hvf::volume_family(v->spec, v->layout));
+  I.depth_buffers = v->built.regions ? 1 : 0;
   I.paper_layout = v->spec.paper ? 1 : 0;
   *out = I;
   return HVF_OK;
@@ -562,7 +574,7 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
     r.get(&v->built.nvox, 8);
     r.get(&nd, 8);
     r.get(&nl, 8);
-    ok = r.ok && nw >= 1 && nw < (1ull << 32) && nd <= HVF_MAX_DEPTH && nl <= HVF_MAX_LEVELS;
+    ok = r.ok && nw >= 1 && nw < (1ull << 40) && nd <= HVF_MAX_DEPTH && nl <= HVF_MAX_LEVELS;
   }
   if (ok) {
     v->built.depth_nodes.resize(nd);
@@ -591,7 +603,8 @@ hvf_status hvf_load(const char* path, hvf_volume** out) {
     ok = (st == HVF_OK);
     if (ok) {
       v->layout = v->spec.paper ? hvf::make_paper_layout(v->spec) : hvf::make_layout(v->spec);
-      ok = v->layout.d.size() == nd && v->spec.lv.size() == nl;
+      ok = v->layout.d.size() == nd && v->spec.lv.size() == nl && (nw < (1ull << 32) || v->spec.regions);
+      v->built.regions = v->spec.regions;
       if (ok) ok = hvf::validate_words(v->layout, v->built, err);
     }
   }

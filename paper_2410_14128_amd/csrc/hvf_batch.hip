@@ -111,6 +111,10 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
       delete b;
       return fail(HVF_E_INPUT, "null volume or buffer in batch " + std::to_string(i));
     }
+    if (vols[i]->built.regions) {
+      delete b;
+      return fail(HVF_E_UNSUPPORTED, "batches do not hold volumes with per-depth regions (batch " + std::to_string(i) + ")");
+    }
     st = hvf_upload(vols[i], nullptr);
     if (st != HVF_OK) {
       delete b;

@@ -74,6 +74,8 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
         s.restart_sv = true;
       } else if (flag == "--paper-layout") {
         s.paper = true;
+      } else if (flag == "--depth-buffers") {
+        s.regions = true;
       } else {
         err = "unknown flag '" + flag + "'";
         return HVF_E_SPEC;
@@ -180,6 +182,10 @@ hvf_status parse_spec(const char* text, Spec& out, std::string& err) {
   if (s.paper) {
     if (s.restart_sv) {
       err = "--restart-sv is not supported with --paper-layout";
+      return HVF_E_UNSUPPORTED;
+    }
+    if (s.regions) {
+      err = "--depth-buffers is not supported with --paper-layout";
       return HVF_E_UNSUPPORTED;
     }
     for (const LevelSpec& L : s.lv)
@@ -295,8 +301,11 @@ namespace {
 struct Validator {
   const Layout& L;
   const std::vector<uint32_t>& w;
+  std::vector<uint64_t> rb;  // per-depth region starts (zero: absolute pointers)
   std::unordered_set<uint64_t> seen;
   std::string err;
+  uint64_t up(size_t d) const { return d + 1 < rb.size() ? rb[d + 1] : 0; }  // region of depth d + 1
+  uint64_t here(size_t d) const { return d < rb.size() ? rb[d] : 0; }        // region of depth d
   bool in(uint64_t ix) {
     if (ix < w.size()) return true;
     err = "word index " + std::to_string(ix) + " past the buffer (" + std::to_string(w.size()) + " words)";
@@ -304,7 +313,7 @@ struct Validator {
   }
   // The node at depth d that the walk enters at pointer ptr; (hb, hv): the header its parent
   // read (HK_MASK depths).
-  bool node(size_t d, uint64_t ptr, uint32_t hb, uint32_t hv) {
+  bool node(size_t d, uint64_t ptr, uint64_t hb, uint32_t hv) {
     if (d >= L.d.size()) {
       err = "a pointer below the last depth";
       return false;
@@ -316,7 +325,7 @@ struct Validator {
     switch (D.hk) {
       case HK_SVO:
         if (!in(ptr + 1)) return false;
-        base = w[ptr];
+        base = w[ptr] + (D.nk == NK_SVO_INNER ? up(d) : here(d));
         valid = w[ptr + 1] & 0xFFu;
         break;
       case HK_DAG:
@@ -341,11 +350,11 @@ struct Validator {
       switch (D.nk) {
         case NK_RAW_PTR:
           if (!in(base + lin)) return false;
-          if (w[base + lin] && !node(d + 1, w[base + lin], 0, 0)) return false;
+          if (w[base + lin] && !node(d + 1, up(d) + w[base + lin], 0, 0)) return false;
           break;
         case NK_DF_PTR:
           if (!in(base + lin)) return false;
-          if (!(w[base + lin] & DF_EMPTY) && !node(d + 1, w[base + lin], 0, 0)) return false;
+          if (!(w[base + lin] & DF_EMPTY) && !node(d + 1, up(d) + w[base + lin], 0, 0)) return false;
           break;
         case NK_BLOCKS:
         case NK_PRAW_VOX:
@@ -365,11 +374,11 @@ struct Validator {
           if (!node(d + 1, base + 2 * rank, 0, 0)) return false;
           break;
         case NK_OCT_PTR:
-          if (!in(base + rank) || !node(d + 1, w[base + rank], 0, 0)) return false;
+          if (!in(base + rank) || !node(d + 1, up(d) + w[base + rank], 0, 0)) return false;
           break;
         case NK_DAG_INNER: {
           if (!in(base + 2 * rank + 1)) return false;
-          const uint32_t c = w[base + 2 * rank];
+          const uint64_t c = up(d) + w[base + 2 * rank];
           if (!in(c) || !node(d + 1, c, c + 1u, w[base + 2 * rank + 1] & 0xFFu)) return false;
           break;
         }
@@ -400,8 +409,10 @@ bool validate_words(const Layout& L, const Built& B, std::string& err) {
     err = "empty word buffer";
     return false;
   }
-  Validator v{L, B.words, {}, {}};
-  if (B.words[0] != 0 && !v.node(0, B.words[0], 0, 0)) {
+  Validator v{L, B.words, {}, {}, {}};
+  if (B.regions)
+    for (uint64_t off : B.depth_offset) v.rb.push_back(off - REGION_BIAS);
+  if (B.words[0] != 0 && !v.node(0, (B.regions ? v.rb[0] : 0) + B.words[0], 0, 0)) {
     err = v.err;
     return false;
   }
@@ -414,6 +425,16 @@ void set_stacked(DevFormat& F, uint32_t mask) {
   const uint32_t all = (F.ndepth >= 32) ? 0xFFFFFFFFu : ((1u << F.ndepth) - 1u);
   F.stacked = (mask == all) ? 0xFFFFFFFFu : mask;
   F.nslots = (uint32_t)__builtin_popcount(mask);
+}
+
+int volume_family(const Spec& s, const Layout& L) { return s.regions ? FAMILY_REGIONS : family_of(L); }
+
+uint32_t family_value(int family) { return family == FAMILY_REGIONS ? (FAM_ALL | FAM_REGIONS) : FAMILIES[family]; }
+
+void set_regions(DevFormat& F, const Built& B) {
+  F.regions = B.regions ? 1u : 0u;
+  for (size_t d = 0; d < HVF_MAX_DEPTH; ++d)
+    F.rbase[d] = (B.regions && d < B.depth_offset.size()) ? B.depth_offset[d] - REGION_BIAS : 0;
 }
 
 int family_of(const Layout& L) {
@@ -749,24 +770,40 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
   }
   bool df_ptr = false;
   for (const DepthInfo& di : L.d) df_ptr = df_ptr || di.nk == NK_DF_PTR;
-  if (cur >= (df_ptr ? (1ull << 31) : (1ull << 32))) {
-    err = "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
-          "-bit word offsets" + (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : "");
-    return HVF_E_OVERFLOW;
+  // One buffer addressed by 32-bit pointers while it fits (31 bits below a DF pointer grid,
+  // whose cells keep the top bit for empty ones); past that, per-depth regions with
+  // region-relative pointers, each region within the same bound.
+  bool regions = s.regions;
+  if (!regions && cur >= (df_ptr ? (1ull << 31) : (1ull << 32))) regions = true;
+  if (regions) {
+    for (size_t d = 0; d < D; ++d) {
+      const uint64_t size = ((d + 1 < D) ? base[d + 1] : cur) - base[d] + REGION_BIAS;
+      const bool below_df = d > 0 && L.d[d - 1].nk == NK_DF_PTR;
+      if (size >= (below_df ? (1ull << 31) : (1ull << 32))) {
+        err = "format needs " + std::to_string(cur) + " words, and its depth " + std::to_string(d) + " alone " +
+              std::to_string(size) + ", beyond " + (below_df ? "31" : "32") + "-bit region-relative pointers";
+        return HVF_E_OVERFLOW;
+      }
+    }
   }
+  B.regions = regions;
   try {
     B.words.assign(cur, 0u);
   } catch (const std::bad_alloc&) {
     err = "host allocation failed";
     return HVF_E_NOMEM;
   }
-  B.words[0] = (uint32_t)(base[0] + root_id);
+  // Pointers: absolute word indices, or with per-depth regions indices relative to the
+  // region of the depth they point into (the next depth's; an SVO node's pointer array
+  // lies in its own depth's region).
+  B.words[0] = (uint32_t)((regions ? REGION_BIAS : base[0]) + root_id);
   for (size_t d = 0; d < D; ++d) {
     const DepthInfo& di = L.d[d];
     std::vector<uint32_t>& A = b.arena[d];
     uint32_t* dst = B.words.data() + base[d];
     std::memcpy(dst, A.data(), A.size() * 4);
-    const uint64_t nb = (d + 1 < D) ? base[d + 1] : 0;
+    const uint64_t nb = regions ? REGION_BIAS : ((d + 1 < D) ? base[d + 1] : 0);
+    const uint64_t ab = regions ? auxb[d] - base[d] + REGION_BIAS : auxb[d];
     switch (di.nk) {
       case NK_RAW_PTR:
         for (size_t i = 0; i < A.size(); ++i) dst[i] = A[i] ? (uint32_t)(nb + A[i] - 1) : 0u;
@@ -786,7 +823,7 @@ hvf_status build_words(const Spec& s, const Layout& L, const uint64_t* codes, si
         break;
       case NK_OCT_PTR:
         if (di.hk == HK_SVO) {
-          for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(auxb[d] + A[i]);
+          for (size_t i = 0; i < A.size(); i += 2) dst[i] = (uint32_t)(ab + A[i]);
           uint32_t* ad = B.words.data() + auxb[d];
           for (size_t i = 0; i < b.aux[d].size(); ++i) ad[i] = (uint32_t)(nb + b.aux[d][i]);
         } else {

@@ -805,6 +805,8 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   hvf_status st = hvf::parse_spec(format_spec, spec, err);
   if (st != HVF_OK) return devbuild_fail(st, err);
   if (spec.paper) return devbuild_fail(HVF_E_UNSUPPORTED, "device construction builds the library's own layout only");
+  if (spec.regions)
+    return devbuild_fail(HVF_E_UNSUPPORTED, "device construction builds one buffer of 32-bit pointers (no --depth-buffers)");
   if (n && !d_morton) return devbuild_fail(HVF_E_INPUT, "null Morton code array");
   if (n > (size_t)INT_MAX) return devbuild_fail(HVF_E_UNSUPPORTED, "a device construction takes fewer than 2^31 codes");
   hvf_volume* v = new (std::nothrow) hvf_volume();

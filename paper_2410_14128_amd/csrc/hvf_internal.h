@@ -27,6 +27,8 @@ struct Spec {
   bool wld = false;         // whole-level de-duplication of SVDAG nodes (Sec. 4.3)
   bool restart_sv = false;  // restarting sparse-voxel intersection (Sec. 4.3)
   bool paper = false;       // --paper-layout: the paper's word layout with RGBA voxels
+  bool regions = false;     // per-depth word regions with region-relative pointers (--depth-buffers,
+                            // or chosen by the builder when the format needs 2^32 words or more)
   int ext[3] = {0, 0, 0};
   std::vector<int> sub;  // sub[k]: log2 side (voxels) of a level-k sub-volume, k >= 1; sub[n] = 0
   std::string text;
@@ -96,6 +98,13 @@ Layout make_paper_layout(const Spec& s);
 
 // ------------------------------------------------------------------ built word buffer
 struct Built {
+  // With per-depth regions (Spec::regions) the nodes of depth d occupy words
+  // [depth_offset[d], depth_offset[d + 1]) and every pointer word is an index relative to
+  // depth_offset[t] - REGION_BIAS, t the depth it points into, so each region stays below
+  // 2^32 words while the whole buffer may be larger (the paper's multiple buffers with
+  // indirection, Sec. 3.3: the indirection is the per-depth region table). The bias keeps
+  // every pointer above 0, the empty marker.
+  bool regions = false;
   std::vector<uint32_t> words;
   std::vector<uint64_t> depth_nodes, depth_offset, depth_words, level_nodes;
   uint64_t nvox = 0;
@@ -125,9 +134,14 @@ struct DevFormat {
   uint32_t stacked;
   uint32_t nslots;
   uint32_t lds_words;
-  uint32_t pad;
+  uint32_t regions;  // 1: per-depth regions; word index of region d's start in rbase[d]
   uint32_t dinfo[HVF_MAX_DEPTH];
+  uint64_t rbase[HVF_MAX_DEPTH];
 };
+
+constexpr uint64_t REGION_BIAS = 16;
+// Per-depth regions of a built buffer (no-op unless B.regions): rbase[d] = depth_offset[d] - REGION_BIAS.
+void set_regions(DevFormat& F, const Built& B);
 
 // Split schedule scratch: survivor counters (one per launch that fills a list, the first
 // launch and each restart round), then one survivor list of n entries (8 bytes each), or
@@ -188,6 +202,9 @@ constexpr uint32_t FAM_PAPER = fam_nk(NK_RAW_PTR) | fam_nk(NK_PRAW_VOX) | fam_nk
                                fam_nk(NK_SVO_INNER) | fam_nk(NK_OCT_PTR) | fam_nk(NK_OCT_FINAL) |
                                fam_nk(NK_PSVO_TERM) | fam_nk(NK_PDAG_TERM) | fam_hk(HK_RAW) | fam_hk(HK_SVO) |
                                fam_hk(HK_DAG);
+// Kernels for buffers with per-depth regions (Spec::regions): every kind, region-relative reads.
+constexpr uint32_t FAM_REGIONS = 1u << 30;
+constexpr int FAMILY_REGIONS = 12;  // family index of those kernels (after the FAMILIES table)
 constexpr uint32_t FAMILIES[] = {FAM_BRICK,    FAM_DAG_BRICK, FAM_SVO_BRICK, FAM_RAW_BRICK, FAM_OCTREE, FAM_RAW_OCTREE,
                                  FAM_DF_BRICK, FAM_DF_OCTREE, FAM_OCT_BRICK, FAM_NODF,      FAM_PAPER,  FAM_ALL};
 constexpr int NUM_FAMILIES = 12;
@@ -203,6 +220,10 @@ constexpr bool fam_w1(uint32_t f) { return f == FAM_OCTREE; }
 
 // Index into FAMILIES of the first family covering the layout.
 int family_of(const Layout& L);
+// Family index of a volume: FAMILY_REGIONS for per-depth regions, else family_of(layout); and
+// the family's kind-set value.
+int volume_family(const Spec& s, const Layout& L);
+uint32_t family_value(int family);
 // Whether the layout has a distance-field depth.
 bool has_df(const Layout& L);
 // Kind set of a volume for the batched kernel: 2 in the paper's layout, 1 with a

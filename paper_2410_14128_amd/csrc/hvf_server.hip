@@ -367,6 +367,7 @@ hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_ste
 
 hvf_status hvf_server_add_volume(hvf_server* S, hvf_volume* v, int* vol_id) {
   if (!S || !v || !vol_id) return fail(HVF_E_INPUT, "null argument");
+  if (v->built.regions) return fail(HVF_E_UNSUPPORTED, "the server does not hold volumes with per-depth regions");
   hvf_status st = hvf_upload(v, nullptr);
   if (st != HVF_OK) return st;
   std::lock_guard<std::mutex> lk(S->mu);

@@ -150,11 +150,13 @@ __device__ __forceinline__ gword* as_global(const uint32_t* p) { return (gword*)
 __device__ __forceinline__ lword* as_lds(const uint32_t* p) { return (lword*)p; }
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint2 ld2(gword* buf, uint32_t ix) {
+template <class I>
+__device__ __forceinline__ uint2 ld2(gword* buf, I ix) {
   const u32x2 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x2*>(buf + ix);
   return make_uint2(v.x, v.y);
 }
-__device__ __forceinline__ uint4 ld4(gword* buf, uint32_t ix) {
+template <class I>
+__device__ __forceinline__ uint4 ld4(gword* buf, I ix) {
   const u32x4 v = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(buf + ix);
   return make_uint4(v.x, v.y, v.z, v.w);
 }
@@ -172,28 +174,43 @@ struct Fmt {
   gword* buf;
   uint64_t pop_lut;
   const uint32_t* dtab;
+  const uint64_t* rtab;  // per-depth region starts (buffers with per-depth regions)
   int ext[3];
   uint32_t stacked;  // depths with a node-stack slot
   lword* pre;
   uint32_t npre;
   // Kernels are compiled twice, with and without a staged prefix (FAM_PRE), so reads in
   // the common unstaged case carry no per-lane test.
-  template <uint32_t FAM>
-  __device__ __forceinline__ uint32_t w1(uint32_t ix) const {
+  // ix: a word index, 32-bit, or 64-bit in buffers with per-depth regions.
+  template <uint32_t FAM, class I>
+  __device__ __forceinline__ uint32_t w1(I ix) const {
     if ((FAM & FAM_PRE) && ix < npre) return pre[ix];
     return buf[ix];
   }
-  template <uint32_t FAM>
-  __device__ __forceinline__ uint2 w2(uint32_t ix) const {
+  template <uint32_t FAM, class I>
+  __device__ __forceinline__ uint2 w2(I ix) const {
     if ((FAM & FAM_PRE) && ix + 2u <= npre) return make_uint2(pre[ix], pre[ix + 1u]);
     return ld2(buf, ix);
   }
-  template <uint32_t FAM>
-  __device__ __forceinline__ uint4 w4(uint32_t ix) const {
+  template <uint32_t FAM, class I>
+  __device__ __forceinline__ uint4 w4(I ix) const {
     if ((FAM & FAM_PRE) && ix + 4u <= npre) return make_uint4(pre[ix], pre[ix + 1u], pre[ix + 2u], pre[ix + 3u]);
     return ld4(buf, ix);
   }
 };
+
+// LDS words of the per-depth tables: descriptors, then the 64-bit region starts.
+constexpr int DTAB_WORDS = 3 * HVF_MAX_DEPTH;
+
+// Index of a word of the current depth: rb + ix in buffers with per-depth regions (rb, the
+// start of the depth's region), else ix.
+template <uint32_t FAM>
+__device__ __forceinline__ auto gx(uint32_t ix, uint64_t rb) {
+  if constexpr ((FAM & FAM_REGIONS) != 0u)
+    return rb + (uint64_t)ix;
+  else
+    return ix;
+}
 
 // Every depth stacked (the default): the slot of depth d is d.
 constexpr uint32_t ALL_STACKED = 0xFFFFFFFFu;
@@ -208,6 +225,7 @@ __device__ __forceinline__ Fmt fmt_of(const DevFormat& F, const uint32_t* dtab, 
   f.buf = as_global(F.buf);
   f.pop_lut = F.pop_lut;
   f.dtab = dtab;
+  f.rtab = reinterpret_cast<const uint64_t*>(dtab + HVF_MAX_DEPTH);
   f.ext[0] = F.ext[0];
   f.ext[1] = F.ext[1];
   f.ext[2] = F.ext[2];
@@ -224,6 +242,7 @@ struct Walk {
   uint32_t info;  // descriptor of depth d
   uint32_t base, valid;
   uint32_t steps;
+  uint64_t rb;  // start of depth d's region (buffers with per-depth regions; else unused)
   // Distance-field skipping at the current depth: every cell whose L1 distance (in cells
   // of this depth) from the anchor cell a[] is below reach is known to be empty. The
   // anchor is the last empty cell read; any change of depth clears reach. Along a ray
@@ -235,7 +254,8 @@ struct Walk {
   // Enter the node at pointer ptr whose depth descriptor is nd: returns its header
   // (base, valid). m: the 64-bit block mask the parent's test read (used by HK_MASK).
   template <uint32_t FAM, class Mem>
-  __device__ __forceinline__ static uint2 enter(const Fmt& F, uint32_t nd, uint32_t ptr, uint2 m, Mem& mem) {
+  __device__ __forceinline__ static uint2 enter(const Fmt& F, uint32_t nd, uint32_t ptr, uint2 m, uint64_t rb,
+                                                Mem& mem) {
     const uint32_t hk = di_hk(nd);
     constexpr uint32_t LOADS = fam_hk(HK_DAG) | fam_hk(HK_SVO) | fam_hk(HK_MASKLOAD);
     // One 8-byte load serves every header kind read at the pointer: an SVDAG node's mask
@@ -244,8 +264,8 @@ struct Walk {
     uint2 h = make_uint2(0u, 0u);
     constexpr uint32_t LOAD_KINDS = (1u << HK_DAG) | (1u << HK_SVO) | (1u << HK_MASKLOAD);
     if ((FAM & LOADS) && ((LOAD_KINDS >> hk) & 1u)) {
-      h = F.template w2<FAM>(ptr);
-      mem.note(ptr, hk == HK_DAG ? 1u : 2u);
+      h = F.template w2<FAM>(gx<FAM>(ptr, rb));
+      mem.note((uint32_t)gx<FAM>(ptr, rb), hk == HK_DAG ? 1u : 2u);
     }
     uint32_t b = h.x, v = h.y;  // HK_MASKLOAD
     if (FAM & fam_hk(HK_SVO)) v = (hk == HK_SVO) ? (h.y & 0xFFu) : v;
@@ -269,18 +289,18 @@ struct Walk {
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ static void octree_child(const Fmt& F, uint32_t nk, uint32_t lin,
                                                       uint32_t base, uint32_t valid, uint32_t& child, uint2& cm,
-                                                      Mem& mem) {
+                                                      uint64_t rb, Mem& mem) {
     const uint32_t rank = __popc(valid & ((1u << lin) - 1u));
     if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) {
       child = base + 2u * rank;
     } else if ((FAM & fam_nk(NK_DAG_INNER)) && nk == NK_DAG_INNER) {
-      const uint2 dsc = F.template w2<FAM>(base + 2u * rank);  // (child pointer, child masks)
-      mem.note(base + 2u * rank, 2);
+      const uint2 dsc = F.template w2<FAM>(gx<FAM>(base + 2u * rank, rb));  // (child pointer, child masks)
+      mem.note((uint32_t)gx<FAM>(base + 2u * rank, rb), 2);
       child = dsc.x;
       cm = make_uint2(dsc.x + 1u, dsc.y & 0xFFu);
     } else {
-      child = F.template w1<FAM>(base + rank);
-      mem.note(base + rank, 1);
+      child = F.template w1<FAM>(gx<FAM>(base + rank, rb));
+      mem.note((uint32_t)gx<FAM>(base + rank, rb), 1);
     }
   }
 
@@ -315,11 +335,12 @@ struct Walk {
   template <uint32_t FAM, class Mem>
   __device__ __forceinline__ int start(const Fmt& F, Mem& mem) {
     const uint32_t* dtab = F.dtab;
-    const uint32_t root = F.template w1<FAM>(0);  // word 0: pointer to the root sub-volume; 0 = empty
+    const uint32_t root = F.template w1<FAM>(0u);  // word 0: pointer to the root sub-volume; 0 = empty
     mem.note(0, 1);
     if (root == 0u) return DONE;
     d = 0;
     info = dtab[0];
+    rb = (FAM & FAM_REGIONS) ? F.rtab[0] : 0ull;
     const int cs = di_cs(info);
 #pragma unroll
     for (int a = 0; a < 3; ++a) p[a] = 0;
@@ -333,7 +354,7 @@ struct Walk {
         p[a] = up ? mid : p[a];
       }
     }
-    const uint2 h = enter<FAM>(F, info, root, make_uint2(0u, 0u), mem);
+    const uint2 h = enter<FAM>(F, info, root, make_uint2(0u, 0u), rb, mem);
     base = h.x;
     valid = h.y;
     t = R.t0;
@@ -372,19 +393,19 @@ struct Walk {
       if (l1 >= reach) {  // not known to be empty: read the cell
         uint32_t dist;
         if ((FAM & fam_nk(NK_DF_PTR)) && nk == NK_DF_PTR) {
-          child = F.template w1<FAM>(base + lin);
-          mem.note(base + lin, 1);
+          child = F.template w1<FAM>(gx<FAM>(base + lin, rb));
+          mem.note((uint32_t)gx<FAM>(base + lin, rb), 1);
           occ = (child & DF_EMPTY) == 0u;
           dist = child & ~DF_EMPTY;
         } else if ((FAM & (fam_nk(NK_PDF_PTR) | fam_nk(NK_PDF_VOX))) && (nk == NK_PDF_PTR || nk == NK_PDF_VOX)) {
-          const uint2 q = F.template w2<FAM>(base + 2u * lin);  // (terminating integer, distance)
-          mem.note(base + 2u * lin, 2);
+          const uint2 q = F.template w2<FAM>(gx<FAM>(base + 2u * lin, rb));  // (terminating integer, distance)
+          mem.note((uint32_t)gx<FAM>(base + 2u * lin, rb), 2);
           child = q.x;
           occ = q.x != 0u;
           dist = q.y;
         } else {
-          const uint4 q = F.template w4<FAM>(base + 4u * lin);
-          mem.note(base + 4u * lin, 4);
+          const uint4 q = F.template w4<FAM>(gx<FAM>(base + 4u * lin, rb));
+          mem.note((uint32_t)gx<FAM>(base + 4u * lin, rb), 4);
           cm = make_uint2(q.x, q.y);
           occ = (q.x | q.y) != 0u;
           dist = q.z;
@@ -413,8 +434,8 @@ struct Walk {
       const uint32_t idx = rawk ? lin : (blk ? 2u * lin : (dagi ? 2u * rank : rank));
       uint2 q = make_uint2(0u, 0u);
       if (rawk || blk || ((optr || dagi) && occ)) {
-        q = F.template w2<FAM>(base + idx);
-        mem.note(base + idx, (blk || (FAM & fam_nk(NK_DAG_INNER) && nk == NK_DAG_INNER)) ? 2u : 1u);
+        q = F.template w2<FAM>(gx<FAM>(base + idx, rb));
+        mem.note((uint32_t)gx<FAM>(base + idx, rb), (blk || (FAM & fam_nk(NK_DAG_INNER) && nk == NK_DAG_INNER)) ? 2u : 1u);
       }
       // The far-plane times below do not depend on the read: computing them before its
       // first use lets the load's latency overlap them. The empty asm statement takes them
@@ -427,8 +448,8 @@ struct Walk {
       if (blk) occ = (cm.x | cm.y) != 0u;
       if ((FAM & fam_nk(NK_SVO_INNER)) && nk == NK_SVO_INNER) child = base + 2u * rank;
       if ((FAM & fam_nk(NK_PDAG_TERM)) && nk == NK_PDAG_TERM && occ) {  // the leaf word holds the pointer
-        child = F.template w1<FAM>(child);
-        mem.note(q.x, 1);
+        child = F.template w1<FAM>(gx<FAM>(child, rb));
+        mem.note((uint32_t)gx<FAM>(q.x, rb), 1);
       }
     }
     const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL) ||
@@ -441,7 +462,8 @@ struct Walk {
       ++d;
       reach = 0;
       info = dtab[d];
-      const uint2 h = enter<FAM>(F, info, child, cm, mem);
+      if (FAM & FAM_REGIONS) rb = F.rtab[d];
+      const uint2 h = enter<FAM>(F, info, child, cm, rb, mem);
       base = h.x;
       valid = h.y;
       refine3(R, p, cs, di_cs(info), t);
@@ -520,6 +542,7 @@ struct Walk {
       base = sv.x;
       valid = sv.y;
       info = dtab[nd];
+      if (FAM & FAM_REGIONS) rb = F.rtab[nd];
       d = nd;
       reach = 0;
       const int mask = ~((1 << di_cs(info)) - 1);
@@ -533,24 +556,26 @@ struct Walk {
     base = sv.x;
     valid = sv.y;
     info = dtab[r];
+    if (FAM & FAM_REGIONS) rb = F.rtab[r];
     for (int k = r; k < nd; ++k) {
       const uint32_t knk = di_nk(info), kl = cell_lin<FAM>(info);
       uint32_t child = 0u;
       uint2 cm = make_uint2(0u, 0u);
       if (((FAM & fam_nk(NK_RAW_PTR)) && knk == NK_RAW_PTR) || ((FAM & fam_nk(NK_DF_PTR)) && knk == NK_DF_PTR)) {
-        child = F.template w1<FAM>(base + kl);  // an ancestor cell: non-empty, so a plain pointer
-        mem.note(base + kl, 1);
+        child = F.template w1<FAM>(gx<FAM>(base + kl, rb));  // an ancestor cell: non-empty, so a plain pointer
+        mem.note((uint32_t)gx<FAM>(base + kl, rb), 1);
       } else if ((FAM & fam_nk(NK_BLOCKS)) && knk == NK_BLOCKS) {
-        cm = F.template w2<FAM>(base + 2u * kl);
-        mem.note(base + 2u * kl, 2);
+        cm = F.template w2<FAM>(gx<FAM>(base + 2u * kl, rb));
+        mem.note((uint32_t)gx<FAM>(base + 2u * kl, rb), 2);
       } else if ((FAM & fam_nk(NK_DF_BLOCKS)) && knk == NK_DF_BLOCKS) {
-        cm = F.template w2<FAM>(base + 4u * kl);
-        mem.note(base + 4u * kl, 2);
+        cm = F.template w2<FAM>(gx<FAM>(base + 4u * kl, rb));
+        mem.note((uint32_t)gx<FAM>(base + 4u * kl, rb), 2);
       } else {
-        octree_child<FAM>(F, knk, kl, base, valid, child, cm, mem);
+        octree_child<FAM>(F, knk, kl, base, valid, child, cm, rb, mem);
       }
       info = dtab[k + 1];
-      const uint2 h = enter<FAM>(F, info, child, cm, mem);
+      if (FAM & FAM_REGIONS) rb = F.rtab[k + 1];
+      const uint2 h = enter<FAM>(F, info, child, cm, rb, mem);
       base = h.x;
       valid = h.y;
     }
@@ -576,7 +601,10 @@ __device__ __forceinline__ const uint32_t* stage_prefix(const DevFormat& F, uint
 }
 
 __device__ __forceinline__ void load_dtab(const DevFormat& F, uint32_t* dtab) {
-  if (threadIdx.x < HVF_MAX_DEPTH) dtab[threadIdx.x] = F.dinfo[threadIdx.x];
+  if (threadIdx.x < HVF_MAX_DEPTH) {
+    dtab[threadIdx.x] = F.dinfo[threadIdx.x];
+    reinterpret_cast<uint64_t*>(dtab + HVF_MAX_DEPTH)[threadIdx.x] = F.rbase[threadIdx.x];
+  }
   __syncthreads();
 }
 
@@ -642,7 +670,7 @@ __device__ __forceinline__ void push_survivor(bool cut, uint32_t i, float rest, 
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                       int4* __restrict__ hits, uint32_t n) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -660,7 +688,7 @@ template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_budget_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                              int4* __restrict__ hits, uint32_t n, uint32_t budget,
                                                              uint2* __restrict__ surv, uint32_t* __restrict__ nsurv) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -734,7 +762,7 @@ template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_split_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, const uint2* __restrict__ surv,
                                                             const uint32_t* __restrict__ nsurv, uint32_t klog2) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -797,7 +825,7 @@ __global__ __launch_bounds__(BLOCK) void trace_resume_kernel(const DevFormat F, 
                                                              int4* __restrict__ hits, const uint2* __restrict__ in,
                                                              const uint32_t* __restrict__ nin, uint32_t budget,
                                                              uint2* __restrict__ out, uint32_t* __restrict__ nout) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -861,7 +889,7 @@ __global__ __launch_bounds__(BLOCK) void trace_persistent_kernel(const DevFormat
                                                                  int4* __restrict__ hits, uint32_t n,
                                                                  uint32_t* __restrict__ counter, uint32_t refill,
                                                                  uint32_t inner) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -1060,7 +1088,7 @@ template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n, uint32_t period,
                                                             float minlen, uint32_t min_idle) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
@@ -1081,7 +1109,7 @@ __global__ __launch_bounds__(BLOCK) void trace_indexed_kernel(const DevFormat F,
                                                               int4* __restrict__ hits, uint32_t n,
                                                               const uint32_t* __restrict__ perm,
                                                               const uint32_t* __restrict__ key) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -1166,6 +1194,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
   fm.buf = nullptr;
   fm.pop_lut = 0;
   fm.dtab = dt;
+  fm.rtab = nullptr;  // batches hold no volume with per-depth regions
   fm.ext[0] = fm.ext[1] = fm.ext[2] = 0;
   fm.stacked = 1u;
   fm.pre = nullptr;
@@ -1233,7 +1262,7 @@ __global__ __launch_bounds__(BLOCK) void trace_count_kernel(const DevFormat F, c
                                                             uint32_t* __restrict__ log, uint32_t cap,
                                                             uint32_t* __restrict__ count,
                                                             uint32_t* __restrict__ nsteps) {
-  __shared__ uint32_t dtab[HVF_MAX_DEPTH];
+  __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
@@ -1284,6 +1313,7 @@ size_t stack_lds_bytes(const DevFormat& F) {
     case 8: LAUNCH(FAM_OCT_BRICK); break;    \
     case 9: LAUNCH(FAM_NODF); break;         \
     case 10: LAUNCH(FAM_PAPER); break;       \
+    case 12: LAUNCH(FAM_ALL | FAM_REGIONS); break; \
     default: LAUNCH(FAM_ALL); break;         \
   }
 
@@ -1585,6 +1615,10 @@ hvf_status launch_trace_count(const DevFormat& F, bool paper, const hvf_ray* d_r
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
   if (paper)
     hipLaunchKernelGGL(trace_count_kernel<FAM_PAPER>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
+                       reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log,
+                       cap, d_count, d_steps);
+  else if (F.regions)
+    hipLaunchKernelGGL(trace_count_kernel<FAM_ALL | FAM_REGIONS>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F,
                        reinterpret_cast<const float4*>(d_rays), reinterpret_cast<int4*>(d_hits), (uint32_t)n, d_log,
                        cap, d_count, d_steps);
   else

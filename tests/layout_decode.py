@@ -34,20 +34,29 @@ def _depths(info):
 
 
 def decode(info, words):
-    """Return the sorted list of occupied voxels (x, y, z)."""
+    """Return the sorted list of occupied voxels (x, y, z). With per-depth regions
+    (info["depth_buffers"]) every pointer is relative to the start of the region of the
+    depth it points into: the next depth's, or for an SVO node's pointer array its own."""
     W = [int(v) for v in words] if len(words) < 200000 else words
     D, nlev = _depths(info)
     out = []
+    regions = info.get("depth_buffers", False)
+
+    def rb(d):  # pointers count from 16 words before their region (0 stays the empty marker)
+        return info["depth_offset"][d] - 16 if regions and d < len(D) else 0
+
     root = int(W[0])
     if root == 0:
         return out
+    root += rb(0)
 
     def enter(d, ptr):
         k, kind, j, L, cs, w = D[d]
         if kind in ("R", "B", "D", "E"):
             return ptr, 0xFF
         if kind == "S":
-            return int(W[ptr]), int(W[ptr + 1]) & 0xFF
+            deepest_above = j == L - 1 and k < nlev - 1  # its pointer array lies in its own region
+            return int(W[ptr]) + (rb(d) if deepest_above else rb(d + 1)), int(W[ptr + 1]) & 0xFF
         return ptr + 1, int(W[ptr]) & 0xFF
 
     def walk(d, ptr, corner):
@@ -78,7 +87,7 @@ def decode(info, words):
                     continue  # empty DF cell: the low bits hold its distance
                 if p:
                     cx, cy, cz = idx & ((1 << wx) - 1), (idx >> wx) & ((1 << wy) - 1), idx >> (wx + wy)
-                    walk(d + 1, p, (corner[0] + (cx << cs), corner[1] + (cy << cs), corner[2] + (cz << cs)))
+                    walk(d + 1, p + rb(d + 1), (corner[0] + (cx << cs), corner[1] + (cy << cs), corner[2] + (cz << cs)))
             return
         deepest = (j == L - 1)
         for o in range(8):
@@ -92,11 +101,11 @@ def decode(info, words):
                 walk(d + 1, base + 2 * rank, c)
             elif kind == "G" and not deepest:
                 # descriptor: (child pointer, copy of the child's mask word)
-                child = int(W[base + 2 * rank])
+                child = int(W[base + 2 * rank]) + rb(d + 1)
                 assert int(W[base + 2 * rank + 1]) == int(W[child]), "descriptor mask differs from the child's"
                 walk(d + 1, child, c)
             else:
-                walk(d + 1, int(W[base + rank]), c)
+                walk(d + 1, int(W[base + rank]) + rb(d + 1), c)
 
     walk(0, root, (0, 0, 0))
     out.sort(key=lambda v: (v[2], v[1], v[0]))
@@ -111,9 +120,12 @@ def df_grids(info, words):
     W = [int(v) for v in words] if len(words) < 200000 else words
     D, nlev = _depths(info)
     grids = []
+    regions = info.get("depth_buffers", False)
     root = int(W[0])
     if root == 0:
         return grids
+    rb = (lambda d: info["depth_offset"][d] - 16 if regions and d < len(D) else 0)
+    root += rb(0)
 
     def cells(d, ptr):
         k, kind, j, L, cs, w = D[d]
@@ -129,7 +141,7 @@ def df_grids(info, words):
                 kids = [int(v) for v in vals if v]
             if d + 1 < len(D) and D[d + 1][1] in ("R", "D", "B", "E"):
                 for c in kids:
-                    cells(d + 1, c)
+                    cells(d + 1, c + rb(d + 1))
             elif d + 1 < len(D):
                 # octree below: DF grids deeper than an octree are not listed
                 pass

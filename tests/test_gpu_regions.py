@@ -1,0 +1,116 @@
+"""Buffers with per-depth regions (the paper's multiple buffers with indirection, Sec. 3.3):
+each depth's nodes in their own region, pointers relative to the region they point into,
+so a format may pass 2^32 words.
+
+* Small volumes built with --depth-buffers trace bit for bit like the single-buffer layout
+  under every schedule, and read the very same words (the counting kernel's logs match:
+  nodes sit at the same places, only pointer values differ).
+* A volume past 2^32 words (R(3,4,4) R(7,7,7) R(5,5,5) over 32768 x 65536 x 65536: a
+  depth of pointer grids just below 2^32 words and a depth of bricks, 4.31 G words in all)
+  builds, uploads and traces at parity with the oracle, which traces the same voxels built
+  as R(3,4,4) G(12) (every format of one volume has the same first hits, pinned on the CPU).
+* Batches, the server and device construction refuse such volumes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2410_14128_amd as H
+    H.lib()
+    return H
+
+
+SCHEDS = [dict(), dict(steal=1, steal_len=2, steal_idle=16), dict(steal=2, steal_len=1), dict(split=8, split_budget=4),
+          dict(split=64, split_budget=2, split_rounds=2), dict(persistent=1, refill=8, inner=4), dict(sort=1, sort_bits=3),
+          dict(lds_depths=2), dict(stack_depth=2)]
+
+
+@pytest.mark.parametrize("spec", ["G(4) R(3,3,3) --whole-level-dedup", "S(3) R(4,4,4)", "R(2,2,2) S(2) G(3)",
+                                  "D(3,3,3,6) R(2,2,2) R(2,2,2)", "S(2) G(2) R(3,3,3) --restart-sv", "R(3,3,3) R(4,4,4)"])
+def test_regions_trace_like_one_buffer(H, spec):
+    import torch
+    codes = W.scene_shell(12, 7, 8, 4, 1.4)
+    rays = np.concatenate([W.random_rays(12, (128,) * 3, 20000), W.camera_rays(12, 0, (128,) * 3, 160, 120)])
+    one, reg = H.Volume(spec, codes), H.Volume(spec + " --depth-buffers", codes)
+    assert reg.info()["depth_buffers"]
+    d = torch.from_numpy(rays).cuda()
+    want = one.trace(d, sched=H.schedule())
+    for sd in SCHEDS:
+        try:
+            got = reg.trace(d, sched=H.schedule(**sd))
+        except H.HvfError as e:  # a staged prefix larger than the LDS limit is refused
+            assert "lds_depths" in sd and e.name == "HVF_E_INPUT"
+            continue
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), f"{spec} {sd}"
+    idx = np.arange(0, len(rays), 11)
+    assert compare(want.cpu().numpy()[idx], oracle.Volume(spec.replace(" --restart-sv", ""), codes)
+                   .trace(rays[idx], nthreads=8), spec) == 0
+    small = torch.from_numpy(rays[:3000]).cuda()
+    h1, l1, c1 = one.trace_count(small, cap=512)
+    h2, l2, c2 = reg.trace_count(small, cap=512)
+    torch.cuda.synchronize()
+    assert torch.equal(h1, h2) and torch.equal(c1, c2)
+    mask = torch.arange(512, device="cuda")[None, :] < c1[:, None]
+    assert torch.equal(torch.where(mask, l1, 0), torch.where(mask, l2, 0))
+
+
+def test_regions_refused_by_batches_server_and_device_build(H):
+    import torch
+    codes = W.scene_shell(12, 6, 6, 2, 1.4)
+    v = H.Volume("G(3) R(3,3,3) --depth-buffers", codes)
+    d = torch.from_numpy(W.random_rays(1, (64,) * 3, 100)).cuda()
+    for make in (lambda: H.Batch([v], [d]), lambda: H.Server(1 << 20).add_volume(v),
+                 lambda: H.Volume.from_device("G(3) R(3,3,3) --depth-buffers",
+                                              torch.from_numpy(codes.view(np.int64)).cuda())):
+        with pytest.raises(H.HvfError) as e:
+            make()
+        assert e.value.name == "HVF_E_UNSUPPORTED"
+
+
+def test_volume_past_2_32_words(H):
+    import torch
+    rng = np.random.default_rng(2032)
+    # R(3,4,4) R(7,7,7) R(5,5,5) over 32768 x 65536 x 65536: 2,047 of the 2,048 top cells
+    # hold ten random voxels each, so the depth of 128^3-cell pointer grids takes
+    # 2,047 x 2^21 words (just below 2^32) and the bricks 20,470 x 1,024 more.
+    top = np.array([(x, y, z) for z in range(16) for y in range(16) for x in range(8) if (x, y, z) != (7, 15, 15)])
+    xyz = (np.repeat(top, 10, axis=0) << 12) + rng.integers(0, 1 << 12, size=(len(top) * 10, 3))
+    codes = np.unique(W.morton_encode(xyz.astype(np.int32)))
+    spec = "R(3,4,4) R(7,7,7) R(5,5,5)"
+    print(f"building {spec} over {len(codes)} voxels", flush=True)
+    v = H.Volume(spec, codes)
+    info = v.info()
+    print(f"built: {info['num_words']} words, depth offsets {info['depth_offset'][:info['num_depths']]}", flush=True)
+    assert info["depth_buffers"] and info["num_words"] > (1 << 32) and info["extent_log2"] == (15, 16, 16)
+    v.upload()
+    # rays aimed at occupied voxels from random points of the volume, and random rays
+    ext = (1 << 15, 1 << 16, 1 << 16)
+    tgt = W.morton_decode(codes[rng.choice(len(codes), 3000, replace=False)]).astype(np.float64) + 0.5
+    org = rng.uniform(0, 1, size=(3000, 3)) * np.array(ext)
+    dirs = tgt - org
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    aimed = np.zeros((3000, 8), np.float32)
+    aimed[:, 0:3], aimed[:, 4:7], aimed[:, 7] = org, dirs, np.inf
+    rays = np.ascontiguousarray(np.concatenate([aimed, W.random_rays(2032, ext, 3000)]))
+    d = torch.from_numpy(rays).cuda()
+    got = v.trace(d, sched=H.schedule())
+    stolen = v.trace(d, sched=H.schedule(steal=1, steal_len=2, steal_idle=16))
+    torch.cuda.synchronize()
+    assert torch.equal(got, stolen)
+    got = got.cpu().numpy()
+    assert (got[:3000, 0] >= 0).mean() > 0.5
+    v.close()
+    del v
+    ref = oracle.Volume("R(3,4,4) G(12)", codes).trace(rays, nthreads=8)
+    assert compare(got, ref, "past 2^32 words") == 0

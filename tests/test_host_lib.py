@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests import layout_decode as LD
 from tests.layout_decode import decode_codes, df_grids
 
 H = pytest.importorskip("paper_2410_14128_amd")
@@ -161,7 +162,36 @@ def _fnv64(data: bytes, h: int = 1469598103934665603) -> int:
     return h
 
 
+@pytest.mark.parametrize("spec", SPECS + ["S(2) G(2) R(2,2,2) --restart-sv", "R(2,2,2) S(3) G(1) --wld"])
+def test_depth_buffers_are_lossless(spec, tmp_path):
+    """--depth-buffers (per-depth regions with region-relative pointers, what the builder
+    picks past 2^32 words) keeps every node where the single-buffer layout puts it and only
+    changes pointer values: decoding gives the input occupancy, the depth offsets and node
+    counts are unchanged, and a saved file loads (with its pointers validated)."""
+    codes = W.scene_solid_noise(4) if H.Volume(spec, np.zeros(0, np.uint64)).info()["extent_log2"] == (6, 6, 6) \
+        else W.scene_bernoulli(4, *H.Volume(spec, np.zeros(0, np.uint64)).info()["extent_log2"], 0.08)
+    a, b = H.Volume(spec, codes), H.Volume(spec + " --depth-buffers", codes)
+    ia, ib = a.info(), b.info()
+    assert ib["depth_buffers"] and not ia["depth_buffers"]
+    for k in ("num_words", "depth_offset", "depth_nodes", "level_nodes", "num_voxels"):
+        assert ia[k] == ib[k], k
+    assert np.array_equal(LD.decode_codes(ib, b.words(), W.morton_encode), codes)
+    wa, wb = a.words(), b.words()
+    assert np.array_equal(wa == 0, wb == 0)  # the same words are empty, only pointer values move
+    p = str(tmp_path / "r.hvf")
+    b.save(p)
+    u = H.Volume.load(p)
+    assert u.info() == ib and np.array_equal(u.words(), wb)
+
+
+def test_depth_buffers_refusals():
+    with pytest.raises(H.HvfError) as e:
+        H.Volume("G(3) R(2,2,2) --paper-layout --depth-buffers", np.zeros(0, np.uint64))
+    assert e.value.name == "HVF_E_UNSUPPORTED"
+
+
 @pytest.mark.parametrize("spec", ["G(3) R(3,3,3) --whole-level-dedup", "R(2,2,2) S(2) R(2,2,2)",
+                                  "G(3) R(3,3,3) --whole-level-dedup --depth-buffers", "S(3) R(3,3,3) --depth-buffers",
                                   "D(3,3,3,4) S(3)", "S(2) G(2) R(2,2,2) --paper-layout",
                                   "R(3,3,3) G(3) --paper-layout", "D(2,2,2,3) R(4,4,4) --paper-layout"])
 def test_load_rejects_pointers_past_the_buffer(tmp_path, spec):
