@@ -52,6 +52,8 @@ def lib():
         L.orc_num_words.restype = i64
         L.orc_num_words.argtypes = [vp]
         L.orc_copy_words.argtypes = [vp, vp]
+        L.orc_split_buffers.restype = i32
+        L.orc_split_buffers.argtypes = [vp]
         L.orc_num_levels.restype = i32
         L.orc_num_levels.argtypes = [vp]
         L.orc_node_counts.argtypes = [vp, vp]
@@ -105,6 +107,10 @@ class Volume:
     @property
     def num_words(self) -> int:
         return int(lib().orc_num_words(self._h))
+
+    def split_buffers(self) -> bool:
+        """One buffer per level (--depth-buffers, or past 2^32 words)."""
+        return bool(lib().orc_split_buffers(self._h))
 
     def words(self) -> np.ndarray:
         out = np.empty(self.num_words, dtype=np.uint32)

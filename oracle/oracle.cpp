@@ -26,6 +26,12 @@
 //     DF levels walk the same DDA but do not check occupancy while the walk stays within
 //     the stored distance of the last empty cell they read (Sec. 4.2); SVO/SVDAG levels
 //     recurse over octants in entry-time order.
+//   * buffers: the paper caps a format at 2^32 words and notes that several buffers with
+//     indirection would lift the cap (Sec. 3.3). Past 2^32 words (or with --depth-buffers)
+//     each level gets a buffer of its own: a level's node words and in-level pointers live
+//     in its buffer, and the terminating integers of its cells and leaves point into the
+//     next level's buffer (word 0 of every buffer is reserved, so no pointer is 0, the
+//     empty marker). Word 0 of the format, the root pointer, points into level 0's buffer.
 //   * flat_dda: the same first-hit query on a dense occupancy bitset (a single Raw level).
 //   * brute: the plain definition -- among all occupied voxels, the visited one with the
 //     smallest entry time.
@@ -59,6 +65,7 @@ struct Level {
 struct Format {
   std::vector<Level> lv;
   bool wld = false;
+  bool split = false;  // one buffer per level (--depth-buffers; also chosen past 2^32 words)
   std::vector<int> sub;  // sub[k]: log2 side of a level-k sub-volume per axis (k >= 1 cubic)
   int ext[3] = {0, 0, 0};
 };
@@ -95,6 +102,8 @@ bool parse_spec(const char* spec, Format& f) {
         f.wld = true;
       else if (flag == "--restart-sv" || flag == "-restart-sv")
         ;  // restarting intersection (Sec. 4.3) changes how a tracer revisits nodes, not the result
+      else if (flag == "--depth-buffers")
+        f.split = true;
       else {
         g_err = "unknown flag " + flag;
         return false;
@@ -216,9 +225,12 @@ using DedupMap = std::unordered_map<std::vector<uint32_t>, uint32_t, VecHash>;
 
 struct Volume {
   Format f;
-  std::vector<uint32_t> words;
+  std::vector<uint32_t> words;               // one buffer; with split buffers only word 0
+  std::vector<std::vector<uint32_t>> level;  // split buffers: level k's buffer
   std::vector<int64_t> node_count;  // per level: nodes / arrays written
   bool overflow = false;
+  // The buffer that pointers into level k index.
+  const std::vector<uint32_t>& buf(int k) const { return f.split ? level[(size_t)k] : words; }
 };
 
 struct Builder {
@@ -229,13 +241,15 @@ struct Builder {
 
   Builder(Volume& v, const uint64_t* c, size_t nn) : V(v), codes(c), n(nn) { level_maps.resize(v.f.lv.size()); }
 
-  uint32_t write(const std::vector<uint32_t>& data) {
-    uint64_t p = V.words.size();
+  // Append words of level k; returns their index in the buffer pointers into level k use.
+  uint32_t write(int k, const std::vector<uint32_t>& data) {
+    std::vector<uint32_t>& B = V.f.split ? V.level[(size_t)k] : V.words;
+    uint64_t p = B.size();
     if (p + data.size() >= (1ull << 32)) {
       V.overflow = true;
       return 0;
     }
-    V.words.insert(V.words.end(), data.begin(), data.end());
+    B.insert(B.end(), data.begin(), data.end());
     return (uint32_t)p;
   }
 
@@ -258,7 +272,7 @@ struct Builder {
     std::vector<uint32_t> sub = construct(k + 1, x, y, z, lo, hi, empty);
     if (empty) return 0u;
     if (V.f.lv[k + 1].kind != 'R') V.node_count[k + 1] += 1;  // the sub-volume's root node
-    return write(sub);
+    return write(k + 1, sub);
   }
 
   std::vector<uint32_t> construct(int k, uint64_t x, uint64_t y, uint64_t z, size_t lo, size_t hi, bool& empty) {
@@ -361,7 +375,7 @@ struct Builder {
       // Children are laid out contiguously, two words each.
       std::vector<uint32_t> block;
       for (auto& c : kids) block.insert(block.end(), c.begin(), c.end());
-      uint32_t first = write(block);
+      uint32_t first = write(k, block);
       V.node_count[k] += (int64_t)kids.size();
       return {first, masks};
     }
@@ -372,7 +386,7 @@ struct Builder {
       if (it != map.end()) {
         p = it->second;
       } else {
-        p = write(c);
+        p = write(k, c);
         map.emplace(c, p);
         V.node_count[k] += 1;
       }
@@ -383,11 +397,12 @@ struct Builder {
 
   void build_root() {
     V.words.assign(1, 0u);  // word 0: root pointer
+    V.level.assign(V.f.split ? V.f.lv.size() : 0, std::vector<uint32_t>(1, 0u));  // word 0 of each: reserved
     V.node_count.assign(V.f.lv.size(), 0);
     bool empty;
     std::vector<uint32_t> root = construct(0, 0, 0, 0, 0, n, empty);
     if (!empty) {
-      uint32_t p = write(root);
+      uint32_t p = write(0, root);
       V.words[0] = p;
       if (V.f.lv[0].kind != 'R') V.node_count[0] += 1;
     }
@@ -537,9 +552,9 @@ struct Tracer {
       float e, x;
       if (!known_empty && interval(c, clo, cs, te, tx, e, x) && e < x) {
         const size_t at = (size_t)p + stride * (size_t)(cell[0] + n[0] * (cell[1] + n[1] * cell[2]));
-        uint32_t term = V.words[at];
+        uint32_t term = V.buf(k)[at];
         if (df && term == 0) {  // march up to this many cells before checking again
-          reach = V.words[at + 1];
+          reach = V.buf(k)[at + 1];
           for (int a = 0; a < 3; ++a) anchor[a] = cell[a];
         }
         if (visit_child(k, term, clo, e, x, h)) return true;
@@ -571,7 +586,8 @@ struct Tracer {
     int cs = V.f.sub[k + 1];
     int D = L.e[0];
     int half = cs + (D - j - 1);
-    uint32_t masks = (L.kind == 'S') ? V.words[p + 1] : V.words[p];
+    const std::vector<uint32_t>& W = V.buf(k);
+    uint32_t masks = (L.kind == 'S') ? W[p + 1] : W[p];
     uint32_t valid = masks & 0xFF;
     struct Cand {
       float e, x;
@@ -594,11 +610,11 @@ struct Tracer {
       uint32_t rank = (uint32_t)__builtin_popcount(valid & ((1u << o) - 1u));
       uint32_t childp;  // address of the child node
       if (L.kind == 'S')
-        childp = V.words[p] + 2 * rank;
+        childp = W[p] + 2 * rank;
       else
-        childp = V.words[p + 1 + rank];
+        childp = W[p + 1 + rank];
       if (j + 1 == D) {
-        uint32_t term = V.words[childp];  // leaf node: its first word is the terminating integer
+        uint32_t term = W[childp];  // leaf node: its first word is the terminating integer
         if (visit_child(k, term, clo, cd.e, cd.x, h)) return true;
       } else {
         if (octree(k, j + 1, childp, clo, cd.e, cd.x, h)) return true;
@@ -634,7 +650,7 @@ struct Decoder {
       for (int64_t z = 0; z < n[2]; ++z)
         for (int64_t y = 0; y < n[1]; ++y)
           for (int64_t x = 0; x < n[0]; ++x) {
-            uint32_t t = V.words[(size_t)p + stride * (size_t)(x + n[0] * (y + n[1] * z))];
+            uint32_t t = V.buf(k)[(size_t)p + stride * (size_t)(x + n[0] * (y + n[1] * z))];
             int64_t clo[3] = {lo[0] + (x << cs), lo[1] + (y << cs), lo[2] + (z << cs)};
             term(k, t, clo);
           }
@@ -654,15 +670,16 @@ struct Decoder {
     int cs = V.f.sub[k + 1];
     int D = L.e[0];
     int half = cs + (D - j - 1);
-    uint32_t valid = ((L.kind == 'S') ? V.words[p + 1] : V.words[p]) & 0xFF;
+    const std::vector<uint32_t>& W = V.buf(k);
+    uint32_t valid = ((L.kind == 'S') ? W[p + 1] : W[p]) & 0xFF;
     for (int o = 0; o < 8; ++o) {
       if (!((valid >> o) & 1)) continue;
       int64_t clo[3] = {lo[0] + ((int64_t)(o & 1) << half), lo[1] + ((int64_t)((o >> 1) & 1) << half),
                         lo[2] + ((int64_t)((o >> 2) & 1) << half)};
       uint32_t rank = (uint32_t)__builtin_popcount(valid & ((1u << o) - 1u));
-      uint32_t childp = (L.kind == 'S') ? V.words[p] + 2 * rank : V.words[p + 1 + rank];
+      uint32_t childp = (L.kind == 'S') ? W[p] + 2 * rank : W[p + 1 + rank];
       if (j + 1 == D)
-        term(k, V.words[childp], clo);
+        term(k, W[childp], clo);
       else
         node(k, j + 1, childp, clo);
     }
@@ -755,10 +772,20 @@ void* orc_build(const char* spec, const uint64_t* codes, int64_t n) {
   }
   auto* V = new Volume();
   V->f = f;
-  Builder b(*V, codes, (size_t)n);
-  b.build_root();
+  {
+    Builder b(*V, codes, (size_t)n);
+    b.build_root();
+  }
+  if (V->overflow && !V->f.split) {  // past 2^32 words: one buffer per level (Sec. 3.3)
+    delete V;
+    V = new Volume();
+    V->f = f;
+    V->f.split = true;
+    Builder b(*V, codes, (size_t)n);
+    b.build_root();
+  }
   if (V->overflow) {
-    g_err = "format exceeds 2^32 words";
+    g_err = "a level of this format exceeds 2^32 words";
     delete V;
     return nullptr;
   }
@@ -766,11 +793,23 @@ void* orc_build(const char* spec, const uint64_t* codes, int64_t n) {
 }
 
 void orc_free(void* h) { delete (Volume*)h; }
-int64_t orc_num_words(void* h) { return (int64_t)((Volume*)h)->words.size(); }
-void orc_copy_words(void* h, uint32_t* out) {
-  auto& w = ((Volume*)h)->words;
-  std::memcpy(out, w.data(), w.size() * 4);
+// Words of the format: word 0, then (split buffers) each level's buffer in level order.
+int64_t orc_num_words(void* h) {
+  const Volume& V = *(Volume*)h;
+  int64_t n = (int64_t)V.words.size();
+  for (auto& b : V.level) n += (int64_t)b.size();
+  return n;
 }
+void orc_copy_words(void* h, uint32_t* out) {
+  const Volume& V = *(Volume*)h;
+  std::memcpy(out, V.words.data(), V.words.size() * 4);
+  out += V.words.size();
+  for (auto& b : V.level) {
+    std::memcpy(out, b.data(), b.size() * 4);
+    out += b.size();
+  }
+}
+int orc_split_buffers(void* h) { return ((Volume*)h)->f.split ? 1 : 0; }
 int orc_num_levels(void* h) { return (int)((Volume*)h)->f.lv.size(); }
 void orc_node_counts(void* h, int64_t* out) {
   auto& v = ((Volume*)h)->node_count;

@@ -335,6 +335,26 @@ def test_every_format_matches_flat_dda(seed):
         assert np.array_equal(oracle.Volume(spec, codes).trace(rays), flat), spec
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_split_buffers_match_flat_dda(seed):
+    """One buffer per level (the oracle's answer past 2^32 words, forced here by
+    --depth-buffers): every type sequence of the 8^3 suite, and DF levels, give the flat
+    DDA's hits, decode losslessly, and hold the single buffer's words (each level's buffer
+    starts with a reserved word, so pointer values differ)."""
+    codes = W.scene_bernoulli(seed, 3, 3, 3, 0.06 * seed)
+    occ = dense_of([tuple(v) for v in W.morton_decode(codes)], (3, 3, 3))
+    rays = np.concatenate([W.random_rays(seed, (8, 8, 8), 400), W.camera_rays(seed, 0, (8, 8, 8), 24, 16),
+                           np.concatenate([r for r, _ in EDGE_CASES])])
+    flat = oracle.flat_dda(occ, (3, 3, 3), rays)
+    for spec in SPECS_8 + ["D(1,1,1,2) R(2,2,2)", "D(2,2,2,3) S(1)", "R(1,1,1) D(1,1,1,2) G(1)"]:
+        one, split = oracle.Volume(spec, codes), oracle.Volume(spec + " --depth-buffers", codes)
+        assert split.split_buffers() and not one.split_buffers()
+        assert np.array_equal(split.trace(rays), flat), spec
+        assert np.array_equal(split.decode(), codes), spec
+        nlev = len(spec.split(" --")[0].split())
+        assert split.num_words == one.num_words + nlev  # plus one reserved word per level
+
+
 def test_shell_scene_formats_agree():
     codes = W.scene_shell(4, 6, 8, 4, 1.4)
     occ = dense_of([tuple(v) for v in W.morton_decode(codes)], (6, 6, 6))
