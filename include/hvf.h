@@ -115,7 +115,12 @@ typedef struct hvf_info {
  *   continues the walk from e exactly as the walk would have, with a copy of its node
  *   stack, so no step is walked twice. A ray's result is its parts' hit of least t, kept
  *   per ray in LDS; parts behind a hit stop. Lanes past the last ray of a launch help too.
- *   This keeps lanes busy while a wave's longest walks finish. */
+ *   This keeps lanes busy while a wave's longest walks finish.
+ * interleave = 1 (needs persistent = 0, sort = 0 and split = 0): lane l of wave w of the
+ *   launch takes ray l * W + w, W = ceil(n / 64), so each wave holds rays from all over the
+ *   batch instead of 64 neighbours; hits are still written at each ray's index. This evens
+ *   out the work per wave when the walk lengths of neighbouring rays are correlated (the
+ *   secondary rays of one image), and costs coherent batches their locality. */
 typedef struct hvf_schedule {
   int32_t persistent;
   int32_t refill;
@@ -134,6 +139,7 @@ typedef struct hvf_schedule {
   int32_t steal;        /* 0, or P: see above */
   int32_t steal_len;    /* voxels; shorter rests are not forked (steal > 0) */
   int32_t steal_idle;   /* idle lanes a wave needs before it forks walks (steal > 0) */
+  int32_t interleave;   /* 0 or 1: see above */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).
@@ -227,7 +233,8 @@ hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
 /* Autotune: time candidate schedules (one lane per ray; short stacks of 2 and 4 depths;
  * persistent at full, 2 or 4 blocks per CU with refill thresholds 8/32 and 4 or 16 steps
  * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; five
- * stealing schedules), then the best with the deepest LDS prefixes that fit, on the
+ * stealing schedules; one lane per ray and the five stealing schedules again with
+ * interleaved rays), then the best with the deepest LDS prefixes that fit, on the
  * caller's device ray sample; pick the fastest, store it as the volume's schedule and copy
  * it to *out (may be NULL). d_hits_scratch: n device hits, overwritten. Synchronises
  * hip_stream. Results never depend on the schedule chosen. */

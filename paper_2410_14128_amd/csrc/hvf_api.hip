@@ -13,7 +13,7 @@
 
 namespace hvf {
 hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                        hipStream_t s);
+                        bool interleave, hipStream_t s);
 hvf_status launch_trace_count(const DevFormat& F, bool paper, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, uint32_t* d_log,
                               uint32_t cap, uint32_t* d_count, uint32_t* d_steps, hipStream_t s);
 hvf_status launch_trace_persistent(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
@@ -22,7 +22,7 @@ hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                               uint32_t budget, uint32_t klog2, uint32_t rounds, uint32_t* scratch, hipStream_t s);
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, uint32_t min_idle, hipStream_t s);
+                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, hipStream_t s);
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
@@ -134,12 +134,14 @@ hvf_status check_sched(const hvf_schedule& sc) {
       sc.lds_depths > HVF_MAX_DEPTH || sc.split < 0 || sc.split > 64 || (sc.split & (sc.split - 1)) != 0 ||
       sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))) || sc.split_rounds < 0 ||
       sc.split_rounds > (int)hvf::HVF_SPLIT_MAX_ROUNDS || (sc.split_rounds && !sc.split) || sc.steal < 0 ||
-      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20) || sc.steal_idle < 1 || sc.steal_idle > 64)))
+      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20) || sc.steal_idle < 1 || sc.steal_idle > 64)) || sc.interleave < 0 || sc.interleave > 1)
     return fail(HVF_E_INPUT, "schedule field out of range");
   if (sc.split && (sc.persistent || sc.sort))
     return fail(HVF_E_INPUT, "the split schedule runs without persistent lanes and without sorting");
   if (sc.steal && (sc.persistent || sc.sort || sc.split))
     return fail(HVF_E_INPUT, "the stealing schedule runs without persistent lanes, sorting or splitting");
+  if (sc.interleave && (sc.persistent || sc.sort || sc.split))
+    return fail(HVF_E_INPUT, "interleaved rays need one lane per ray: no persistent lanes, sorting or splitting");
   return HVF_OK;
 }
 }  // namespace
@@ -167,7 +169,7 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.steal)
     return hvf::launch_trace_steal(F, family, d_rays, n, d_hits, (uint32_t)sc.steal, (float)sc.steal_len,
-                                   (uint32_t)sc.steal_idle, s);
+                                   (uint32_t)sc.steal_idle, sc.interleave != 0, s);
   if (sc.split) {
     const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split),
                    rounds = (uint32_t)sc.split_rounds;
@@ -208,7 +210,7 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
     }
     counter = v->dcounters + 2 * (v->counter_next.fetch_add(1) % HVF_NUM_COUNTERS);
   }
-  if (!sc.persistent) return hvf::launch_trace(F, family, d_rays, n, d_hits, s);
+  if (!sc.persistent) return hvf::launch_trace(F, family, d_rays, n, d_hits, sc.interleave != 0, s);
   unsigned grid = 0;
   st = hvf::persistent_grid(F, sc.blocks_per_cu, &grid);
   if (st != HVF_OK) return st;
@@ -294,8 +296,11 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
   for (const auto& c : split_cand) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, c[0], c[1], c[2]});
   // Stealing: (period, length in voxels, idle lanes).
   const int steal_cand[][3] = {{1, 2, 16}, {2, 2, 8}, {2, 8, 1}, {4, 8, 1}, {1, 8, 32}};
-  for (const auto& c : steal_cand)
-    cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, c[0], c[1], c[2]});
+  for (int il : {0, 1}) {
+    if (il) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1});
+    for (const auto& c : steal_cand)
+      cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, c[0], c[1], c[2], il});
+  }
   hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");

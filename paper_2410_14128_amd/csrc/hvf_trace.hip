@@ -667,15 +667,24 @@ __device__ __forceinline__ void push_survivor(bool cut, uint32_t i, float rest, 
   surv[base + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull))] = make_uint2(i, __float_as_uint(rest));
 }
 
+// The ray of the lane with global index g: g itself, or with interleaving (W > 0: the
+// number of waves that hold rays) lane l of wave w takes ray l * W + w, so a wave's rays
+// are spread over the whole batch. Waves from W on take none (n stands for "no ray").
+__device__ __forceinline__ uint32_t ray_of(uint32_t g, uint32_t W, uint32_t n) {
+  if (W == 0u) return g;
+  const uint32_t w = g >> 6, l = g & 63u;
+  return w < W ? l * W + w : n;
+}
+
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_kernel(const DevFormat F, const float4* __restrict__ rays,
-                                                      int4* __restrict__ hits, uint32_t n) {
+                                                      int4* __restrict__ hits, uint32_t n, uint32_t W) {
   __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
   const Fmt fm = fmt_of(F, dtab, pre);
-  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t i = ray_of(blockIdx.x * BLOCK + threadIdx.x, W, n);
   if (i >= n) return;
   const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
   put_hit(hits, i, F.lds_words ? trace_one<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, r0, r1)
@@ -1087,14 +1096,14 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n, uint32_t period,
-                                                            float minlen, uint32_t min_idle) {
+                                                            float minlen, uint32_t min_idle, uint32_t W) {
   __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
   const Fmt fm = fmt_of(F, dtab, pre);
-  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x, w0 = threadIdx.x & ~63u;
+  const uint32_t i = ray_of(blockIdx.x * BLOCK + threadIdx.x, W, n), w0 = threadIdx.x & ~63u;
   if (F.lds_words)
     steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, min_idle, best_all + w0,
                               tbl_all + w0);
@@ -1318,24 +1327,25 @@ size_t stack_lds_bytes(const DevFormat& F) {
   }
 
 hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                        hipStream_t s) {
+                        bool interleave, hipStream_t s) {
   if (n == 0) return HVF_OK;
-  if (n >= (1ull << 32)) {
-    hvf_set_error("at most 2^32 - 1 rays per call");
+  if (n >= (1ull << 32) - (interleave ? 64u : 0u)) {
+    hvf_set_error(interleave ? "at most 2^32 - 65 interleaved rays per call" : "at most 2^32 - 1 rays per call");
     return HVF_E_INPUT;
   }
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
   const float4* r = reinterpret_cast<const float4*>(d_rays);
   int4* h = reinterpret_cast<int4*>(d_hits);
+  const uint32_t W = interleave ? (uint32_t)((n + 63) / 64) : 0u;
 #define HVF_LAUNCH_TRACE(FAMV) \
-  hipLaunchKernelGGL(trace_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n)
+  hipLaunchKernelGGL(trace_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, W)
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_TRACE)
 #undef HVF_LAUNCH_TRACE
   return launch_check("trace");
 }
 
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, uint32_t min_idle, hipStream_t s) {
+                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32) - BLOCK) {
     hvf_set_error("at most 2^32 - 257 rays per stealing call");
@@ -1344,9 +1354,10 @@ hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_r
   const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
   const float4* r = reinterpret_cast<const float4*>(d_rays);
   int4* h = reinterpret_cast<int4*>(d_hits);
+  const uint32_t W = interleave ? (uint32_t)((n + 63) / 64) : 0u;
 #define HVF_LAUNCH_STEAL(FAMV)                                                                                  \
   hipLaunchKernelGGL(trace_steal_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
-                     period, minlen, min_idle)
+                     period, minlen, min_idle, W)
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_STEAL)
 #undef HVF_LAUNCH_STEAL
   return launch_check("stealing trace");
