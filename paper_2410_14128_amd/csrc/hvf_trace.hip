@@ -363,11 +363,12 @@ struct Walk {
     return RUN;
   }
 
-  // One step. On DONE, out holds the result (a miss leaves it untouched).
-  template <uint32_t FAM, class Mem>
+  // One step. On DONE, out holds the result (a miss leaves it untouched). GUARD: count this
+  // walk's steps against MAX_STEPS (callers that pass false keep a guard of their own).
+  template <uint32_t FAM, bool GUARD = true, class Mem>
   __device__ __forceinline__ int step(const Fmt& F, uint2* stk, int4& out, Mem& mem) {
     const uint32_t* dtab = F.dtab;
-    if (++steps > MAX_STEPS) {
+    if (GUARD && ++steps > MAX_STEPS) {
       out = make_int4(-2, -2, -2, 0);  // guard tripped: reported, never silent
       return DONE;
     }
@@ -437,11 +438,6 @@ struct Walk {
         q = F.template w2<FAM>(gx<FAM>(base + idx, rb));
         mem.note((uint32_t)gx<FAM>(base + idx, rb), (blk || (FAM & fam_nk(NK_DAG_INNER) && nk == NK_DAG_INNER)) ? 2u : 1u);
       }
-      // The far-plane times below do not depend on the read: computing them before its
-      // first use lets the load's latency overlap them. The empty asm statement takes them
-      // as operands and is a scheduling boundary, so the compiler cannot sink them past it.
-      far_times(cs, tf, m);
-      asm volatile("" ::"v"(tf[0]), "v"(tf[1]), "v"(tf[2]), "v"(m));
       child = q.x;
       cm = blk ? q : make_uint2(q.x + 1u, q.y & 0xFFu);
       if (rawk) occ = child != 0u;
@@ -454,7 +450,14 @@ struct Walk {
     }
     const bool fin = ((FAM & fam_nk(NK_CELLS)) && nk == NK_CELLS) || ((FAM & fam_nk(NK_OCT_FINAL)) && nk == NK_OCT_FINAL) ||
                      ((FAM & fam_nk(NK_PRAW_VOX)) && nk == NK_PRAW_VOX) || ((FAM & fam_nk(NK_PDF_VOX)) && nk == NK_PDF_VOX);
-    if (occ && !fin) {
+    const bool desc = occ && !fin;
+    // One set of plane times serves both ends of the step: a descent's first mid-plane test
+    // (planes p + 2^(cs-1)) and an advance's far planes (p + 2^cs on axes the ray walks up,
+    // p on the others).
+    const int stepv = 1 << cs, half = stepv >> 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tf[a] = R.T(a, p[a] + (desc ? half : (R.is_neg(a) ? 0 : stepv)));
+    if (desc) {
       if (F.stacked == ALL_STACKED)  // uniform: every depth has a slot, slot = depth
         stk[d * BLOCK] = make_uint2(base, valid);
       else if ((F.stacked >> d) & 1u)
@@ -466,13 +469,14 @@ struct Walk {
       const uint2 h = enter<FAM>(F, info, child, cm, rb, mem);
       base = h.x;
       valid = h.y;
-      refine3(R, p, cs, di_cs(info), t);
+      // The child cell holding the ray at t: the first bit from the mid-plane times above,
+      // the rest (descents of more than one bit per axis) by refine3.
+#pragma unroll
+      for (int a = 0; a < 3; ++a) p[a] += ((tf[a] <= t) != R.is_neg(a)) ? half : 0;
+      refine3(R, p, cs - 1, di_cs(info), t);
       return RUN;
     }
-    // Far-plane times of the current cell (computed above on the common path): the advance
-    // below needs them, and for an occupied voxel they decide the hit.
-    if (dfk) far_times(cs, tf, m);
-    const int stepv = 1 << cs;
+    m = fmin_fx(fmin_fx(tf[0], tf[1]), tf[2]);
     // An occupied single voxel. The walk's t is always the entry time of its current cell:
     // the root cell is entered at t0, an advance enters the next cell at the crossing time
     // of the plane between them, and a descent picks the child holding the ray at t, whose
@@ -972,7 +976,6 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
   Walk w{};
   Plain mem;
   int4 out = miss_hit();
-  int4 own = miss_hit();  // the earliest hit of this lane's own ray found by this lane
   uint32_t home = lane;   // the lane (of this wave) whose ray the current part belongs to
   int kf = 1;             // shallowest ancestor depth this part may still fork at
   float tv = 0.0f;
@@ -984,14 +987,14 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
     tv = cross_time(w.R, minlen);
   }
   for (uint32_t it = 1;; ++it) {
-    if (run && w.template step<FAM>(fm, stk, out, mem) == DONE) {
+    // The step guard counts the wave's iterations (a part never takes more steps than the
+    // iterations since the launch began).
+    if (run && (it > MAX_STEPS || w.template step<FAM, false>(fm, stk, out, mem) == DONE)) {
       run = false;
-      if (out.x != -1) {  // a hit, or the step guard (-2)
-        const uint32_t k = out.x == -2 ? KEY_GUARD : time_key(__int_as_float(out.w));
-        atomicMin(&best[home], k);
-        if (home == lane && out.x >= 0 && (own.x < 0 || k < time_key(__int_as_float(own.w)))) own = out;
-      }
-      out = miss_hit();
+      if (it > MAX_STEPS) out.x = -2;
+      if (out.x != -1)  // a hit, or the step guard (-2)
+        atomicMin(&best[home], out.x == -2 ? KEY_GUARD : time_key(__int_as_float(out.w)));
+      out.x = -1;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     if ((it & (period - 1u)) != 0u) {
@@ -1063,13 +1066,20 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
       const int nn = g[3];
       const uint32_t ns = fm.stacked == ALL_STACKED ? (uint32_t)nn + 1u : slot_of(fm.stacked, nn + 1);
       const uint2* dstk = stk - lane + (uint32_t)src;
-      for (uint32_t j = 0; j < ns; ++j) stk[j * BLOCK] = dstk[j * BLOCK];
+      for (uint32_t j0 = 0; j0 < ns; j0 += 4) {  // four reads in flight, then four writes
+        uint2 v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+          if (j0 + u < ns) v[u] = dstk[(j0 + u) * BLOCK];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+          if (j0 + u < ns) stk[(j0 + u) * BLOCK] = v[u];
+      }
       w.t = f[7];
       w.p[0] = g[0];
       w.p[1] = g[1];
       w.p[2] = g[2];
       w.d = nn + 1;
-      w.steps = 0;
       w.template pop_to<FAM>(fm, stk, nn, mem);
       run = true;
     }
@@ -1080,15 +1090,11 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
   int4 res = miss_hit();
   if (k == KEY_GUARD) {
     res = make_int4(-2, -2, -2, 0);
-  } else if (k != KEY_NOHIT) {
-    if (own.x >= 0 && time_key(__int_as_float(own.w)) == k) {
-      res = own;
-    } else {  // found by another lane: the voxel entered at the hit time
-      const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
-      Ray R;
-      (void)setup(r0, r1, fm.ext, R);
-      res = voxel_at(R, fm.ext, key_time(k));
-    }
+  } else if (k != KEY_NOHIT) {  // the voxel entered at the hit time, whichever lane found it
+    const float4 r0 = ray_half(rays, 2 * (size_t)i), r1 = ray_half(rays, 2 * (size_t)i + 1);
+    Ray R;
+    (void)setup(r0, r1, fm.ext, R);
+    res = voxel_at(R, fm.ext, key_time(k));
   }
   put_hit(hits, i, res);
 }
