@@ -202,7 +202,10 @@ hvf_status hvf_upload(hvf_volume* vol, void* hip_stream);
 
 /* Trace n rays (Sec. 4.2). d_rays, d_hits: device pointers to n hvf_ray / hvf_hit,
  * caller-owned. Asynchronous on hip_stream; the caller synchronises. Uploads the volume
- * first if needed. n == 0 is a no-op. Errors: HVF_E_INPUT, HVF_E_DEVICE, HVF_E_NOMEM. */
+ * first if needed. n == 0 is a no-op. Errors: HVF_E_INPUT, HVF_E_DEVICE, HVF_E_NOMEM.
+ * vol is not const: a trace may upload the buffer and create the volume's trace scratch
+ * (persistent ray counters, the split survivor list) on first use, under the volume's
+ * lock; the occupancy and the words never change. */
 hvf_status hvf_trace(hvf_volume* vol, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits, void* hip_stream);
 
 /* hvf_trace with an explicit schedule (NULL: the volume's current schedule). */
