@@ -186,6 +186,11 @@ def run_headline(args, torch, H, W, C):
                 "B_ray_sector": round(bs, 1), "B_ray_word": round(bw, 1), "loads_per_ray": round(loads, 1),
                 "log_overflow_rays": over, "grid_threads": ((len(b) + 255) // 256) * 256,
                 "roof_mrays_s": round(HBM_PEAK_GBS * 1e9 / bs / 1e6, 1) if fin else None}
+    # `achieved` counts algorithmic bytes (the sector model); the measured HBM bytes (FETCH_SIZE +
+    # WRITE_SIZE from the committed counters) over the same launch time sit beside it.
+    if roofline["traffic"] is not None:
+        roofline["traffic_gbs"] = round(roofline["traffic"] / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
     log(f"[bench] headline: {ms * 1e3:.1f} us per step, {value:.1f} Mrays/s; {kernel} {avg_ms * 1e3:.1f} us, "
         f"B_ray {bs:.0f} B, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of HBM roofline); "
         f"hits identical to the plain schedule: {same}")
