@@ -158,9 +158,9 @@ typedef struct hvf_schedule {
  *   occupied voxel's RGBA word 0xFFFFFFFF); an SVO node is (pointer to its children, masks),
  *   an SVDAG node its masks followed by one pointer per child; a DF cell is (terminating
  *   integer, capped distance). Results are unchanged; the buffer is larger for Raw- and
- *   SVO-final formats and smaller for deep SVDAGs. Not with --restart-sv (HVF_E_UNSUPPORTED),
- *   short stacks or staged LDS depths (HVF_E_INPUT) or hvf_build_device; batches and the
- *   server take such volumes, alone or mixed with the library's layout.
+ *   SVO-final formats and smaller for deep SVDAGs. Not with --restart-sv (HVF_E_UNSUPPORTED)
+ *   or short stacks or staged LDS depths (HVF_E_INPUT); hvf_build_device builds it too;
+ *   batches and the server take such volumes, alone or mixed with the library's layout.
  * morton, n: strictly ascending Morton codes of the occupied voxels (host memory; x is
  *   bit 0, y bit 1, z bit 2 of each 3-bit group), all inside the volume. Not retained.
  * out: receives a new handle owned by the caller (release with hvf_free).
@@ -174,7 +174,11 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
  * passes on hip_stream (a hipStream_t, or NULL for the null stream), and SVDAG nodes are
  * de-duplicated by sorted content hashes, confirmed word by word.
  * format_spec: as for hvf_build, distance-field levels included (their capped distances
- *   come from separable relaxations along x, y and z on the device).
+ *   come from separable relaxations along x, y and z on the device), and --paper-layout:
+ *   the paper's write order (every node after its children's sub-trees) is computed from
+ *   per-node subtree word counts, summed bottom-up and turned into offsets top-down; an
+ *   SVDAG child or leaf is stored if it is the first equal one of its sub-volume (or level)
+ *   in that order. Not with --depth-buffers (HVF_E_UNSUPPORTED).
  * d_morton, n: device pointer to n strictly ascending Morton codes (x bit 0, y bit 1,
  *   z bit 2 of each 3-bit group), all inside the volume; n < 2^31. Read only, not retained.
  * out: receives a new handle owned by the caller (release with hvf_free); its device

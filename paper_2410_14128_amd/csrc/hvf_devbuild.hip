@@ -19,6 +19,8 @@
 //    the L1 distance to the nearest occupied one capped at M. L1 distance splits by axis,
 //    so forward and backward relaxations along x, then y, then z, one thread per line and
 //    in place in the output, give the same integers as the host's breadth-first search.
+// The paper's own word layout (--paper-layout) is built from the same nodes by run_paper
+// (its write order is described with its kernels below).
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -374,6 +376,261 @@ __global__ void k_write_dag(DagView V, const uint32_t* __restrict__ canon, const
   }
 }
 
+// ---------------------------------------------------------------- the paper's word layout
+// The paper's layout (--paper-layout) is written in the order of the construction pass
+// (Sec. 4.1): every node first has its children's sub-trees written, in Morton order, and
+// then its own words ("units"):
+//   * a Raw or DF node (one sub-volume of the level): its cells, or (term, distance) pairs;
+//   * an SVO node: the block of its children's entries, two words each; a sub-volume's
+//     root SVO node then also its own entry (pointer to that block, masks);
+//   * an SVDAG node: the words of each child it stores, in child order (a child below the
+//     root is stored only if no equal node was stored before it in the same sub-volume, or
+//     level with whole-level de-duplication), then, for a sub-volume root, its own words.
+// Word 0 holds the pointer to the level-0 root's words. Within one depth, that order visits
+// nodes in Morton (index) order, so "stored first" is "first in index order" as for the
+// library's layout, and offsets follow from per-node subtree sizes: W(x) = its children's W
+// plus its own units, summed bottom-up, then start(child) = start(x) + the W of the
+// children before it, top-down.
+
+constexpr uint32_t PAPER_VOXEL = 0xFFFFFFFFu;  // an occupied voxel's RGBA word
+
+// Sum of v over every node's run of children [first, first + count): E is the exclusive
+// scan of v.
+__global__ void kp_run_sum(const uint64_t* __restrict__ v, const uint64_t* __restrict__ E,
+                           const uint32_t* __restrict__ first, const uint32_t* __restrict__ count, size_t n,
+                           uint64_t* __restrict__ out) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  const uint32_t f = first[x], c = count[x];
+  out[x] = c ? E[f + c - 1u] + v[f + c - 1u] - E[f] : 0u;
+}
+
+// Unit sizes of SVDAG children (and leaves) that are stored: 1 + children, 0 if merged;
+// cnt null: leaves (one word each).
+__global__ void kp_unit_sizes(const uint32_t* __restrict__ canon, const uint32_t* __restrict__ cnt, size_t n,
+                              uint64_t* __restrict__ usize, uint32_t* __restrict__ uflag) {
+  const size_t y = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (y >= n) return;
+  const bool st = canon ? canon[y] == (uint32_t)y : true;
+  usize[y] = st ? 1u + (cnt ? cnt[y] : 0u) : 0u;
+  uflag[y] = st ? 1u : 0u;
+}
+
+// Own words and subtree words of every node of a depth. kind 0: Raw (own = cells * per);
+// 1: SVO (2 per child, + 2 for a sub-volume root); 2: SVDAG (the stored children's words,
+// + 1 + children for a sub-volume root). kidw: the children's subtree words (null at the
+// deepest depth); ksum: the stored children's unit words (SVDAG).
+__global__ void kp_own(int kind, int root, uint64_t rawwords, const uint32_t* __restrict__ count,
+                       const uint64_t* __restrict__ kidw, const uint64_t* __restrict__ ksum, size_t n,
+                       uint64_t* __restrict__ own, uint64_t* __restrict__ W) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  uint64_t o;
+  if (kind == 0)
+    o = rawwords;
+  else if (kind == 1)
+    o = 2ull * count[x] + (root ? 2u : 0u);
+  else
+    o = ksum[x] + (root ? 1ull + count[x] : 0u);
+  own[x] = o;
+  W[x] = o + (kidw ? kidw[x] : 0u);
+}
+
+// start(y) = start(parent) + the subtree words of the siblings before y (E: exclusive scan of
+// W over the depth); null parent: the single root, starting at word 1.
+__global__ void kp_start(const uint32_t* __restrict__ par, const uint32_t* __restrict__ pfirst,
+                         const uint64_t* __restrict__ pstart, const uint64_t* __restrict__ E, size_t n,
+                         uint64_t* __restrict__ start) {
+  const size_t y = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (y >= n) return;
+  if (!par) {
+    start[y] = 1u + E[y];
+    return;
+  }
+  const uint32_t p = par[y];
+  start[y] = pstart[p] + E[y] - E[pfirst[p]];
+}
+
+// base(x): the first word of x's own units (after its children's sub-trees).
+__global__ void kp_base(const uint64_t* __restrict__ start, const uint64_t* __restrict__ W,
+                        const uint64_t* __restrict__ own, size_t n, uint64_t* __restrict__ base) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x < n) base[x] = start[x] + W[x] - own[x];
+}
+
+// Offset of each child's (or leaf's) unit inside its parent's run of child units: the
+// parent's base plus the unit words of the siblings before it (E: exclusive scan of usize).
+__global__ void kp_unit_off(const uint32_t* __restrict__ par, const uint32_t* __restrict__ pfirst,
+                            const uint64_t* __restrict__ pbase, const uint64_t* __restrict__ E, size_t n,
+                            uint64_t* __restrict__ uoff) {
+  const size_t y = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (y >= n) return;
+  const uint32_t p = par ? par[y] : 0u;
+  uoff[y] = pbase[p] + E[y] - E[pfirst[p]];
+}
+
+// Offset of a sub-volume root's own words (what a parent level's term points at): a Raw
+// node's cells at base; an SVO root's entry after its block; an SVDAG root's words after
+// its stored children's.
+__global__ void kp_root_off(int kind, const uint64_t* __restrict__ base, const uint64_t* __restrict__ own,
+                            const uint32_t* __restrict__ count, size_t n, uint64_t* __restrict__ roff) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  uint64_t o = base[x];
+  if (kind == 1) o += 2ull * count[x];
+  if (kind == 2) o += own[x] - 1u - count[x];
+  roff[x] = o;
+}
+
+// Raw/DF cells: each child (a next-level root, or a voxel of the last level) writes its
+// terminating integer into its parent's cells (per words per cell: 1, or 2 with a distance).
+__global__ void kp_write_raw(const uint64_t* __restrict__ ckey, const uint32_t* __restrict__ par,
+                             const uint64_t* __restrict__ croot, size_t nc, int w0, int w1, int root, uint32_t per,
+                             const uint64_t* __restrict__ pbase, uint64_t lim, uint32_t* __restrict__ err,
+                             uint32_t* __restrict__ dst) {
+  const size_t j = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (j >= nc) return;
+  const uint64_t k = ckey[j];
+  const uint64_t local = root ? k : (k & ((1ull << (3 * w0)) - 1ull));
+  const uint64_t cell = coord_of(local) | (coord_of(local >> 1) << w0) | (coord_of(local >> 2) << (w0 + w1));
+  const uint64_t at = pbase[par ? par[j] : 0u] + per * cell;
+  if (at >= lim) {
+    atomicOr(err, 1u);
+    return;
+  }
+  dst[at] = croot ? (uint32_t)croot[j] : PAPER_VOXEL;
+}
+
+// DF distances in place in the (term, distance) pairs of every node of a depth: 0 where the
+// term is not 0, else far; relaxed per axis; capped.
+__global__ void kp_df_init(uint32_t* __restrict__ dst, const uint64_t* __restrict__ nbase, size_t nodes,
+                           int cbits, uint64_t lim, uint32_t* __restrict__ err) {
+  const size_t g = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (g >= (nodes << cbits)) return;
+  const size_t node = g >> cbits;
+  if (nbase[node] + (2ull << cbits) > lim) {  // the node's pairs must fit (the relaxations rely on it)
+    atomicOr(err, 1u);
+    return;
+  }
+  uint32_t* o = dst + nbase[node] + 2u * (g & ((1ull << cbits) - 1u));
+  o[1] = o[0] ? 0u : DF_FAR;
+}
+
+__global__ void kp_df_relax(uint32_t* __restrict__ dst, const uint64_t* __restrict__ nbase, size_t lines,
+                            int lbits, int cbits, uint32_t len, uint64_t step, uint64_t lo_mask, int lo_bits,
+                            uint64_t lim) {
+  const size_t g = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (g >= lines) return;
+  const size_t node = g >> lbits, l = g & ((1ull << lbits) - 1u);
+  if (nbase[node] + (2ull << cbits) > lim) return;  // reported by kp_df_init
+  const uint64_t first = (l & lo_mask) | ((l >> lo_bits) << (lo_bits + __builtin_ctzll((unsigned long long)len)));
+  uint32_t* o = dst + nbase[node] + 2u * first + 1u;
+  const uint64_t st = 2u * step;
+  uint32_t prev = o[0];
+  for (uint32_t i = 1; i < len; ++i) {
+    uint32_t v = o[i * st];
+    if (prev + 1u < v) {
+      v = prev + 1u;
+      o[i * st] = v;
+    }
+    prev = v;
+  }
+  for (uint32_t i = len - 1; i-- > 0;) {
+    uint32_t v = o[i * st];
+    if (prev + 1u < v) {
+      v = prev + 1u;
+      o[i * st] = v;
+    }
+    prev = v;
+  }
+}
+
+__global__ void kp_df_cap(uint32_t* __restrict__ dst, const uint64_t* __restrict__ nbase, size_t nodes, int cbits,
+                          uint32_t cap, uint64_t lim) {
+  const size_t g = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (g >= (nodes << cbits) || nbase[g >> cbits] + (2ull << cbits) > lim) return;
+  uint32_t* o = dst + nbase[g >> cbits] + 2u * (g & ((1ull << cbits) - 1u)) + 1u;
+  if (*o > cap) *o = cap;
+}
+
+// SVO blocks: entry t of node x's block is its child's (pointer to the child's block,
+// masks), or at a level's deepest depth (the next-level root's words, 0) / (voxel, 0).
+// A sub-volume root also writes its own entry after the block.
+__global__ void kp_write_svo(const uint32_t* __restrict__ first, const uint32_t* __restrict__ count,
+                             const uint32_t* __restrict__ masks, const uint64_t* __restrict__ base, size_t n,
+                             int mode, const uint64_t* __restrict__ kbase, const uint32_t* __restrict__ kmasks,
+                             const uint64_t* __restrict__ kroot, int root, uint64_t lim, uint32_t* __restrict__ err,
+                             uint32_t* __restrict__ dst) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x >= n) return;
+  const uint32_t f = first[x], c = count[x];
+  if (base[x] + 2ull * c + (root ? 2u : 0u) > lim) {
+    atomicOr(err, 1u);
+    return;
+  }
+  uint32_t* o = dst + base[x];
+  for (uint32_t t = 0; t < c; ++t) {
+    if (mode == 0) {  // children at the next depth of this level
+      o[2 * t] = (uint32_t)kbase[f + t];
+      o[2 * t + 1] = kmasks[f + t];
+    } else {  // leaves: next-level roots (mode 1) or voxels (mode 2)
+      o[2 * t] = mode == 1 ? (uint32_t)kroot[f + t] : PAPER_VOXEL;
+      o[2 * t + 1] = 0u;
+    }
+  }
+  if (root) {
+    o[2 * c] = (uint32_t)base[x];
+    o[2 * c + 1] = masks[x];
+  }
+}
+
+// SVDAG words {masks, pointer per child} of every stored node at its unit offset (roots at
+// their root offset). Children's pointers go to their canonical (stored) unit.
+__global__ void kp_write_dag(const uint32_t* __restrict__ canon, const uint32_t* __restrict__ first,
+                             const uint32_t* __restrict__ count, const uint32_t* __restrict__ masks,
+                             const uint64_t* __restrict__ off, size_t n, const uint32_t* __restrict__ kcanon,
+                             const uint64_t* __restrict__ koff, uint64_t lim, uint32_t* __restrict__ err,
+                             uint32_t* __restrict__ dst) {
+  const size_t y = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (y >= n || (canon && canon[y] != (uint32_t)y)) return;
+  const uint32_t f = first[y], c = count[y];
+  if (off[y] + 1ull + c > lim) {
+    atomicOr(err, 1u);
+    return;
+  }
+  uint32_t* o = dst + off[y];
+  o[0] = masks[y];
+  for (uint32_t t = 0; t < c; ++t) {
+    const uint32_t k = kcanon ? kcanon[f + t] : f + t;
+    o[1 + t] = (uint32_t)koff[k];
+  }
+}
+
+// SVDAG leaf words {terminating integer} of the stored leaves: a voxel (last level) or the
+// next-level root's words.
+__global__ void kp_write_leaves(const uint32_t* __restrict__ canon, const uint64_t* __restrict__ off,
+                                const uint64_t* __restrict__ kroot, size_t n, uint64_t lim,
+                                uint32_t* __restrict__ err, uint32_t* __restrict__ dst) {
+  const size_t l = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (l >= n || (canon && canon[l] != (uint32_t)l)) return;
+  if (off[l] >= lim) {
+    atomicOr(err, 1u);
+    return;
+  }
+  dst[off[l]] = kroot ? (uint32_t)kroot[l] : PAPER_VOXEL;
+}
+
+// head[i] = i where g changes (the first element of a run), else 0 (max-scanned after).
+__global__ void kp_run_heads(const uint32_t* __restrict__ g, size_t n, uint32_t* __restrict__ head) {
+  const size_t i = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (i < n) head[i] = (i == 0 || g[i] != g[i - 1]) ? (uint32_t)i : 0u;
+}
+
+__global__ void kp_masks_count(const uint32_t* __restrict__ masks, size_t n, uint32_t* __restrict__ count) {
+  const size_t x = (size_t)blockIdx.x * TB + threadIdx.x;
+  if (x < n) count[x] = (uint32_t)__popc(masks[x] & 0xFFu);
+}
+
 // ---------------------------------------------------------------- host orchestration
 struct DepthState {
   size_t n = 0;               // nodes (before de-duplication)
@@ -403,6 +660,7 @@ class DeviceBuilder {
   }
 
   hvf_status run(Built& B, uint32_t** dbuf, size_t* nwords);
+  hvf_status run_paper(Built& B, uint32_t** dbuf, size_t* nwords);  // the paper's layout
   const std::string& error() const { return err_; }
 
  private:
@@ -517,6 +775,11 @@ class DeviceBuilder {
     return di.nk == NK_SVO_INNER || di.nk == NK_DAG_INNER || di.nk == NK_OCT_PTR || di.nk == NK_OCT_FINAL;
   }
   bool dedup(int i, std::vector<DepthState>& D, bool has_children);
+  bool validate_codes();
+  bool structure(std::vector<DepthState>& D, int dl, uint32_t*& code_rank);
+  bool groups(std::vector<DepthState>& D, int dl);
+  bool canon_of(const DagView& V, size_t n, uint32_t* canon);
+  bool scan64(const uint64_t* v, size_t n, uint64_t*& E);
 };
 
 // SVDAG depth i: canonical nodes, stored-node offsets, word count.
@@ -588,13 +851,7 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   std::vector<DepthState> D(nd);
   for (int i = 1; i < nd; ++i) D[i].ns = L.d[i].cs + L.d[i].w[0];
   // 1. the codes: strictly ascending and inside the volume
-  uint32_t* err = alloc<uint32_t>(1);
-  if (!err || !hip(hipMemsetAsync(err, 0, sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, S.ext[0], S.ext[1], S.ext[2], err);
-  uint32_t herr = 0;
-  if (!launched("validate") || !fetch(err, herr)) return st_;
-  if (herr & 1u) return stop(HVF_E_INPUT, "Morton codes must be strictly ascending");
-  if (herr & 2u) return stop(HVF_E_INPUT, "Morton code outside the volume");
+  if (!validate_codes()) return st_;
   // Nodes of more than 2^31 words are out of range of the traversal's 32-bit offsets.
   bool df_ptr = false;
   for (const DepthInfo& di : L.d) {
@@ -605,62 +862,10 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   // 2. node keys, bottom-up. The deepest stored depth takes its nodes from the codes (and
   //    keeps every code's node rank: bricks and final octree masks are filled per voxel).
   const int dl = L.d[nd - 1].arena ? nd - 1 : nd - 2;
-  uint32_t* flag = alloc<uint32_t>(n_);
-  if (!flag) return st_;
   uint32_t* code_rank = nullptr;
-  if (dl == 0) {
-    D[0].n = 1;
-  } else {
-    DepthState& q = D[dl];
-    code_rank = alloc<uint32_t>(n_);
-    if (!code_rank) return st_;
-    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag);
-    uint32_t cnt = 0;
-    if (!launched("flags") || !inclusive_sum(flag, code_rank, n_) || !fetch(code_rank + n_ - 1, cnt)) return st_;
-    q.n = cnt;
-    if (!(q.keys = alloc<uint64_t>(q.n))) return st_;
-    hipLaunchKernelGGL(k_run_keys, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag, code_rank, q.keys);
-    if (!launched("keys")) return st_;
-  }
-  for (int i = dl - 1; i >= 0; --i) {
-    DepthState& q = D[i];
-    DepthState& c = D[i + 1];
-    if (!(c.parent = alloc<uint32_t>(c.n))) return st_;
-    if (i == 0) {
-      q.n = 1;
-      if (!hip(hipMemsetAsync(c.parent, 0, c.n * sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
-    } else {
-      const int sh = 3 * (q.ns - c.ns);
-      hipLaunchKernelGGL(k_run_flags, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag);
-      uint32_t cnt = 0;
-      if (!launched("flags") || !inclusive_sum(flag, c.parent, c.n) || !fetch(c.parent + c.n - 1, cnt)) return st_;
-      q.n = cnt;
-      if (!(q.keys = alloc<uint64_t>(q.n))) return st_;
-      hipLaunchKernelGGL(k_run_keys, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag, c.parent, q.keys);
-      hipLaunchKernelGGL(k_decrement, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n);
-      if (!launched("parents")) return st_;
-    }
-    q.first = alloc<uint32_t>(q.n);
-    q.count = alloc<uint32_t>(q.n);
-    if (!q.first || !q.count) return st_;
-    hipLaunchKernelGGL(k_child_first, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first);
-    hipLaunchKernelGGL(k_child_count, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first, q.count);
-    if (!launched("child runs")) return st_;
-  }
+  if (!structure(D, dl, code_rank)) return st_;
   // 3. sub-volume of every SVDAG node (top-down)
-  if (!S.wld) {
-    for (int i = 0; i <= dl; ++i) {
-      const DepthInfo& di = L.d[i];
-      if (S.lv[di.level].kind != LK_DAG) continue;
-      DepthState& q = D[i];
-      if (!(q.group = alloc<uint32_t>(q.n))) return st_;
-      if (di.j == 0)
-        hipLaunchKernelGGL(k_iota, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.group, q.n);
-      else
-        hipLaunchKernelGGL(k_gather, dim3(grid_for(q.n)), dim3(TB), 0, s_, D[i - 1].group, q.parent, q.n, q.group);
-      if (!launched("groups")) return st_;
-    }
-  }
+  if (!groups(D, dl)) return st_;
   // 4. word offsets inside every depth, bottom-up
   for (int i = dl; i >= 0; --i) {
     const DepthInfo& di = L.d[i];
@@ -786,6 +991,397 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
   return HVF_OK;
 }
 
+
+// Strictly ascending codes inside the volume (else a recorded error).
+bool DeviceBuilder::validate_codes() {
+  uint32_t* err = alloc<uint32_t>(1);
+  if (!err || !hip(hipMemsetAsync(err, 0, sizeof(uint32_t), s_), "hipMemsetAsync")) return false;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, S.ext[0], S.ext[1], S.ext[2], err);
+  uint32_t herr = 0;
+  if (!launched("validate") || !fetch(err, herr)) return false;
+  if (herr & 1u) return fail(HVF_E_INPUT, "Morton codes must be strictly ascending");
+  if (herr & 2u) return fail(HVF_E_INPUT, "Morton code outside the volume");
+  return true;
+}
+
+// Node keys of every depth down to dl (the deepest takes them from the codes and keeps
+// every code's node rank in code_rank), every node's parent, and every parent's run of
+// children.
+bool DeviceBuilder::structure(std::vector<DepthState>& D, int dl, uint32_t*& code_rank) {
+  uint32_t* flag = alloc<uint32_t>(n_);
+  if (!flag) return false;
+  code_rank = nullptr;
+  if (dl == 0) {
+    D[0].n = 1;
+  } else {
+    DepthState& q = D[dl];
+    code_rank = alloc<uint32_t>(n_);
+    if (!code_rank) return false;
+    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag);
+    uint32_t cnt = 0;
+    if (!launched("flags") || !inclusive_sum(flag, code_rank, n_) || !fetch(code_rank + n_ - 1, cnt)) return false;
+    q.n = cnt;
+    if (!(q.keys = alloc<uint64_t>(q.n))) return false;
+    hipLaunchKernelGGL(k_run_keys, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, n_, 3 * q.ns, flag, code_rank, q.keys);
+    if (!launched("keys")) return false;
+  }
+  for (int i = dl - 1; i >= 0; --i) {
+    DepthState& q = D[i];
+    DepthState& c = D[i + 1];
+    if (!(c.parent = alloc<uint32_t>(c.n))) return false;
+    if (i == 0) {
+      q.n = 1;
+      if (!hip(hipMemsetAsync(c.parent, 0, c.n * sizeof(uint32_t), s_), "hipMemsetAsync")) return false;
+    } else {
+      const int sh = 3 * (q.ns - c.ns);
+      hipLaunchKernelGGL(k_run_flags, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag);
+      uint32_t cnt = 0;
+      if (!launched("flags") || !inclusive_sum(flag, c.parent, c.n) || !fetch(c.parent + c.n - 1, cnt)) return false;
+      q.n = cnt;
+      if (!(q.keys = alloc<uint64_t>(q.n))) return false;
+      hipLaunchKernelGGL(k_run_keys, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, c.n, sh, flag, c.parent, q.keys);
+      hipLaunchKernelGGL(k_decrement, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n);
+      if (!launched("parents")) return false;
+    }
+    q.first = alloc<uint32_t>(q.n);
+    q.count = alloc<uint32_t>(q.n);
+    if (!q.first || !q.count) return false;
+    hipLaunchKernelGGL(k_child_first, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first);
+    hipLaunchKernelGGL(k_child_count, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.parent, c.n, q.first, q.count);
+    if (!launched("child runs")) return false;
+  }
+  return true;
+}
+
+// Sub-volume (the index of its level's root node) of every SVDAG node, top-down; none with
+// whole-level de-duplication.
+bool DeviceBuilder::groups(std::vector<DepthState>& D, int dl) {
+  if (S.wld) return true;
+  for (int i = 0; i <= dl; ++i) {
+    const DepthInfo& di = L.d[i];
+    if (S.lv[di.level].kind != LK_DAG) continue;
+    DepthState& q = D[i];
+    if (!(q.group = alloc<uint32_t>(q.n))) return false;
+    if (di.j == 0)
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.group, q.n);
+    else
+      hipLaunchKernelGGL(k_gather, dim3(grid_for(q.n)), dim3(TB), 0, s_, D[i - 1].group, q.parent, q.n, q.group);
+    if (!launched("groups")) return false;
+  }
+  return true;
+}
+
+// canon[x]: the first node in index order with x's content (V: masks, children's canonical
+// ids, group), found through sorted content hashes and confirmed word by word.
+bool DeviceBuilder::canon_of(const DagView& V, size_t n, uint32_t* canon) {
+  uint64_t* hash = alloc<uint64_t>(n);
+  uint64_t* shash = alloc<uint64_t>(n);
+  uint32_t* idx = alloc<uint32_t>(n);
+  uint32_t* sidx = alloc<uint32_t>(n);
+  uint32_t* head = alloc<uint32_t>(n);
+  uint32_t* runh = alloc<uint32_t>(n);
+  if (!hash || !shash || !idx || !sidx || !head || !runh) return false;
+  hipLaunchKernelGGL(k_dag_hash, dim3(grid_for(n)), dim3(TB), 0, s_, V, n, hash);
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(TB), 0, s_, idx, n);
+  if (!launched("hash") || !sort_pairs(hash, shash, idx, sidx, n)) return false;
+  hipLaunchKernelGGL(k_hash_heads, dim3(grid_for(n)), dim3(TB), 0, s_, shash, n, head);
+  if (!launched("heads") || !max_scan(head, runh, n)) return false;
+  hipLaunchKernelGGL(k_canon, dim3(grid_for(n)), dim3(TB), 0, s_, V, sidx, runh, n, canon);
+  return launched("canon");
+}
+
+bool DeviceBuilder::scan64(const uint64_t* v, size_t n, uint64_t*& E) {
+  E = alloc<uint64_t>(n);
+  return E && exclusive_sum(v, E, n);
+}
+
+hvf_status DeviceBuilder::run_paper(Built& B, uint32_t** dbuf, size_t* nwords) {
+  const int nd = (int)L.d.size();
+  const int nlev = (int)S.lv.size();
+  std::vector<DepthState> D(nd);
+  for (int i = 1; i < nd; ++i) D[i].ns = L.d[i].cs + L.d[i].w[0];
+  if (!validate_codes()) return st_;
+  // 1. nodes of every depth (all are stored in this layout); the deepest depth's children
+  //    are the codes.
+  const int dl = nd - 1;
+  uint32_t* code_rank = nullptr;
+  if (!structure(D, dl, code_rank)) return st_;
+  uint32_t* cpar = nullptr;  // every code's node at the deepest depth (null: the single root)
+  {
+    DepthState& q = D[dl];
+    q.first = alloc<uint32_t>(q.n);
+    q.count = alloc<uint32_t>(q.n);
+    if (!q.first || !q.count) return st_;
+    if (dl == 0) {
+      const uint32_t z = 0, nn = (uint32_t)n_;
+      if (!hip(hipMemcpyAsync(q.first, &z, sizeof(z), hipMemcpyHostToDevice, s_), "hipMemcpyAsync") ||
+          !hip(hipMemcpyAsync(q.count, &nn, sizeof(nn), hipMemcpyHostToDevice, s_), "hipMemcpyAsync") ||
+          !hip(hipStreamSynchronize(s_), "hipStreamSynchronize"))
+        return st_;
+    } else {
+      if (!(cpar = alloc<uint32_t>(n_))) return st_;
+      if (!hip(hipMemcpyAsync(cpar, code_rank, n_ * sizeof(uint32_t), hipMemcpyDeviceToDevice, s_), "hipMemcpyAsync"))
+        return st_;
+      hipLaunchKernelGGL(k_decrement, dim3(grid_for(n_)), dim3(TB), 0, s_, cpar, n_);
+      hipLaunchKernelGGL(k_child_first, dim3(grid_for(n_)), dim3(TB), 0, s_, cpar, n_, q.first);
+      hipLaunchKernelGGL(k_child_count, dim3(grid_for(n_)), dim3(TB), 0, s_, cpar, n_, q.first, q.count);
+      if (!launched("code runs")) return st_;
+    }
+  }
+  if (!groups(D, dl)) return st_;
+  // 2. octree masks: valid children, and at a level's deepest depth also the leaf bits
+  for (int i = dl; i >= 0; --i) {
+    const DepthInfo& di = L.d[i];
+    if (S.lv[di.level].kind == LK_RAW) continue;
+    DepthState& q = D[i];
+    if (!(q.masks = alloc<uint32_t>(q.n))) return st_;
+    const int deepest = di.j == S.lv[di.level].e[0] - 1;
+    if (i < dl)
+      hipLaunchKernelGGL(k_masks_children, dim3(grid_for(q.n)), dim3(TB), 0, s_, D[i + 1].keys, q.first, q.count, q.n,
+                         deepest, q.masks);
+    else
+      hipLaunchKernelGGL(k_masks_voxels, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, code_rank, n_, q.masks);
+    if (!launched("masks")) return st_;
+  }
+  // 3. SVDAG de-duplication, bottom-up. Leaves of the last level are all the same voxel
+  //    word: the first of each sub-volume (or of the level) is stored. A leaf above the next
+  //    level holds that sub-volume's own pointer and is never merged. Nodes below a
+  //    sub-volume root are merged with the first equal node (masks, children's canonical
+  //    ids) of their group.
+  const bool last_dag = S.lv[nlev - 1].kind == LK_DAG;
+  uint32_t* canonL = nullptr;  // last level's leaves (one per code)
+  if (last_dag) {
+    uint32_t* g = alloc<uint32_t>(n_);
+    uint32_t* head = alloc<uint32_t>(n_);
+    canonL = alloc<uint32_t>(n_);
+    if (!g || !head || !canonL) return st_;
+    if (S.wld || dl == 0) {
+      if (!hip(hipMemsetAsync(g, 0, n_ * sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
+    } else {
+      hipLaunchKernelGGL(k_gather, dim3(grid_for(n_)), dim3(TB), 0, s_, D[dl].group, cpar, n_, g);
+    }
+    hipLaunchKernelGGL(kp_run_heads, dim3(grid_for(n_)), dim3(TB), 0, s_, g, n_, head);
+    if (!launched("leaf heads") || !max_scan(head, canonL, n_)) return st_;
+  }
+  std::vector<uint32_t*> ident(nd, nullptr);  // iota over a depth (leaves above the next level)
+  for (int i = dl; i >= 0; --i) {
+    const DepthInfo& di = L.d[i];
+    if (S.lv[di.level].kind != LK_DAG) continue;
+    DepthState& q = D[i];
+    if (!(q.canon = alloc<uint32_t>(q.n))) return st_;
+    if (di.j == 0) {
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.canon, q.n);
+      if (!launched("iota")) return st_;
+      continue;
+    }
+    const uint32_t* cid;
+    if (i == dl) {
+      cid = canonL;
+    } else if (L.d[i + 1].level == di.level) {
+      cid = D[i + 1].canon;
+    } else {
+      if (!(ident[i + 1] = alloc<uint32_t>(D[i + 1].n))) return st_;
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(D[i + 1].n)), dim3(TB), 0, s_, ident[i + 1], D[i + 1].n);
+      if (!launched("iota")) return st_;
+      cid = ident[i + 1];
+    }
+    const DagView V{q.masks, q.first, q.count, cid, S.wld ? nullptr : q.group};
+    if (!canon_of(V, q.n, q.canon)) return st_;
+  }
+  // 4. words: each node's own units and its subtree (bottom-up); the unit words of SVDAG
+  //    children and leaves (0 when merged) come first.
+  std::vector<uint64_t*> W(nd), EW(nd), own(nd), usz(nd), EU(nd);
+  std::vector<uint64_t> stored(nd, 0);
+  uint64_t* uszL = nullptr;  // last level's leaf units
+  uint64_t* EUL = nullptr;
+  uint64_t storedL = 0;
+  uint32_t* flag = alloc<uint32_t>(std::max(n_, (size_t)1));
+  uint32_t* nst = alloc<uint32_t>(1);
+  if (!flag || !nst) return st_;
+  auto count_stored = [&](size_t n, uint64_t& out) {
+    uint32_t c = 0;
+    if (!sum(flag, nst, n) || !fetch(nst, c)) return false;
+    out = c;
+    return true;
+  };
+  if (last_dag) {
+    if (!(uszL = alloc<uint64_t>(n_))) return st_;
+    hipLaunchKernelGGL(kp_unit_sizes, dim3(grid_for(n_)), dim3(TB), 0, s_, canonL, nullptr, n_, uszL, flag);
+    if (!launched("leaf sizes") || !count_stored(n_, storedL) || !scan64(uszL, n_, EUL)) return st_;
+  }
+  for (int i = dl; i >= 0; --i) {
+    const DepthInfo& di = L.d[i];
+    const int kind = S.lv[di.level].kind == LK_RAW ? 0 : (S.lv[di.level].kind == LK_SVO ? 1 : 2);
+    DepthState& q = D[i];
+    // this depth's units as children of the depth above: SVDAG nodes below a root, and
+    // next-level roots under an SVDAG level's deepest depth (its leaves)
+    if (i > 0 && S.lv[L.d[i - 1].level].kind == LK_DAG) {
+      const bool leaf = L.d[i - 1].level != di.level;  // one-word leaves, never merged
+      if (!(usz[i] = alloc<uint64_t>(q.n))) return st_;
+      hipLaunchKernelGGL(kp_unit_sizes, dim3(grid_for(q.n)), dim3(TB), 0, s_, leaf ? nullptr : q.canon,
+                         leaf ? nullptr : q.count, q.n, usz[i], flag);
+      if (!launched("unit sizes") || !count_stored(q.n, stored[i]) || !scan64(usz[i], q.n, EU[i])) return st_;
+    }
+    uint64_t* kidw = nullptr;
+    uint64_t* ksum = nullptr;
+    if (i < dl) {
+      if (!(kidw = alloc<uint64_t>(q.n))) return st_;
+      hipLaunchKernelGGL(kp_run_sum, dim3(grid_for(q.n)), dim3(TB), 0, s_, W[i + 1], EW[i + 1], q.first, q.count, q.n,
+                         kidw);
+      if (!launched("subtree sums")) return st_;
+    }
+    if (kind == 2) {
+      if (!(ksum = alloc<uint64_t>(q.n))) return st_;
+      const uint64_t* ku = i < dl ? usz[i + 1] : uszL;
+      const uint64_t* ke = i < dl ? EU[i + 1] : EUL;
+      hipLaunchKernelGGL(kp_run_sum, dim3(grid_for(q.n)), dim3(TB), 0, s_, ku, ke, q.first, q.count, q.n, ksum);
+      if (!launched("unit sums")) return st_;
+    }
+    const int cells = di.w[0] + di.w[1] + di.w[2];
+    const uint64_t rawwords = kind == 0 ? (uint64_t)(S.lv[di.level].maxd ? 2 : 1) << cells : 0;
+    if (!(own[i] = alloc<uint64_t>(q.n)) || !(W[i] = alloc<uint64_t>(q.n))) return st_;
+    hipLaunchKernelGGL(kp_own, dim3(grid_for(q.n)), dim3(TB), 0, s_, kind, di.j == 0 ? 1 : 0, rawwords, q.count, kidw,
+                       ksum, q.n, own[i], W[i]);
+    if (!launched("own words") || !scan64(W[i], q.n, EW[i])) return st_;
+  }
+  uint64_t total = 0;
+  if (!fetch(W[0], total)) return st_;
+  total += 1;  // word 0: the root pointer
+  if (total >= (1ull << 32)) return stop(HVF_E_OVERFLOW, "the format exceeds 2^32 words (16 GiB, the paper's limit)");
+  // 5. offsets, top-down: subtree starts, own-unit bases, children's units, roots' words
+  std::vector<uint64_t*> start(nd), base(nd), uoff(nd), roff(nd);
+  uint64_t* loffL = nullptr;
+  for (int i = 0; i <= dl; ++i) {
+    DepthState& q = D[i];
+    if (!(start[i] = alloc<uint64_t>(q.n)) || !(base[i] = alloc<uint64_t>(q.n))) return st_;
+    hipLaunchKernelGGL(kp_start, dim3(grid_for(q.n)), dim3(TB), 0, s_, i ? q.parent : nullptr,
+                       i ? D[i - 1].first : nullptr, i ? start[i - 1] : nullptr, EW[i], q.n, start[i]);
+    hipLaunchKernelGGL(kp_base, dim3(grid_for(q.n)), dim3(TB), 0, s_, start[i], W[i], own[i], q.n, base[i]);
+    if (!launched("starts")) return st_;
+    if (usz[i]) {
+      if (!(uoff[i] = alloc<uint64_t>(q.n))) return st_;
+      hipLaunchKernelGGL(kp_unit_off, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.parent, D[i - 1].first, base[i - 1],
+                         EU[i], q.n, uoff[i]);
+      if (!launched("unit offsets")) return st_;
+    }
+    const DepthInfo& di = L.d[i];
+    if (di.j == 0) {
+      const int kind = S.lv[di.level].kind == LK_RAW ? 0 : (S.lv[di.level].kind == LK_SVO ? 1 : 2);
+      if (!(roff[i] = alloc<uint64_t>(q.n))) return st_;
+      hipLaunchKernelGGL(kp_root_off, dim3(grid_for(q.n)), dim3(TB), 0, s_, kind, base[i], own[i], q.count, q.n,
+                         roff[i]);
+      if (!launched("root offsets")) return st_;
+    }
+  }
+  if (last_dag) {
+    if (!(loffL = alloc<uint64_t>(n_))) return st_;
+    hipLaunchKernelGGL(kp_unit_off, dim3(grid_for(n_)), dim3(TB), 0, s_, cpar, D[dl].first, base[dl], EUL, n_, loffL);
+    if (!launched("leaf offsets")) return st_;
+  }
+  // 6. the words. Every write is checked against the buffer's end (a violation would be a
+  //    construction error, reported, never a write out of bounds).
+  const size_t nw = (size_t)total + HVF_BUFFER_PAD_WORDS;
+  uint32_t* werr = alloc<uint32_t>(1);
+  if (!werr || !hip(hipMemsetAsync(werr, 0, sizeof(uint32_t), s_), "hipMemsetAsync")) return st_;
+  if (!hip(hipMalloc(&buf_, nw * sizeof(uint32_t)), "hipMalloc of the word buffer") ||
+      !hip(hipMemsetAsync(buf_, 0, nw * sizeof(uint32_t), s_), "hipMemsetAsync"))
+    return st_;
+  const uint64_t lim = total;
+  for (int i = 0; i <= dl; ++i) {
+    const DepthInfo& di = L.d[i];
+    const LevelSpec& lv = S.lv[di.level];
+    DepthState& q = D[i];
+    const bool deepest = lv.kind == LK_RAW || di.j == lv.e[0] - 1;  // children in the next level (or voxels)
+    if (lv.kind == LK_RAW) {
+      const uint32_t per = lv.maxd ? 2u : 1u;
+      if (i < dl) {
+        const DepthState& c = D[i + 1];
+        hipLaunchKernelGGL(kp_write_raw, dim3(grid_for(c.n)), dim3(TB), 0, s_, c.keys, i == 0 ? nullptr : c.parent,
+                           roff[i + 1], c.n, di.w[0], di.w[1], i == 0 ? 1 : 0, per, base[i], lim, werr, buf_);
+      } else {
+        hipLaunchKernelGGL(kp_write_raw, dim3(grid_for(n_)), dim3(TB), 0, s_, codes_, cpar, nullptr, n_, di.w[0],
+                           di.w[1], i == 0 ? 1 : 0, per, base[i], lim, werr, buf_);
+      }
+      if (!launched("raw cells")) return st_;
+      if (lv.maxd) {
+        const int cb = di.w[0] + di.w[1] + di.w[2];
+        const size_t all = q.n << cb;
+        hipLaunchKernelGGL(kp_df_init, dim3(grid_for(all)), dim3(TB), 0, s_, buf_, base[i], q.n, cb, lim, werr);
+        int lo = 0;
+        for (int a = 0; a < 3; ++a) {
+          const uint32_t len = 1u << di.w[a];
+          if (len > 1u) {
+            const int lb = cb - di.w[a];
+            const size_t lines = q.n << lb;
+            hipLaunchKernelGGL(kp_df_relax, dim3(grid_for(lines)), dim3(TB), 0, s_, buf_, base[i], lines, lb, cb,
+                               len, 1ull << lo, (1ull << lo) - 1ull, lo, lim);
+          }
+          lo += di.w[a];
+        }
+        hipLaunchKernelGGL(kp_df_cap, dim3(grid_for(all)), dim3(TB), 0, s_, buf_, base[i], q.n, cb, (uint32_t)lv.maxd,
+                           lim);
+        if (!launched("distances")) return st_;
+      }
+    } else if (lv.kind == LK_SVO) {
+      const int mode = !deepest ? 0 : (i < dl ? 1 : 2);
+      hipLaunchKernelGGL(kp_write_svo, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.first, q.count, q.masks, base[i], q.n,
+                         mode, mode == 0 ? base[i + 1] : nullptr, mode == 0 ? D[i + 1].masks : nullptr,
+                         mode == 1 ? roff[i + 1] : nullptr, di.j == 0 ? 1 : 0, lim, werr, buf_);
+      if (!launched("svo blocks")) return st_;
+    } else {
+      const uint32_t* kc;
+      const uint64_t* ko;
+      if (!deepest) {
+        kc = D[i + 1].canon;
+        ko = uoff[i + 1];
+      } else if (i < dl) {
+        kc = nullptr;
+        ko = uoff[i + 1];
+      } else {
+        kc = canonL;
+        ko = loffL;
+      }
+      hipLaunchKernelGGL(kp_write_dag, dim3(grid_for(q.n)), dim3(TB), 0, s_, di.j == 0 ? nullptr : q.canon, q.first,
+                         q.count, q.masks, di.j == 0 ? roff[i] : uoff[i], q.n, kc, ko, lim, werr, buf_);
+      if (deepest && i < dl)
+        hipLaunchKernelGGL(kp_write_leaves, dim3(grid_for(D[i + 1].n)), dim3(TB), 0, s_, nullptr, uoff[i + 1],
+                           roff[i + 1], D[i + 1].n, lim, werr, buf_);
+      if (deepest && i == dl)
+        hipLaunchKernelGGL(kp_write_leaves, dim3(grid_for(n_)), dim3(TB), 0, s_, canonL, loffL, nullptr, n_, lim, werr,
+                           buf_);
+      if (!launched("svdag words")) return st_;
+    }
+  }
+  uint32_t herr = 0;
+  uint64_t r0 = 0;
+  if (!fetch(werr, herr) || !fetch(roff[0], r0)) return st_;
+  if (herr || r0 >= total) return stop(HVF_E_DEVICE, "device construction of the paper's layout: a word fell outside the buffer");
+  const uint32_t root = (uint32_t)r0;
+  if (!hip(hipMemcpyAsync(buf_, &root, sizeof(uint32_t), hipMemcpyHostToDevice, s_), "hipMemcpyAsync") ||
+      !hip(hipStreamSynchronize(s_), "hipStreamSynchronize"))
+    return st_;
+  // 7. statistics, as the host builder counts them: Raw levels their sub-volumes; SVO levels
+  //    their roots and every child entry; SVDAG levels their roots and stored children.
+  B.nvox = n_;
+  B.level_nodes.assign(nlev, 0);
+  for (int i = 0; i <= dl; ++i) {
+    const DepthInfo& di = L.d[i];
+    const LevelSpec& lv = S.lv[di.level];
+    if (lv.kind == LK_RAW || di.j == 0) B.level_nodes[di.level] += D[i].n;
+    if (lv.kind == LK_SVO && di.j > 0) B.level_nodes[di.level] += D[i].n;
+    if (lv.kind == LK_DAG && di.j > 0) B.level_nodes[di.level] += stored[i];
+    const bool deepest = lv.kind != LK_RAW && di.j == lv.e[0] - 1;
+    if (deepest && lv.kind == LK_SVO) B.level_nodes[di.level] += i < dl ? D[i + 1].n : n_;
+    if (deepest && lv.kind == LK_DAG) B.level_nodes[di.level] += i < dl ? D[i + 1].n : storedL;
+  }
+  B.depth_nodes.assign(nd, 0);
+  B.depth_offset.assign(nd, 0);
+  B.depth_words.assign(nd, 0);
+  *nwords = (size_t)total;
+  *dbuf = buf_;
+  buf_ = nullptr;
+  return HVF_OK;
+}
 }  // namespace
 }  // namespace hvf
 
@@ -804,7 +1400,6 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   std::string err;
   hvf_status st = hvf::parse_spec(format_spec, spec, err);
   if (st != HVF_OK) return devbuild_fail(st, err);
-  if (spec.paper) return devbuild_fail(HVF_E_UNSUPPORTED, "device construction builds the library's own layout only");
   if (spec.regions)
     return devbuild_fail(HVF_E_UNSUPPORTED, "device construction builds one buffer of 32-bit pointers (no --depth-buffers)");
   if (n && !d_morton) return devbuild_fail(HVF_E_INPUT, "null Morton code array");
@@ -812,9 +1407,10 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   hvf_volume* v = new (std::nothrow) hvf_volume();
   if (!v) return devbuild_fail(HVF_E_NOMEM, "host allocation failed");
   v->spec = spec;
-  v->layout = hvf::make_layout(spec);
+  v->layout = spec.paper ? hvf::make_paper_layout(spec) : hvf::make_layout(spec);
   if (n == 0) {
-    st = hvf::build_words(v->spec, v->layout, nullptr, 0, v->built, err);
+    st = spec.paper ? hvf::build_paper_words(v->spec, v->layout, nullptr, 0, v->built, err)
+                    : hvf::build_words(v->spec, v->layout, nullptr, 0, v->built, err);
     if (st == HVF_OK) st = hvf_upload(v, stream);
     if (st != HVF_OK) {
       hvf_free(v);
@@ -832,7 +1428,7 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   size_t nwords = 0;
   {
     hvf::DeviceBuilder b(v->spec, v->layout, d_morton, n, (hipStream_t)stream);
-    st = b.run(v->built, &dbuf, &nwords);
+    st = spec.paper ? b.run_paper(v->built, &dbuf, &nwords) : b.run(v->built, &dbuf, &nwords);
     if (st != HVF_OK) {
       const std::string m = b.error();
       hvf_free(v);

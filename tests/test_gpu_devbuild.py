@@ -1,8 +1,9 @@
 """Device construction (hvf_build_device) through the C-ABI.
 
 A device-built volume must hold the host builder's word buffer word for word (same
-layout, same SVDAG de-duplication, same statistics), and tracing it must match the
-oracle element by element (hit and xyz bit-exact, t within 1e-6 relative).
+layout, same SVDAG de-duplication, same statistics), in the library's layout and in the
+paper's (--paper-layout, whose host words the oracle pins on the CPU), and tracing it must
+match the oracle element by element (hit and xyz bit-exact, t within 1e-6 relative).
 """
 import numpy as np
 import pytest
@@ -158,3 +159,66 @@ def test_host_copy_on_demand(H, tmp_path):
     assert np.array_equal(dev.words(), host.words())
     rays = W.random_rays(3, (128, 128, 128), 20000)
     assert np.array_equal(gpu_trace(back, rays), gpu_trace(dev, rays))
+
+
+# ---------------------------------------------------------------- the paper's word layout
+PAPER_MORE = ["R(1,0,2) R(2,2,2)", "R(3,2,4)", "R(1,0,2) S(2)", "R(1,0,2) G(1) R(1,1,1)", "D(3,2,4,5) R(1,1,1)",
+              "G(6) --whole-level-dedup", "G(3) G(3) --whole-level-dedup", "S(2) G(2) R(1,1,1) --whole-level-dedup",
+              "D(2,2,2,4) D(2,2,2,6) D(3,3,3,6)", "S(1) G(1) R(1,1,1)", "R(0,0,0) R(2,2,2)", "G(1)", "S(1)",
+              "R(1,1,1)", "D(2,1,0,9) D(2,2,2,1)", "R(2,1,0) G(2) --whole-level-dedup"]
+
+
+@pytest.mark.parametrize("spec", SPECS_8 + DF_SPECS + PAPER_MORE)
+def test_paper_layout_words(H, spec):
+    """Every type sequence, DF levels and non-cubic or one-cell tops, at four densities."""
+    ex = H.Volume(spec).info()["extent_log2"]
+    for seed, p in ((1, 0.05), (2, 0.2), (3, 0.6), (4, 1.0)):
+        same_volume(H, spec + " --paper-layout", W.scene_bernoulli(seed, ex[0], ex[1], ex[2], p))
+
+
+@pytest.mark.parametrize("spec", ["G(6)", "G(3) G(3)", "G(6) --whole-level-dedup", "G(3) G(3) --whole-level-dedup",
+                                  "S(2) G(4)", "G(4) R(2,2,2)", "R(2,2,2) G(2) R(2,2,2)", "G(2) G(2) G(2)",
+                                  "S(2) G(2) G(2) --whole-level-dedup"])
+def test_paper_layout_repetitive_scene(H, spec):
+    """A periodic pattern: the first of many equal SVDAG children (and leaves) is the stored one."""
+    xyz = np.stack(np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij"), -1).reshape(-1, 3)
+    keep = ((xyz[:, 0] % 8) < 3) & ((xyz[:, 1] % 4) != 1) & (((xyz[:, 2] + xyz[:, 0] // 16) % 8) < 5)
+    codes = np.sort(W.morton_encode(xyz[keep].astype(np.uint32)))
+    same_volume(H, spec + " --paper-layout", codes)
+
+
+def test_paper_layout_scenes(H):
+    """A 256^3 shell scene in mixed formats, the 512^3 surface formats, and DF caps."""
+    codes = W.scene_shell(4, 8, 12, 6, 1.2)
+    for spec in ["R(4,4,4) R(4,4,4)", "S(8)", "G(8)", "G(8) --whole-level-dedup", "R(6,6,6) G(2)",
+                 "S(4) G(2) R(2,2,2)", "G(5) R(3,3,3)", "R(2,2,2) S(3) G(3) --whole-level-dedup", "D(4,4,4,6) G(4)"]:
+        same_volume(H, spec + " --paper-layout", codes)
+    codes = C.scene(C.SURF512)
+    for spec in C.SURF512["specs"] + C.SURF512_DF:
+        same_volume(H, spec + " --paper-layout", codes)
+    xyz = np.array([[0, 0, 0], [63, 63, 63], [5, 40, 17], [33, 2, 60]], np.uint32)
+    sparse = np.sort(W.morton_encode(xyz))
+    for spec in ["D(6,6,6,99)", "D(6,6,6,1)", "D(3,3,3,40) D(3,3,3,7)", "G(2) D(4,4,4,12)"]:
+        same_volume(H, spec + " --paper-layout", sparse)
+
+
+def test_paper_layout_empty_single_and_full(H):
+    for spec in ["R(3,3,3)", "G(3)", "S(1) R(2,2,2)", "D(3,3,3,4)", "G(1) G(2)"]:
+        for codes in (np.zeros(0, np.uint64), np.array([0], np.uint64), np.array([511], np.uint64),
+                      np.arange(512, dtype=np.uint64)):
+            same_volume(H, spec + " --paper-layout", codes)
+
+
+@pytest.mark.parametrize("spec", EDGE_SPECS + ["D(3,3,3,6)", "S(1) D(2,2,2,6)"])
+def test_paper_layout_device_built_traces(H, spec):
+    """Device-built paper-layout volumes against the oracle: the edge suite, and a 64^3 scene."""
+    codes = codes_of(EDGE_VOX)
+    rays = np.concatenate([r for r, _ in EDGE_CASES])
+    got = gpu_trace(H.Volume.from_device(spec + " --paper-layout", dev_codes(codes)), rays)
+    assert compare(got, oracle.Volume(spec, codes).trace(rays), spec) == 0
+    if spec == EDGE_SPECS[0]:
+        scene = W.scene_solid_noise(1, log2n=6, n_sph=8, rmin=4, rmax=16, noise=0.05)
+        rays = W.camera_rays(1, 0, (64, 64, 64), 128, 128)
+        for sp in ["R(2,2,2) S(2) R(2,2,2)", "G(4) R(2,2,2)", "S(2) G(4) --whole-level-dedup"]:
+            dev = H.Volume.from_device(sp + " --paper-layout", dev_codes(scene))
+            assert compare(gpu_trace(dev, rays), oracle.Volume(sp, scene).trace(rays, nthreads=8), sp) == 0

@@ -97,9 +97,6 @@ def test_paper_layout_counting_and_refusals(H):
         assert e.value.name == "HVF_E_INPUT"
     sc = v.autotune(d)  # skips the schedules this layout refuses
     assert sc.stack_depth == 0 and sc.lds_depths == 0
-    with pytest.raises(H.HvfError) as e:
-        H.Volume.from_device("G(7) --paper-layout", torch.from_numpy(codes.view(np.int64)).cuda())
-    assert e.value.name == "HVF_E_UNSUPPORTED"
 
 
 def test_paper_layout_batched_and_served(H):
