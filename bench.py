@@ -515,7 +515,11 @@ def run_construction(args, torch, H, C, formats_2048=None):
     word buffers are compared word for word."""
     out = []
     specs = formats_2048 or [C.table_spec(sp) for _, k, sp in C.TABLE_FORMATS if k == 11]
-    for cfg, fmts in ((C.SURF512, C.SURF512["specs"] + C.SURF512_DF), (C.SURF2048, specs)):
+    # the paper's word layout: a few 512^3 formats, and one 2048^3 format beside the others
+    paper512 = [sp + " --paper-layout" for sp in ("G(9) --whole-level-dedup", "R(4,4,4) G(5) --whole-level-dedup",
+                                                  "R(4,4,4) S(5)", "D(4,4,4,6) G(5) --whole-level-dedup")]
+    paper2048 = ["G(11) --whole-level-dedup --paper-layout"]
+    for cfg, fmts in ((C.SURF512, C.SURF512["specs"] + C.SURF512_DF + paper512), (C.SURF2048, specs + paper2048)):
         codes = C.scene(cfg)
         d_codes = torch.from_numpy(codes.view(np.int64)).cuda()
         H.Volume.from_device("S(3)", d_codes[:1] * 0).close()  # load the construction kernels
