@@ -23,7 +23,7 @@ struct hvf_batch {
   uint32_t* d_counter = nullptr;
   uint32_t total = 0;
   int max_depth = 1;
-  int kinds = 0;  // the widest kind set of its volumes (hvf::batch_kinds): picks the kernel
+  int kinds = 0;  // hvf::batch_kernel_code of its volumes: picks the kernel
   hvf_batch_opts opts{16, 8, 0, 1};
   unsigned grid = 0;
   hipStream_t cap = nullptr;  // private stream used for graph capture
@@ -106,6 +106,7 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
   if (!b) return fail(HVF_E_NOMEM, "host allocation failed");
   b->opts = o;
   uint64_t total = 0;
+  int common = -1;  // the kernel family every volume shares, else -1
   for (size_t i = 0; i < m; ++i) {
     if (!vols[i] || (n[i] && (!d_rays[i] || !d_hits[i]))) {
       delete b;
@@ -133,6 +134,8 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     it.stacked = F.stacked;
     b->max_depth = std::max(b->max_depth, F.ndepth);
     b->kinds = std::max(b->kinds, hvf::batch_kinds(vols[i]->spec, vols[i]->layout));
+    const int f = hvf::volume_family(vols[i]->spec, vols[i]->layout);
+    common = (i == 0 || common == f) ? f : -1;
     b->items.push_back(it);
     b->dinfo.insert(b->dinfo.end(), F.dinfo, F.dinfo + HVF_MAX_DEPTH);
     total += n[i];
@@ -142,6 +145,7 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     return fail(HVF_E_INPUT, "a batched launch holds fewer than 2^31 rays");
   }
   b->total = (uint32_t)total;
+  b->kinds = hvf::batch_kernel_code(b->kinds, common);
   hipError_t e = hipMalloc(&b->d_items, b->items.size() * sizeof(hvf::BatchItem));
   if (e == hipSuccess) e = hipMalloc(&b->d_dinfo, b->dinfo.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&b->d_counter, 64 * sizeof(uint32_t));

@@ -229,6 +229,19 @@ bool has_df(const Layout& L);
 // Kind set of a volume for the batched kernel: 2 in the paper's layout, 1 with a
 // distance-field depth, else 0.
 inline int batch_kinds(const Spec& s, const Layout& L) { return s.paper ? 2 : (has_df(L) ? 1 : 0); }
+// Kernel code of a batched launch: the widest kind set of its volumes (batch_kinds), or,
+// when every volume falls in one brick-final family (common_family: that family's index,
+// else -1), that family's own kernel: 3 SVDAG over a brick, 4 SVO over a brick, 5 both over
+// a brick, 6 Raw over a brick.
+inline int batch_kernel_code(int kinds, int common_family) {
+  switch (common_family) {
+    case 1: return 3;
+    case 2: return 4;
+    case 8: return 5;
+    case 3: return 6;
+    default: return kinds;
+  }
+}
 
 // One batch of the batched launch: a volume and its ray / hit arrays. Rays of all
 // batches form one index space; batch b owns indices [first, first + n).

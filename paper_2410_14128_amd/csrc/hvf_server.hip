@@ -162,10 +162,13 @@ hvf_status launch_step(hvf_server* S, Step& st) {
   uint64_t total = 0;
   int max_depth = 1;
   int kinds = 0;
+  int common = -1;  // the kernel family every request's volume shares, else -1
   for (size_t i = 0; i < m; ++i) {
     Request& r = *st.reqs[i];
     hvf_volume* v = S->vols[r.vol];
     kinds = std::max(kinds, hvf::batch_kinds(v->spec, v->layout));
+    const int f = hvf::volume_family(v->spec, v->layout);
+    common = (i == 0 || common == f) ? f : -1;
     const hvf::DevFormat F = hvf::make_devformat(v->layout, v->spec, v->dbuf);
     uint8_t* hr = S->h_arena + r.off;
     if (r.n && !r.src_pinned) std::memcpy(hr, r.src, r.n * sizeof(hvf_ray));
@@ -197,6 +200,7 @@ hvf_status launch_step(hvf_server* S, Step& st) {
     e = hipMemcpyAsync(st.d_dinfo, st.h_dinfo, m * HVF_MAX_DEPTH * sizeof(uint32_t), hipMemcpyHostToDevice, st.stream);
   if (e != hipSuccess) return fail(HVF_E_DEVICE, std::string("server upload: ") + hipGetErrorString(e));
   unsigned grid = 0;
+  kinds = hvf::batch_kernel_code(kinds, common);
   hvf_status s = hvf::batch_grid((uint32_t)m, max_depth, kinds, S->opts.blocks_per_cu, &grid);
   if (s != HVF_OK) return s;
   if (total)

@@ -1503,8 +1503,19 @@ size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
   return words * 4 + (size_t)max_depth * BLOCK * sizeof(uint2);
 }
 
-// kinds: 0 = the library's layout without distance-field levels, 1 = with them, 2 = some
-// volume in the paper's word layout (the batched kernel is compiled for that kind set).
+// kinds (batch_kernel_code): 0 = the library's layout without distance-field levels, 1 =
+// with them, 2 = some volume in the paper's word layout (the batched kernel is compiled for
+// that kind set); 3..6 = every volume in one brick-final family (its own kernel).
+#define HVF_BATCH_SWITCH(kinds, LAUNCH)  \
+  switch (kinds) {                       \
+    case 2: LAUNCH(FAM_ANY); break;      \
+    case 1: LAUNCH(FAM_ALL); break;      \
+    case 3: LAUNCH(FAM_DAG_BRICK); break; \
+    case 4: LAUNCH(FAM_SVO_BRICK); break; \
+    case 5: LAUNCH(FAM_OCT_BRICK); break; \
+    case 6: LAUNCH(FAM_RAW_BRICK); break; \
+    default: LAUNCH(FAM_NODF); break;    \
+  }
 hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_cu, unsigned* grid) {
   if (g_cu_count < 0) {
     int dev = 0;
@@ -1517,12 +1528,11 @@ hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_
   }
   int per_cu = 0;
   const size_t lds = batch_lds_bytes(nitems, max_depth);
-  const hipError_t oe =
-      kinds == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ANY>, BLOCK, lds)
-      : kinds == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_ALL>, BLOCK, lds)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAM_NODF>, BLOCK, lds);
-  if (oe != hipSuccess ||
-      per_cu < 1)
+  hipError_t oe = hipSuccess;
+#define HVF_BATCH_OCCUPANCY(FAMV) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch_kernel<FAMV>, BLOCK, lds)
+  HVF_BATCH_SWITCH(kinds, HVF_BATCH_OCCUPANCY)
+#undef HVF_BATCH_OCCUPANCY
+  if (oe != hipSuccess || per_cu < 1)
     per_cu = 1;
   if (blocks_per_cu > 0 && blocks_per_cu < per_cu) per_cu = blocks_per_cu;
   *grid = (unsigned)(g_cu_count * per_cu);
@@ -1535,15 +1545,11 @@ hvf_status launch_trace_batch(const BatchItem* d_items, const uint32_t* d_dinfo,
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, d_counter, 0u, (size_t)1);
   hvf_status st = launch_check("fill");
   if (st != HVF_OK) return st;
-  if (kinds == 2)
-    hipLaunchKernelGGL(trace_batch_kernel<FAM_ANY>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
-                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
-  else if (kinds == 1)
-    hipLaunchKernelGGL(trace_batch_kernel<FAM_ALL>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
-                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
-  else
-    hipLaunchKernelGGL(trace_batch_kernel<FAM_NODF>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s,
-                       d_items, d_dinfo, nitems, total, d_counter, refill, inner);
+#define HVF_LAUNCH_BATCH(FAMV)                                                                                       \
+  hipLaunchKernelGGL(trace_batch_kernel<FAMV>, dim3(grid), dim3(BLOCK), batch_lds_bytes(nitems, max_depth), s, d_items, \
+                     d_dinfo, nitems, total, d_counter, refill, inner)
+  HVF_BATCH_SWITCH(kinds, HVF_LAUNCH_BATCH)
+#undef HVF_LAUNCH_BATCH
   return launch_check("batched trace");
 }
 

@@ -103,3 +103,39 @@ def test_batch_autotune_keeps_results(H, cases):
     for (spec, *_, ref), h in zip(cases, b.hits):
         assert torch.equal(h, ref), spec
     b.close()
+
+
+@pytest.mark.parametrize("family", [["G(3) R(2,2,2)", "G(4) R(3,3,3) --whole-level-dedup", "G(2) G(2) R(2,2,2)"],
+                                    ["S(3) R(2,2,2)", "S(4) R(3,3,3)", "S(2) S(1) R(2,2,2)"],
+                                    ["S(2) G(2) R(2,2,2)", "G(3) R(2,2,2)", "S(3) R(3,3,3)"],
+                                    ["R(2,2,2) R(3,3,3)", "R(3,3,3) R(2,2,2)", "R(1,1,1) R(2,2,2) R(2,2,2)"]],
+                         ids=["svdag-brick", "svo-brick", "octree-brick", "raw-brick"])
+def test_batches_of_one_family(H, family):
+    """Batches whose volumes all fall in one brick-final family run that family's own
+    batched kernel; every batch's hits still equal hvf_trace of that batch alone, and the
+    server's steps over such volumes too."""
+    import torch
+    vols, rays, refs = [], [], []
+    for i, spec in enumerate(family * 2):
+        k = H.Volume(spec).info()["extent_log2"][0]
+        codes = W.scene_shell(200 + i, k, max(4, (1 << k) // 16), 2, 1.4)
+        v = H.Volume(spec, codes)
+        r = np.concatenate([W.random_rays(300 + i, (1 << k,) * 3, 2000), W.camera_rays(300 + i, 0, (1 << k,) * 3, 48, 32)])
+        d = torch.from_numpy(r).cuda()
+        vols.append(v)
+        rays.append(d)
+        refs.append(v.trace(d, sched=H.schedule()).clone())
+    b = H.Batch(vols, rays)
+    for h in b.hits:
+        h.fill_(-7)
+    b.run()
+    torch.cuda.synchronize()
+    for spec, h, ref in zip(family * 2, b.hits, refs):
+        assert torch.equal(h, ref), spec
+    b.close()
+    srv = H.Server(64 << 20, max_slots=16, max_steps=2)
+    ids = [srv.add_volume(v) for v in vols]
+    rid = [srv.submit(ids[i], rays[i].cpu().numpy()) for i in range(len(vols))]
+    for r, ref in zip(rid, refs):
+        assert np.array_equal(srv.wait(r)[0], ref.cpu().numpy())
+    srv.close()
