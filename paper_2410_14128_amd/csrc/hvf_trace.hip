@@ -1010,7 +1010,9 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
     float e = 0.0f;
     int q[3] = {0, 0, 0}, nd = 0;
     const int k = min(kf, w.d);  // an ancestor: the nodes above it are on the donor's stack
-    if (run && k >= 1 && (w.R.t1 - w.t) > tv) {
+    const bool cand = run && k >= 1 && (w.R.t1 - w.t) > tv;
+    if (__ballot(cand) == 0ull) continue;  // no walk long enough to fork
+    if (cand) {
       e = w.node_exit(fm, k, q, nd);
       want = e < w.R.t1;
       if (!want) kf = k + 1;  // that node reaches t1: try the next depth next time
