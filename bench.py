@@ -966,7 +966,7 @@ def main():
                     help="run one workload only (for profiling); prints no bench line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding over several GPUs is designed, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -56,7 +56,7 @@ typedef enum hvf_status {
   HVF_E_OVERFLOW = 3,    /* the built format would need 2^32 words or more */
   HVF_E_NOMEM = 4,       /* host or device allocation failed, or a memory budget is exceeded */
   HVF_E_DEVICE = 5,      /* a HIP runtime error; the message names it */
-  HVF_E_UNSUPPORTED = 6, /* a valid request this build does not implement */
+  HVF_E_UNSUPPORTED = 6, /* a valid request the library does not implement */
   HVF_E_STATE = 7        /* call not valid in the object's current state */
 } hvf_status;
 
