@@ -138,10 +138,14 @@ def test_surface2048_split_schedule(H, surf2048, sd):
 
 @pytest.mark.parametrize("sd", [dict(steal=1, steal_len=8), dict(steal=4, steal_len=16),
                                 dict(steal=8, steal_len=64),
-                                dict(steal=4, steal_len=8, lds_depths=3)], ids=lambda d: str(d))
+                                dict(steal=4, steal_len=8, lds_depths=3),
+                                dict(steal=1, steal_len=2, steal_idle=16, interleave=1),
+                                dict(interleave=1)], ids=lambda d: str(d))
 def test_surface2048_steal_schedule(H, surf2048, sd):
     """Whole 1080p frames, primary and bounce rays, traced with walks split among the idle
-    lanes of each wave equal the plain schedule bit for bit, and sampled rays the oracle."""
+    lanes of each wave (and with rays interleaved across waves, the benchmark's schedule of
+    the one-frame bounce launch) equal the plain schedule bit for bit, and sampled rays the
+    oracle."""
     import torch
     cfg, codes, prim, idx, ref_p, bounce, ref_b, rnd, ref_r = surf2048
     vol = H.Volume("G(7) R(4,4,4) --whole-level-dedup", codes)
