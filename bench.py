@@ -91,13 +91,25 @@ def traffic_from_profile(name: str, kernel: str):
 
 
 def time_launches(fn_list, steps, warmup):
-    """Run a step = every fn in fn_list once, timing each launch with events on the
-    current (launch) stream. Returns (ms_per_step, per-launch mean ms list)."""
+    """Run a step = every fn in fn_list once, with events on the current (launch) stream
+    around the timed steps. Returns (ms_per_step, per-launch mean ms list). A step of one
+    launch is timed by the events around its `steps` back-to-back launches alone (event
+    pairs around each launch would add their own gaps to it); steps of several launches also
+    record an event pair around each launch, to split the step between them."""
     import torch
     for _ in range(warmup):
         for fn in fn_list:
             fn()
     torch.cuda.synchronize()
+    if len(fn_list) == 1:
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(steps):
+            fn_list[0]()
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        return ms, [ms]
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in fn_list]
           for _ in range(steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -938,8 +950,8 @@ def cpu_baseline(wait_oracle, rays):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sample", type=int, default=16384, help="rays per view for the byte model")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-2048", action="store_true", help="skip the 2048^3 leg (both formats, 8 frames)")
