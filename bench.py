@@ -71,10 +71,15 @@ def byte_model(vol, rays_sample, cap=4096):
             float(cnt.double().mean().item()), over, hits)
 
 
-def traffic_from_profile(name: str, kernel: str):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by the same
-    counter's reading for a plain 1 GiB copy) from the committed rocprofv3 PMC summary, or
-    None when absent, taken for another kernel or with a different kernel source."""
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs, each issuing one wave64 VALU instruction per
+# 4 cycles (16 lanes per cycle) at 2.4 GHz, in wave instructions per second.
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+
+
+def profile_entry(name: str, kernel: str):
+    """The committed rocprofv3 summary entry of `kernel` on workload `name`
+    (profiles/pmc_traffic.json), or None when absent, taken for another kernel or with a
+    different kernel source."""
     p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(p):
         return None
@@ -87,7 +92,15 @@ def traffic_from_profile(name: str, kernel: str):
     w = d.get("workloads", {}).get(name)
     if w is None or w.get("kernel") != kernel:
         return None
-    return round(float(w["bytes_per_launch"]))
+    return w
+
+
+def traffic_from_profile(name: str, kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by the same
+    counter's reading for a plain 1 GiB copy) from the committed rocprofv3 PMC summary, or
+    None when absent, taken for another kernel or with a different kernel source."""
+    w = profile_entry(name, kernel)
+    return None if w is None else round(float(w["bytes_per_launch"]))
 
 
 def time_launches(fn_list, steps, warmup):
@@ -203,6 +216,16 @@ def run_headline(args, torch, H, W, C):
     if roofline["traffic"] is not None:
         roofline["traffic_gbs"] = round(roofline["traffic"] / (avg_ms * 1e-3) / 1e9, 1)
         roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+    # The launch is bound by VALU issue rather than HBM: the committed SQ_INSTS_VALU count per
+    # launch over the same launch time, against the chip's issue rate.
+    ent = profile_entry("headline-bounce-2048", kernel)
+    if ent is not None and "valu_wave_insts_per_launch" in ent:
+        rate = ent["valu_wave_insts_per_launch"] / (avg_ms * 1e-3)
+        roofline["valu_issue"] = {"bound": "alu", "achieved": round(rate / 1e9, 1),
+                                  "peak": round(VALU_PEAK_WAVE_INSTS / 1e9, 1),
+                                  "unit": "G wave64 VALU instructions/s",
+                                  "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+                                  "insts_per_launch": ent["valu_wave_insts_per_launch"]}
     log(f"[bench] headline: {ms * 1e3:.1f} us per step, {value:.1f} Mrays/s; {kernel} {avg_ms * 1e3:.1f} us, "
         f"B_ray {bs:.0f} B, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of HBM roofline); "
         f"hits identical to the plain schedule: {same}")
