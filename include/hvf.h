@@ -267,7 +267,9 @@ typedef struct hvf_batch_opts {
 /* Describe a batched launch over m batches (1 <= m <= 256; total rays < 2^31): volume
  * vols[i] traces d_rays[i][0..n[i]) into d_hits[i]. The pointers are captured: the same
  * device buffers are read and written by every hvf_batch_run. Uploads the volumes.
- * Volumes must outlive the batch. opts may be NULL (defaults). */
+ * Volumes must outlive the batch. opts may be NULL (defaults). Volumes with per-depth
+ * regions (hvf_info.depth_buffers, e.g. past 2^32 words) may sit beside any others; the
+ * launch then runs the region-aware kernel, which compiles every node kind in. */
 hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_rays, const size_t* n,
                             hvf_hit* const* d_hits, size_t m, const hvf_batch_opts* opts, hvf_batch** out);
 
@@ -312,7 +314,8 @@ typedef struct hvf_serve_stats {
  * ignored). max_slots = max_steps = 1 serves one request at a time in arrival order. */
 hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_steps, const hvf_batch_opts* opts,
                              hvf_server** out);
-/* Make a volume resident (uploads it); it must outlive the server. */
+/* Make a volume resident (uploads it); it must outlive the server. Volumes with per-depth
+ * regions are served like any other (steps holding one run the region-aware kernel). */
 hvf_status hvf_server_add_volume(hvf_server* s, hvf_volume* vol, int* vol_id);
 /* Queue a request: n host rays, results into n host hits. Non-blocking. Both arrays must
  * stay valid until the request completes. Rays in pinned host memory are copied to the

@@ -108,12 +108,20 @@ hvf_status hvf_upload(hvf_volume* v, void* stream) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  const size_t bytes = v->built.words.size() * sizeof(uint32_t);
+  const size_t nw = v->built.words.size(), bytes = nw * sizeof(uint32_t);
   uint32_t* p = nullptr;
   // Four spare zero words after the buffer: the kernels read 8 bytes at any word index.
-  e = hipMalloc(&p, bytes + HVF_BUFFER_PAD_WORDS * sizeof(uint32_t));
+  // With per-depth regions, the table of region starts follows (hvf::device_region_table).
+  hvf::DevFormat R{};
+  hvf::set_regions(R, v->built);
+  const size_t alloc_words =
+      v->built.regions ? hvf::region_table_word(nw) + 2 * HVF_MAX_DEPTH : nw + HVF_BUFFER_PAD_WORDS;
+  e = hipMalloc(&p, alloc_words * sizeof(uint32_t));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc of the word buffer");
-  e = hipMemsetAsync(p + v->built.words.size(), 0, HVF_BUFFER_PAD_WORDS * sizeof(uint32_t), (hipStream_t)stream);
+  e = hipMemsetAsync(p + nw, 0, HVF_BUFFER_PAD_WORDS * sizeof(uint32_t), (hipStream_t)stream);
+  if (e == hipSuccess && v->built.regions)
+    e = hipMemcpyAsync(p + hvf::region_table_word(nw), R.rbase, sizeof(R.rbase), hipMemcpyHostToDevice,
+                       (hipStream_t)stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p, v->built.words.data(), bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);

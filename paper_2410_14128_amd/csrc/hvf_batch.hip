@@ -107,14 +107,11 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
   b->opts = o;
   uint64_t total = 0;
   int common = -1;  // the kernel family every volume shares, else -1
+  bool regions = false;  // some volume has per-depth regions
   for (size_t i = 0; i < m; ++i) {
     if (!vols[i] || (n[i] && (!d_rays[i] || !d_hits[i]))) {
       delete b;
       return fail(HVF_E_INPUT, "null volume or buffer in batch " + std::to_string(i));
-    }
-    if (vols[i]->built.regions) {
-      delete b;
-      return fail(HVF_E_UNSUPPORTED, "batches do not hold volumes with per-depth regions (batch " + std::to_string(i) + ")");
     }
     st = hvf_upload(vols[i], nullptr);
     if (st != HVF_OK) {
@@ -132,6 +129,8 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     for (int a = 0; a < 3; ++a) it.ext[a] = F.ext[a];
     it.ndepth = F.ndepth;
     it.stacked = F.stacked;
+    it.rtab = hvf::device_region_table(vols[i]);
+    regions = regions || vols[i]->built.regions;
     b->max_depth = std::max(b->max_depth, F.ndepth);
     b->kinds = std::max(b->kinds, hvf::batch_kinds(vols[i]->spec, vols[i]->layout));
     const int f = hvf::volume_family(vols[i]->spec, vols[i]->layout);
@@ -145,7 +144,7 @@ hvf_status hvf_batch_create(hvf_volume* const* vols, const hvf_ray* const* d_ray
     return fail(HVF_E_INPUT, "a batched launch holds fewer than 2^31 rays");
   }
   b->total = (uint32_t)total;
-  b->kinds = hvf::batch_kernel_code(b->kinds, common);
+  b->kinds = hvf::batch_kernel_code(b->kinds, common, regions);
   hipError_t e = hipMalloc(&b->d_items, b->items.size() * sizeof(hvf::BatchItem));
   if (e == hipSuccess) e = hipMalloc(&b->d_dinfo, b->dinfo.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&b->d_counter, 64 * sizeof(uint32_t));

@@ -233,7 +233,10 @@ inline int batch_kinds(const Spec& s, const Layout& L) { return s.paper ? 2 : (h
 // when every volume falls in one brick-final family (common_family: that family's index,
 // else -1), that family's own kernel: 3 SVDAG over a brick, 4 SVO over a brick, 5 both over
 // a brick, 6 Raw over a brick.
-inline int batch_kernel_code(int kinds, int common_family) {
+// Batches holding a volume with per-depth regions take code 7, the region-aware kernel
+// with every node kind.
+inline int batch_kernel_code(int kinds, int common_family, bool regions) {
+  if (regions) return 7;
   switch (common_family) {
     case 1: return 3;
     case 2: return 4;
@@ -256,6 +259,7 @@ struct BatchItem {
   int32_t ndepth;
   uint32_t stacked;
   uint32_t pad;
+  const uint64_t* rtab;  // per-depth region starts on the device (volumes with regions), else null
 };
 constexpr int HVF_BATCH_MAX_ITEMS = 256;
 
@@ -297,6 +301,18 @@ constexpr int HVF_NUM_COUNTERS = 64;
 // Zero words allocated after a device word buffer, so 8- and 16-byte reads that start at
 // any word of the buffer stay inside the allocation.
 constexpr size_t HVF_BUFFER_PAD_WORDS = 4;
+
+namespace hvf {
+// A volume with per-depth regions keeps its table of 64-bit region starts (as
+// DevFormat::rbase) on the device right after its word buffer and the buffer's spare words,
+// at an even word index, for kernels that hold many volumes (batches, the server).
+inline size_t region_table_word(size_t nwords) { return (nwords + HVF_BUFFER_PAD_WORDS + 1) & ~(size_t)1; }
+// That table's device address, or null (no regions, or not uploaded).
+inline const uint64_t* device_region_table(const hvf_volume* v) {
+  if (!v->built.regions || !v->dbuf) return nullptr;
+  return reinterpret_cast<const uint64_t*>(v->dbuf + region_table_word(v->built.words.size()));
+}
+}  // namespace hvf
 
 // Thread-local error text.
 void hvf_set_error(const std::string& s);

@@ -163,9 +163,11 @@ hvf_status launch_step(hvf_server* S, Step& st) {
   int max_depth = 1;
   int kinds = 0;
   int common = -1;  // the kernel family every request's volume shares, else -1
+  bool regions = false;  // some request's volume has per-depth regions
   for (size_t i = 0; i < m; ++i) {
     Request& r = *st.reqs[i];
     hvf_volume* v = S->vols[r.vol];
+    regions = regions || v->built.regions;
     kinds = std::max(kinds, hvf::batch_kinds(v->spec, v->layout));
     const int f = hvf::volume_family(v->spec, v->layout);
     common = (i == 0 || common == f) ? f : -1;
@@ -183,6 +185,7 @@ hvf_status launch_step(hvf_server* S, Step& st) {
     for (int a = 0; a < 3; ++a) it.ext[a] = F.ext[a];
     it.ndepth = F.ndepth;
     it.stacked = F.stacked;
+    it.rtab = hvf::device_region_table(v);
     st.h_items[i] = it;
     std::memcpy(st.h_dinfo + i * HVF_MAX_DEPTH, F.dinfo, sizeof(F.dinfo));
     max_depth = std::max(max_depth, F.ndepth);
@@ -200,7 +203,7 @@ hvf_status launch_step(hvf_server* S, Step& st) {
     e = hipMemcpyAsync(st.d_dinfo, st.h_dinfo, m * HVF_MAX_DEPTH * sizeof(uint32_t), hipMemcpyHostToDevice, st.stream);
   if (e != hipSuccess) return fail(HVF_E_DEVICE, std::string("server upload: ") + hipGetErrorString(e));
   unsigned grid = 0;
-  kinds = hvf::batch_kernel_code(kinds, common);
+  kinds = hvf::batch_kernel_code(kinds, common, regions);
   hvf_status s = hvf::batch_grid((uint32_t)m, max_depth, kinds, S->opts.blocks_per_cu, &grid);
   if (s != HVF_OK) return s;
   if (total)
@@ -371,7 +374,6 @@ hvf_status hvf_server_create(size_t mem_budget_bytes, int max_slots, int max_ste
 
 hvf_status hvf_server_add_volume(hvf_server* S, hvf_volume* v, int* vol_id) {
   if (!S || !v || !vol_id) return fail(HVF_E_INPUT, "null argument");
-  if (v->built.regions) return fail(HVF_E_UNSUPPORTED, "the server does not hold volumes with per-depth regions");
   hvf_status st = hvf_upload(v, nullptr);
   if (st != HVF_OK) return st;
   std::lock_guard<std::mutex> lk(S->mu);

@@ -174,7 +174,7 @@ struct Fmt {
   gword* buf;
   uint64_t pop_lut;
   const uint32_t* dtab;
-  const uint64_t* rtab;  // per-depth region starts (buffers with per-depth regions)
+  const uint64_t* rtab;  // per-depth region starts (buffers with per-depth regions), or null
   int ext[3];
   uint32_t stacked;  // depths with a node-stack slot
   lword* pre;
@@ -182,6 +182,8 @@ struct Fmt {
   // Kernels are compiled twice, with and without a staged prefix (FAM_PRE), so reads in
   // the common unstaged case carry no per-lane test.
   // ix: a word index, 32-bit, or 64-bit in buffers with per-depth regions.
+  // Start of depth d's region; 0 where a batch item without regions leaves the table null.
+  __device__ __forceinline__ uint64_t region(int d) const { return rtab ? rtab[d] : 0ull; }
   template <uint32_t FAM, class I>
   __device__ __forceinline__ uint32_t w1(I ix) const {
     if ((FAM & FAM_PRE) && ix < npre) return pre[ix];
@@ -340,7 +342,7 @@ struct Walk {
     if (root == 0u) return DONE;
     d = 0;
     info = dtab[0];
-    rb = (FAM & FAM_REGIONS) ? F.rtab[0] : 0ull;
+    rb = (FAM & FAM_REGIONS) ? F.region(0) : 0ull;
     const int cs = di_cs(info);
 #pragma unroll
     for (int a = 0; a < 3; ++a) p[a] = 0;
@@ -465,7 +467,7 @@ struct Walk {
       ++d;
       reach = 0;
       info = dtab[d];
-      if (FAM & FAM_REGIONS) rb = F.rtab[d];
+      if (FAM & FAM_REGIONS) rb = F.region(d);
       const uint2 h = enter<FAM>(F, info, child, cm, rb, mem);
       base = h.x;
       valid = h.y;
@@ -546,7 +548,7 @@ struct Walk {
       base = sv.x;
       valid = sv.y;
       info = dtab[nd];
-      if (FAM & FAM_REGIONS) rb = F.rtab[nd];
+      if (FAM & FAM_REGIONS) rb = F.region(nd);
       d = nd;
       reach = 0;
       const int mask = ~((1 << di_cs(info)) - 1);
@@ -560,7 +562,7 @@ struct Walk {
     base = sv.x;
     valid = sv.y;
     info = dtab[r];
-    if (FAM & FAM_REGIONS) rb = F.rtab[r];
+    if (FAM & FAM_REGIONS) rb = F.region(r);
     for (int k = r; k < nd; ++k) {
       const uint32_t knk = di_nk(info), kl = cell_lin<FAM>(info);
       uint32_t child = 0u;
@@ -578,7 +580,7 @@ struct Walk {
         octree_child<FAM>(F, knk, kl, base, valid, child, cm, rb, mem);
       }
       info = dtab[k + 1];
-      if (FAM & FAM_REGIONS) rb = F.rtab[k + 1];
+      if (FAM & FAM_REGIONS) rb = F.region(k + 1);
       const uint2 h = enter<FAM>(F, info, child, cm, rb, mem);
       base = h.x;
       valid = h.y;
@@ -1211,7 +1213,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
   fm.buf = nullptr;
   fm.pop_lut = 0;
   fm.dtab = dt;
-  fm.rtab = nullptr;  // batches hold no volume with per-depth regions
+  fm.rtab = nullptr;  // per item: its region starts (region-aware kernels only read them)
   fm.ext[0] = fm.ext[1] = fm.ext[2] = 0;
   fm.stacked = 1u;
   fm.pre = nullptr;
@@ -1248,6 +1250,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(const BatchItem* __r
           fm.ext[1] = it.ext[1];
           fm.ext[2] = it.ext[2];
           fm.stacked = it.stacked;
+          fm.rtab = it.rtab;
           hits = reinterpret_cast<int4*>(it.hits);
           ray = id - it.first;
           const float4* rays = reinterpret_cast<const float4*>(it.rays);
@@ -1507,7 +1510,8 @@ size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
 
 // kinds (batch_kernel_code): 0 = the library's layout without distance-field levels, 1 =
 // with them, 2 = some volume in the paper's word layout (the batched kernel is compiled for
-// that kind set); 3..6 = every volume in one brick-final family (its own kernel).
+// that kind set); 3..6 = every volume in one brick-final family (its own kernel); 7 = some
+// volume with per-depth regions (every kind, 64-bit word indices).
 #define HVF_BATCH_SWITCH(kinds, LAUNCH)  \
   switch (kinds) {                       \
     case 2: LAUNCH(FAM_ANY); break;      \
@@ -1516,6 +1520,7 @@ size_t batch_lds_bytes(uint32_t nitems, int max_depth) {
     case 4: LAUNCH(FAM_SVO_BRICK); break; \
     case 5: LAUNCH(FAM_OCT_BRICK); break; \
     case 6: LAUNCH(FAM_RAW_BRICK); break; \
+    case 7: LAUNCH(FAM_ANY | FAM_REGIONS); break; \
     default: LAUNCH(FAM_NODF); break;    \
   }
 hvf_status batch_grid(uint32_t nitems, int max_depth, int kinds, int blocks_per_cu, unsigned* grid) {

@@ -9,7 +9,8 @@ so a format may pass 2^32 words.
   depth of pointer grids just below 2^32 words and a depth of bricks, 4.31 G words in all)
   builds, uploads and traces at parity with the oracle, which traces the same voxels built
   as R(3,4,4) G(12) (every format of one volume has the same first hits, pinned on the CPU).
-* Batches, the server and device construction refuse such volumes.
+* Batches and the server hold such volumes beside others (the batched launch then runs the
+  region-aware kernel); device construction refuses them.
 """
 import numpy as np
 import pytest
@@ -66,17 +67,47 @@ def test_regions_trace_like_one_buffer(H, spec):
     assert torch.equal(torch.where(mask, l1, 0), torch.where(mask, l2, 0))
 
 
-def test_regions_refused_by_batches_server_and_device_build(H):
+def test_regions_in_batches_and_server(H):
+    """Volumes with per-depth regions batch and serve beside volumes without them (the
+    batched launch then runs the region-aware kernel with every node kind): every batch's
+    and request's hits equal hvf_trace of that volume alone."""
+    import torch
+    specs = ["G(4) R(3,3,3) --whole-level-dedup --depth-buffers", "S(3) R(4,4,4)", "R(2,2,2) S(2) G(3) --depth-buffers",
+             "S(2) G(2) R(3,3,3) --paper-layout", "D(3,3,3,6) R(2,2,2) R(2,2,2) --depth-buffers", "G(7)"]
+    vols, rays, refs = [], [], []
+    for j, spec in enumerate(specs):
+        codes = W.scene_shell(30 + j, 7, 8, 4, 1.4)
+        r = np.concatenate([W.random_rays(40 + j, (128,) * 3, 3000), W.camera_rays(40 + j, j % 3, (128,) * 3, 80, 60)])
+        v = H.Volume(spec, codes)
+        d = torch.from_numpy(r).cuda()
+        vols.append(v)
+        rays.append(d)
+        refs.append(v.trace(d, sched=H.schedule()))
+    torch.cuda.synchronize()
+    for order in (list(range(len(specs))), [1, 3, 5, 0, 2, 4], [0]):
+        bt = H.Batch([vols[j] for j in order], [rays[j] for j in order])
+        got = bt.run()
+        torch.cuda.synchronize()
+        for j, g in zip(order, got):
+            assert torch.equal(g, refs[j]), (order, specs[j])
+        bt.close()
+    srv = H.Server(256 << 20, max_slots=8, max_steps=2)
+    ids = [srv.add_volume(v) for v in vols]
+    host = [r.cpu().numpy() for r in rays]
+    reqs = [(j, srv.submit(ids[j], host[j][k::3])) for j in range(len(specs)) for k in range(3)]
+    for j, rid in reqs:
+        h, _ = srv.wait(rid)
+        k = [r for jj, r in reqs if jj == j].index(rid)
+        assert np.array_equal(h, refs[j].cpu().numpy()[k::3]), specs[j]
+    srv.close()
+
+
+def test_regions_refused_by_device_build(H):
     import torch
     codes = W.scene_shell(12, 6, 6, 2, 1.4)
-    v = H.Volume("G(3) R(3,3,3) --depth-buffers", codes)
-    d = torch.from_numpy(W.random_rays(1, (64,) * 3, 100)).cuda()
-    for make in (lambda: H.Batch([v], [d]), lambda: H.Server(1 << 20).add_volume(v),
-                 lambda: H.Volume.from_device("G(3) R(3,3,3) --depth-buffers",
-                                              torch.from_numpy(codes.view(np.int64)).cuda())):
-        with pytest.raises(H.HvfError) as e:
-            make()
-        assert e.value.name == "HVF_E_UNSUPPORTED"
+    with pytest.raises(H.HvfError) as e:
+        H.Volume.from_device("G(3) R(3,3,3) --depth-buffers", torch.from_numpy(codes.view(np.int64)).cuda())
+    assert e.value.name == "HVF_E_UNSUPPORTED"
 
 
 def test_volume_past_2_32_words(H):
@@ -107,8 +138,15 @@ def test_volume_past_2_32_words(H):
     d = torch.from_numpy(rays).cuda()
     got = v.trace(d, sched=H.schedule())
     stolen = v.trace(d, sched=H.schedule(steal=1, steal_len=2, steal_idle=16))
+    # the same rays in a batched launch beside a small volume (64-bit word indices there too)
+    small = H.Volume("G(3) R(2,2,2)", W.scene_shell(5, 5, 4, 2, 1.4))
+    ds = torch.from_numpy(W.random_rays(5, (32,) * 3, 2000)).cuda()
+    bt = H.Batch([small, v, small], [ds, d, ds])
+    bh = bt.run()
     torch.cuda.synchronize()
-    assert torch.equal(got, stolen)
+    assert torch.equal(got, stolen) and torch.equal(bh[1], got)
+    assert torch.equal(bh[0], small.trace(ds)) and torch.equal(bh[2], bh[0])
+    bt.close()
     got = got.cpu().numpy()
     assert (got[:3000, 0] >= 0).mean() > 0.5
     v.close()
