@@ -178,7 +178,10 @@ hvf_status hvf_build(const char* format_spec, const uint64_t* morton, size_t n, 
  *   the paper's write order (every node after its children's sub-trees) is computed from
  *   per-node subtree word counts, summed bottom-up and turned into offsets top-down; an
  *   SVDAG child or leaf is stored if it is the first equal one of its sub-volume (or level)
- *   in that order. Not with --depth-buffers (HVF_E_UNSUPPORTED).
+ *   in that order; --paper-layout is not combined with --depth-buffers (HVF_E_UNSUPPORTED).
+ *   With --depth-buffers, or by itself once the library's layout reaches 2^32 words (2^31
+ *   with a DF pointer grid), the buffer is split into per-depth regions with
+ *   region-relative pointers, exactly as hvf_build does.
  * d_morton, n: device pointer to n strictly ascending Morton codes (x bit 0, y bit 1,
  *   z bit 2 of each 3-bit group), all inside the volume; n < 2^31. Read only, not retained.
  * out: receives a new handle owned by the caller (release with hvf_free); its device

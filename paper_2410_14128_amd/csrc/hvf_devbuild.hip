@@ -912,20 +912,32 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     auxb[i] = cur;
     cur += D[i].aux;
   }
-  if (cur >= (df_ptr ? (1ull << 31) : (1ull << 32)))
-    return stop(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, beyond " + (df_ptr ? "31" : "32") +
-                                    "-bit word offsets" +
-                                    (df_ptr ? " (a DF pointer grid keeps the top bit for empty cells)" : ""));
-  const size_t total = (size_t)cur + HVF_BUFFER_PAD_WORDS;
+  // One buffer of 32-bit pointers while it fits (31 bits below a DF pointer grid, whose
+  // cells keep the top bit for empty ones); past that, or with --depth-buffers, per-depth
+  // regions with pointers relative to the region they point into, each within that bound.
+  bool regions = S.regions;
+  if (!regions && cur >= (df_ptr ? (1ull << 31) : (1ull << 32))) regions = true;
+  if (regions)
+    for (int i = 0; i < nd; ++i) {
+      const uint64_t size = ((i + 1 < nd) ? base[i + 1] : cur) - base[i] + REGION_BIAS;
+      const bool below_df = i > 0 && L.d[i - 1].nk == NK_DF_PTR;
+      if (size >= (below_df ? (1ull << 31) : (1ull << 32)))
+        return stop(HVF_E_OVERFLOW, "format needs " + std::to_string(cur) + " words, and its depth " +
+                                        std::to_string(i) + " alone " + std::to_string(size) + ", beyond " +
+                                        (below_df ? "31" : "32") + "-bit region-relative pointers");
+    }
+  // Spare zero words after the buffer; with regions, the table of region starts after them.
+  const size_t total = regions ? region_table_word((size_t)cur) + 2 * HVF_MAX_DEPTH : (size_t)cur + HVF_BUFFER_PAD_WORDS;
   if (!hip(hipMalloc(&buf_, total * sizeof(uint32_t)), "hipMalloc of the word buffer") ||
       !hip(hipMemsetAsync(buf_, 0, total * sizeof(uint32_t), s_), "hipMemsetAsync"))
     return st_;
-  // 6. node words with absolute child offsets
+  // 6. node words with absolute child offsets, or offsets relative to the region of the
+  //    depth they point into (the next depth's; an SVO node's pointer array lies in its own)
   for (int i = 0; i <= dl; ++i) {
     const DepthInfo& di = L.d[i];
     const DepthState& q = D[i];
     uint32_t* dst = buf_ + base[i];
-    const uint32_t nb = (i + 1 < nd) ? (uint32_t)base[i + 1] : 0u;
+    const uint32_t nb = regions ? (uint32_t)REGION_BIAS : (i + 1 < nd) ? (uint32_t)base[i + 1] : 0u;
     if (is_brick(di)) {
       const bool blocks = di.nk == NK_BLOCKS || di.nk == NK_DF_BLOCKS;
       const int wx = blocks ? di.w[0] : 0, wy = blocks ? di.w[1] : 0;
@@ -955,7 +967,7 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
                          c.n, di.w[0], di.w[1], i == 0 ? 1 : 0, cells, nb, dst);
     } else if (di.hk == HK_SVO) {
       const int mode = di.nk == NK_SVO_INNER ? 1 : (di.nk == NK_OCT_PTR ? 2 : 0);
-      const uint32_t target = mode == 1 ? nb : (uint32_t)auxb[i];
+      const uint32_t target = mode == 1 ? nb : (uint32_t)(regions ? auxb[i] - base[i] + REGION_BIAS : auxb[i]);
       hipLaunchKernelGGL(k_write_svo, dim3(grid_for(q.n)), dim3(TB), 0, s_, q.masks, q.first,
                          mode == 1 ? D[i + 1].id : nullptr, q.n, mode, target, dst);
       if (mode == 2)
@@ -970,10 +982,17 @@ hvf_status DeviceBuilder::run(Built& B, uint32_t** dbuf, size_t* nwords) {
     }
     if (!launched("write")) return st_;
   }
-  const uint32_t root = (uint32_t)base[0];  // the root is the first node of depth 0
+  // the root is the first node of depth 0
+  const uint32_t root = regions ? (uint32_t)REGION_BIAS : (uint32_t)base[0];
   if (!hip(hipMemcpyAsync(buf_, &root, sizeof(uint32_t), hipMemcpyHostToDevice, s_), "hipMemcpyAsync")) return st_;
+  uint64_t rtab[HVF_MAX_DEPTH] = {};
+  for (int i = 0; i < nd && regions; ++i) rtab[i] = base[i] - REGION_BIAS;
+  if (regions && !hip(hipMemcpyAsync(buf_ + region_table_word((size_t)cur), rtab, sizeof(rtab), hipMemcpyHostToDevice, s_),
+                      "hipMemcpyAsync"))
+    return st_;
   if (!hip(hipStreamSynchronize(s_), "hipStreamSynchronize")) return st_;
   // 7. statistics (the host copy of the words is downloaded when first read)
+  B.regions = regions;
   B.nvox = n_;
   B.depth_nodes.assign(nd, 0);
   B.depth_offset.assign(nd, 0);
@@ -1400,8 +1419,8 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
   std::string err;
   hvf_status st = hvf::parse_spec(format_spec, spec, err);
   if (st != HVF_OK) return devbuild_fail(st, err);
-  if (spec.regions)
-    return devbuild_fail(HVF_E_UNSUPPORTED, "device construction builds one buffer of 32-bit pointers (no --depth-buffers)");
+  if (spec.regions && spec.paper)
+    return devbuild_fail(HVF_E_UNSUPPORTED, "the paper's word layout is one buffer (no --depth-buffers)");
   if (n && !d_morton) return devbuild_fail(HVF_E_INPUT, "null Morton code array");
   if (n > (size_t)INT_MAX) return devbuild_fail(HVF_E_UNSUPPORTED, "a device construction takes fewer than 2^31 codes");
   hvf_volume* v = new (std::nothrow) hvf_volume();
@@ -1435,6 +1454,7 @@ extern "C" hvf_status hvf_build_device(const char* format_spec, const uint64_t* 
       return devbuild_fail(st, m);
     }
   }
+  if (v->built.regions) v->spec.regions = true;  // chosen by the builder past 2^32 words
   v->dbuf = dbuf;
   v->device = dev;
   v->host_pending = true;

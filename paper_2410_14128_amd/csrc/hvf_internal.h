@@ -310,7 +310,7 @@ inline size_t region_table_word(size_t nwords) { return (nwords + HVF_BUFFER_PAD
 // That table's device address, or null (no regions, or not uploaded).
 inline const uint64_t* device_region_table(const hvf_volume* v) {
   if (!v->built.regions || !v->dbuf) return nullptr;
-  return reinterpret_cast<const uint64_t*>(v->dbuf + region_table_word(v->built.words.size()));
+  return reinterpret_cast<const uint64_t*>(v->dbuf + region_table_word(word_count(v)));
 }
 }  // namespace hvf
 

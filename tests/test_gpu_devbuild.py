@@ -114,12 +114,32 @@ def test_edge_suite_device_built(H, spec):
     assert compare(got, ref, spec) == 0
 
 
+@pytest.mark.parametrize("spec", SPECS_8 + DF_SPECS)
+def test_depth_buffers_words(H, spec):
+    """Per-depth regions built on the device: region-relative pointers and the same word
+    positions as the host build, word for word; traces and batched traces agree."""
+    import torch
+    for seed, p in ((1, 0.05), (3, 0.6)):
+        host, dev = same_volume(H, spec + " --depth-buffers", W.scene_bernoulli(seed, 3, 3, 3, p))
+        assert dev.info()["depth_buffers"] and host.info()["depth_buffers"]
+    ext = host.info()["extent_log2"]
+    rays = torch.from_numpy(W.random_rays(8, tuple(1 << e for e in ext), 3000)).cuda()
+    want = host.trace(rays)
+    bt = H.Batch([dev, host], [rays, rays])
+    got = bt.run()
+    torch.cuda.synchronize()
+    assert torch.equal(dev.trace(rays), want) and torch.equal(got[0], want) and torch.equal(got[1], want)
+    bt.close()
+
+
 def test_empty_single_and_full(H):
     for spec in ["R(3,3,3)", "G(3)", "S(1) R(2,2,2)"]:
         same_volume(H, spec, np.zeros(0, np.uint64))
         same_volume(H, spec, np.array([0], np.uint64))
         same_volume(H, spec, np.array([511], np.uint64))
         same_volume(H, spec, np.arange(512, dtype=np.uint64))
+        same_volume(H, spec + " --depth-buffers", np.zeros(0, np.uint64))
+        same_volume(H, spec + " --depth-buffers", np.arange(512, dtype=np.uint64))
 
 
 def test_errors(H):

@@ -10,7 +10,7 @@ so a format may pass 2^32 words.
   builds, uploads and traces at parity with the oracle, which traces the same voxels built
   as R(3,4,4) G(12) (every format of one volume has the same first hits, pinned on the CPU).
 * Batches and the server hold such volumes beside others (the batched launch then runs the
-  region-aware kernel); device construction refuses them.
+  region-aware kernel), and device construction builds them word for word like the host.
 """
 import numpy as np
 import pytest
@@ -102,11 +102,11 @@ def test_regions_in_batches_and_server(H):
     srv.close()
 
 
-def test_regions_refused_by_device_build(H):
+def test_paper_layout_regions_refused_by_device_build(H):
     import torch
     codes = W.scene_shell(12, 6, 6, 2, 1.4)
     with pytest.raises(H.HvfError) as e:
-        H.Volume.from_device("G(3) R(3,3,3) --depth-buffers", torch.from_numpy(codes.view(np.int64)).cuda())
+        H.Volume.from_device("G(3) R(3,3,3) --paper-layout --depth-buffers", torch.from_numpy(codes.view(np.int64)).cuda())
     assert e.value.name == "HVF_E_UNSUPPORTED"
 
 
@@ -147,6 +147,19 @@ def test_volume_past_2_32_words(H):
     assert torch.equal(got, stolen) and torch.equal(bh[1], got)
     assert torch.equal(bh[0], small.trace(ds)) and torch.equal(bh[2], bh[0])
     bt.close()
+    # the same volume built on the device (the builder picks per-depth regions by itself)
+    print("device build", flush=True)
+    dv = H.Volume.from_device(spec, torch.from_numpy(codes.view(np.int64)).cuda())
+    assert dv.info()["depth_buffers"] and dv.info()["num_words"] == info["num_words"]
+    dgot = dv.trace(d, sched=H.schedule())
+    torch.cuda.synchronize()
+    assert torch.equal(dgot, got)
+    wh = v.words()
+    wd = dv.words()
+    assert np.array_equal(wh, wd)
+    del wh, wd, dgot
+    dv.close()
+    del dv
     got = got.cpu().numpy()
     assert (got[:3000, 0] >= 0).mean() > 0.5
     v.close()
