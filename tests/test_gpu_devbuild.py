@@ -114,6 +114,20 @@ def test_edge_suite_device_built(H, spec):
     assert compare(got, ref, spec) == 0
 
 
+def test_depth_buffers_save_and_load(H, tmp_path):
+    """A device-built volume with per-depth regions saves and loads like a host-built one."""
+    import torch
+    spec = "G(3) R(3,3,3) --whole-level-dedup --depth-buffers"
+    codes = W.scene_bernoulli(11, 3, 3, 3, 0.3)
+    host, dev = same_volume(H, spec, codes)
+    p = str(tmp_path / "dev.hvf")
+    dev.save(p)
+    back = H.Volume.load(p)
+    assert back.info() == host.info() and np.array_equal(back.words(), host.words())
+    rays = torch.from_numpy(W.random_rays(12, (64,) * 3, 2000)).cuda()
+    assert torch.equal(back.trace(rays), host.trace(rays))
+
+
 @pytest.mark.parametrize("spec", SPECS_8 + DF_SPECS)
 def test_depth_buffers_words(H, spec):
     """Per-depth regions built on the device: region-relative pointers and the same word
