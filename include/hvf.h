@@ -120,7 +120,12 @@ typedef struct hvf_info {
  *   launch takes ray l * W + w, W = ceil(n / 64), so each wave holds rays from all over the
  *   batch instead of 64 neighbours; hits are still written at each ray's index. This evens
  *   out the work per wave when the walk lengths of neighbouring rays are correlated (the
- *   secondary rays of one image), and costs coherent batches their locality. */
+ *   secondary rays of one image), and costs coherent batches their locality.
+ * rays_per_wave = R (0 meaning 64, else 1..64; R < 64 needs steal > 0 and interleave = 1):
+ *   each wave starts with R rays (lane l < R of wave w takes ray l * W + w, W = ceil(n / R))
+ *   and its other lanes start idle, taking forks from the first step on. A launch of few
+ *   rays then spreads over W waves instead of ceil(n / 64): more waves per SIMD to hide
+ *   each step's latency, at the cost of forks. */
 typedef struct hvf_schedule {
   int32_t persistent;
   int32_t refill;
@@ -140,6 +145,7 @@ typedef struct hvf_schedule {
   int32_t steal_len;    /* voxels; shorter rests are not forked (steal > 0) */
   int32_t steal_idle;   /* idle lanes a wave needs before it forks walks (steal > 0) */
   int32_t interleave;   /* 0 or 1: see above */
+  int32_t rays_per_wave; /* 0 (= 64) or 1..64: see above */
 } hvf_schedule;
 
 /* Build a volume on the host (Sec. 4.1).
@@ -244,7 +250,8 @@ hvf_status hvf_set_schedule(hvf_volume* vol, const hvf_schedule* sched);
  * persistent at full, 2 or 4 blocks per CU with refill thresholds 8/32 and 4 or 16 steps
  * between checks; sorted with cell sides 2^2, 2^4, 2^6; seven split schedules; five
  * stealing schedules; one lane per ray and the five stealing schedules again with
- * interleaved rays), then the best with the deepest LDS prefixes that fit, on the
+ * interleaved rays; the first of those with 32 and with 16 rays per wave), then the best
+ * with the deepest LDS prefixes that fit, on the
  * caller's device ray sample; pick the fastest, store it as the volume's schedule and copy
  * it to *out (may be NULL). d_hits_scratch: n device hits, overwritten. Synchronises
  * hip_stream. Results never depend on the schedule chosen. */

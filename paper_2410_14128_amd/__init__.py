@@ -55,16 +55,17 @@ class hvf_schedule(ctypes.Structure):
                 ("sort", ctypes.c_int32), ("sort_bits", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("stack_depth", ctypes.c_int32), ("lds_depths", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("split_budget", ctypes.c_int32), ("split_rounds", ctypes.c_int32), ("steal", ctypes.c_int32),
-                ("steal_len", ctypes.c_int32), ("steal_idle", ctypes.c_int32), ("interleave", ctypes.c_int32)]
+                ("steal_len", ctypes.c_int32), ("steal_idle", ctypes.c_int32), ("interleave", ctypes.c_int32),
+                ("rays_per_wave", ctypes.c_int32)]
 
 
 def schedule(persistent: int = 0, refill: int = 16, inner: int = 8, sort: int = 0, sort_bits: int = 4,
              blocks_per_cu: int = 0, stack_depth: int = 0, lds_depths: int = 0, split: int = 0,
              split_budget: int = 0, split_rounds: int = 0, steal: int = 0, steal_len: int = 0,
-             steal_idle: int = 1, interleave: int = 0) -> hvf_schedule:
+             steal_idle: int = 1, interleave: int = 0, rays_per_wave: int = 0) -> hvf_schedule:
     """A device schedule for a trace (results never depend on it)."""
     return hvf_schedule(persistent, refill, inner, sort, sort_bits, blocks_per_cu, stack_depth, lds_depths, split,
-                        split_budget, split_rounds, steal, steal_len, steal_idle, interleave)
+                        split_budget, split_rounds, steal, steal_len, steal_idle, interleave, rays_per_wave)
 
 
 def kernel_names(info: dict, sched: dict) -> list:
@@ -90,7 +91,8 @@ def schedule_dict(s: hvf_schedule) -> dict:
     return {"persistent": s.persistent, "refill": s.refill, "inner": s.inner, "sort": s.sort, "sort_bits": s.sort_bits,
             "blocks_per_cu": s.blocks_per_cu, "stack_depth": s.stack_depth, "lds_depths": s.lds_depths,
             "split": s.split, "split_budget": s.split_budget, "split_rounds": s.split_rounds, "steal": s.steal,
-            "steal_len": s.steal_len, "steal_idle": s.steal_idle, "interleave": s.interleave}
+            "steal_len": s.steal_len, "steal_idle": s.steal_idle, "interleave": s.interleave,
+            "rays_per_wave": s.rays_per_wave}
 
 
 class hvf_batch_opts(ctypes.Structure):

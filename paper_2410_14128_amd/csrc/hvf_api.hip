@@ -22,7 +22,8 @@ hvf_status persistent_grid(const DevFormat& F, int blocks_per_cu, unsigned* grid
 hvf_status launch_trace_split(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
                               uint32_t budget, uint32_t klog2, uint32_t rounds, uint32_t* scratch, hipStream_t s);
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, hipStream_t s);
+                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, uint32_t rays_per_wave,
+                              hipStream_t s);
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s);
 hvf_status launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hvf_status trace_sorted(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
@@ -142,8 +143,11 @@ hvf_status check_sched(const hvf_schedule& sc) {
       sc.lds_depths > HVF_MAX_DEPTH || sc.split < 0 || sc.split > 64 || (sc.split & (sc.split - 1)) != 0 ||
       sc.split == 1 || (sc.split && (sc.split_budget < 1 || sc.split_budget > (1 << 20))) || sc.split_rounds < 0 ||
       sc.split_rounds > (int)hvf::HVF_SPLIT_MAX_ROUNDS || (sc.split_rounds && !sc.split) || sc.steal < 0 ||
-      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20) || sc.steal_idle < 1 || sc.steal_idle > 64)) || sc.interleave < 0 || sc.interleave > 1)
+      sc.steal > 64 || (sc.steal & (sc.steal - 1)) != 0 || (sc.steal && (sc.steal_len < 1 || sc.steal_len > (1 << 20) || sc.steal_idle < 1 || sc.steal_idle > 64)) || sc.interleave < 0 || sc.interleave > 1 || sc.rays_per_wave < 0 ||
+      sc.rays_per_wave > 64)
     return fail(HVF_E_INPUT, "schedule field out of range");
+  if (sc.rays_per_wave && sc.rays_per_wave < 64 && !(sc.steal && sc.interleave))
+    return fail(HVF_E_INPUT, "fewer than 64 rays per wave needs the stealing schedule with interleaved rays");
   if (sc.split && (sc.persistent || sc.sort))
     return fail(HVF_E_INPUT, "the split schedule runs without persistent lanes and without sorting");
   if (sc.steal && (sc.persistent || sc.sort || sc.split))
@@ -177,7 +181,7 @@ hvf_status hvf_trace_sched(hvf_volume* v, const hvf_ray* d_rays, size_t n, hvf_h
   if (sc.sort) return hvf::trace_sorted(F, family, d_rays, n, d_hits, sc, s);
   if (sc.steal)
     return hvf::launch_trace_steal(F, family, d_rays, n, d_hits, (uint32_t)sc.steal, (float)sc.steal_len,
-                                   (uint32_t)sc.steal_idle, sc.interleave != 0, s);
+                                   (uint32_t)sc.steal_idle, sc.interleave != 0, (uint32_t)sc.rays_per_wave, s);
   if (sc.split) {
     const uint32_t budget = (uint32_t)sc.split_budget, klog2 = (uint32_t)__builtin_ctz((unsigned)sc.split),
                    rounds = (uint32_t)sc.split_rounds;
@@ -309,6 +313,8 @@ hvf_status hvf_autotune(hvf_volume* v, const hvf_ray* d_sample, size_t n, hvf_hi
     for (const auto& c : steal_cand)
       cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, c[0], c[1], c[2], il});
   }
+  // Fewer rays per wave (interleaved, stealing): more waves for launches of few rays.
+  for (int rpw : {32, 16}) cand.push_back(hvf_schedule{0, 16, 8, 0, 4, 0, 0, 0, 0, 0, 0, 1, 2, 16, 1, rpw});
   hvf_schedule best = cand[0];
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(HVF_E_DEVICE, "hipEventCreate failed");

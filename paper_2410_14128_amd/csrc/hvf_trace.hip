@@ -674,12 +674,13 @@ __device__ __forceinline__ void push_survivor(bool cut, uint32_t i, float rest, 
 }
 
 // The ray of the lane with global index g: g itself, or with interleaving (W > 0: the
-// number of waves that hold rays) lane l of wave w takes ray l * W + w, so a wave's rays
-// are spread over the whole batch. Waves from W on take none (n stands for "no ray").
-__device__ __forceinline__ uint32_t ray_of(uint32_t g, uint32_t W, uint32_t n) {
+// number of waves that hold rays) lane l < R of wave w takes ray l * W + w, so a wave's
+// rays are spread over the whole batch. Lanes from R on and waves from W on take none
+// (n stands for "no ray"; an index of n or more is no ray either).
+__device__ __forceinline__ uint32_t ray_of(uint32_t g, uint32_t W, uint32_t n, uint32_t R = 64u) {
   if (W == 0u) return g;
   const uint32_t w = g >> 6, l = g & 63u;
-  return w < W ? l * W + w : n;
+  return (w < W && l < R) ? l * W + w : n;
 }
 
 template <uint32_t FAM>
@@ -1106,14 +1107,14 @@ __device__ __forceinline__ void steal_loop(const Fmt& fm, uint2* stk, const floa
 template <uint32_t FAM>
 __global__ __launch_bounds__(BLOCK) void trace_steal_kernel(const DevFormat F, const float4* __restrict__ rays,
                                                             int4* __restrict__ hits, uint32_t n, uint32_t period,
-                                                            float minlen, uint32_t min_idle, uint32_t W) {
+                                                            float minlen, uint32_t min_idle, uint32_t W, uint32_t R) {
   __shared__ __align__(8) uint32_t dtab[DTAB_WORDS];
   __shared__ uint32_t best_all[BLOCK], tbl_all[BLOCK];
   extern __shared__ uint2 stk_all[];
   const uint32_t* pre = stage_prefix(F, stk_all);
   load_dtab(F, dtab);
   const Fmt fm = fmt_of(F, dtab, pre);
-  const uint32_t i = ray_of(blockIdx.x * BLOCK + threadIdx.x, W, n), w0 = threadIdx.x & ~63u;
+  const uint32_t i = ray_of(blockIdx.x * BLOCK + threadIdx.x, W, n, R), w0 = threadIdx.x & ~63u;
   if (F.lds_words)
     steal_loop<FAM | FAM_PRE>(fm, stk_all + threadIdx.x, rays, hits, i, n, period, minlen, min_idle, best_all + w0,
                               tbl_all + w0);
@@ -1356,19 +1357,27 @@ hvf_status launch_trace(const DevFormat& F, int family, const hvf_ray* d_rays, s
 }
 
 hvf_status launch_trace_steal(const DevFormat& F, int family, const hvf_ray* d_rays, size_t n, hvf_hit* d_hits,
-                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, hipStream_t s) {
+                              uint32_t period, float minlen, uint32_t min_idle, bool interleave, uint32_t rays_per_wave,
+                              hipStream_t s) {
   if (n == 0) return HVF_OK;
   if (n >= (1ull << 32) - BLOCK) {
     hvf_set_error("at most 2^32 - 257 rays per stealing call");
     return HVF_E_INPUT;
   }
-  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  // With interleaving, R rays per wave over W = ceil(n / R) waves; else one ray per lane.
+  const uint32_t R = (interleave && rays_per_wave >= 1u && rays_per_wave < 64u) ? rays_per_wave : 64u;
+  const uint64_t W = interleave ? ((uint64_t)n + R - 1) / R : 0u;
+  const uint64_t lanes = interleave ? W * 64u : (uint64_t)n;
+  if (lanes >= (1ull << 32) - BLOCK) {
+    hvf_set_error("too many waves for one stealing call (rays / rays_per_wave * 64 reaches 2^32)");
+    return HVF_E_INPUT;
+  }
+  const unsigned grid = (unsigned)((lanes + BLOCK - 1) / BLOCK);
   const float4* r = reinterpret_cast<const float4*>(d_rays);
   int4* h = reinterpret_cast<int4*>(d_hits);
-  const uint32_t W = interleave ? (uint32_t)((n + 63) / 64) : 0u;
 #define HVF_LAUNCH_STEAL(FAMV)                                                                                  \
   hipLaunchKernelGGL(trace_steal_kernel<FAMV>, dim3(grid), dim3(BLOCK), stack_lds_bytes(F), s, F, r, h, (uint32_t)n, \
-                     period, minlen, min_idle, W)
+                     period, minlen, min_idle, (uint32_t)W, R)
   HVF_FAMILY_SWITCH(family, HVF_LAUNCH_STEAL)
 #undef HVF_LAUNCH_STEAL
   return launch_check("stealing trace");

@@ -108,7 +108,10 @@ SCHEDULES = [dict(stack_depth=1), dict(stack_depth=2), dict(stack_depth=3, persi
              dict(steal=16, steal_len=1 << 20), dict(steal=1, steal_len=1, steal_idle=16),
              dict(steal=2, steal_len=2, steal_idle=64), dict(interleave=1), dict(interleave=1, lds_depths=2),
              dict(interleave=1, stack_depth=2), dict(steal=1, steal_len=2, steal_idle=16, interleave=1),
-             dict(steal=4, steal_len=1, interleave=1, lds_depths=2)]
+             dict(steal=4, steal_len=1, interleave=1, lds_depths=2),
+             dict(steal=1, steal_len=2, steal_idle=16, interleave=1, rays_per_wave=32),
+             dict(steal=1, steal_len=1, steal_idle=1, interleave=1, rays_per_wave=1),
+             dict(steal=2, steal_len=2, steal_idle=8, interleave=1, rays_per_wave=17, lds_depths=2)]
 
 
 @pytest.mark.parametrize("sd", SCHEDULES, ids=lambda d: "-".join(f"{k}{v}" for k, v in d.items()))
@@ -143,9 +146,9 @@ def test_schedules_give_identical_results(H, sd):
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 255, 256, 257, 1000, 4097])
 def test_interleaved_rays_ragged_counts(H, n):
-    """Interleaved launches (lane l of wave w takes ray l * W + w) at counts that leave the
-    last waves partly or wholly empty: every ray is traced once, hits land at each ray's
-    index, equal to the plain launch's."""
+    """Interleaved launches (lane l < R of wave w takes ray l * W + w) at counts that leave the
+    last waves partly or wholly empty, with 64 and with fewer rays per wave: every ray is
+    traced once, hits land at each ray's index, equal to the plain launch's."""
     import torch
     codes, ext = W.scene_shell(11, 7, 8, 4, 1.4), (128,) * 3
     v = H.Volume("G(4) R(3,3,3) --whole-level-dedup", codes)
@@ -153,7 +156,10 @@ def test_interleaved_rays_ragged_counts(H, n):
     d = torch.from_numpy(np.ascontiguousarray(rays)).cuda()
     plain = v.trace(d).cpu().numpy()
     for sd in (dict(interleave=1), dict(steal=1, steal_len=1, interleave=1),
-               dict(steal=1, steal_len=2, steal_idle=16, interleave=1)):
+               dict(steal=1, steal_len=2, steal_idle=16, interleave=1),
+               dict(steal=1, steal_len=2, steal_idle=16, interleave=1, rays_per_wave=32),
+               dict(steal=1, steal_len=1, steal_idle=4, interleave=1, rays_per_wave=7),
+               dict(steal=1, steal_len=1, steal_idle=1, interleave=1, rays_per_wave=1)):
         hb = torch.full((n, 4), 7, dtype=torch.int32, device="cuda")
         v.trace(d, hb, sched=H.schedule(**sd))
         assert np.array_equal(hb.cpu().numpy(), plain), f"n={n} {sd}"

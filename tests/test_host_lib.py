@@ -307,8 +307,8 @@ def test_df_layout_sizes():
 
 
 def test_schedule_checks_split_fields():
-    """Out-of-range split, steal and interleave fields are refused before any device work (no GPU
-    needed)."""
+    """Out-of-range split, steal, interleave and rays-per-wave fields are refused before any
+    device work (no GPU needed)."""
     import ctypes
     v = H.Volume("R(3,3,3)", np.array([0, 7, 100], np.uint64))
     bad = [H.schedule(split=3, split_budget=8), H.schedule(split=1, split_budget=8), H.schedule(split=128, split_budget=8),
@@ -323,7 +323,10 @@ def test_schedule_checks_split_fields():
            H.schedule(steal=4, steal_len=8, sort=1),
            H.schedule(steal=4, steal_len=8, split=4, split_budget=8),
            H.schedule(interleave=2), H.schedule(interleave=-1), H.schedule(interleave=1, persistent=1),
-           H.schedule(interleave=1, sort=1), H.schedule(interleave=1, split=4, split_budget=8)]
+           H.schedule(interleave=1, sort=1), H.schedule(interleave=1, split=4, split_budget=8),
+           H.schedule(rays_per_wave=-1), H.schedule(rays_per_wave=65),
+           H.schedule(rays_per_wave=32), H.schedule(rays_per_wave=32, interleave=1),
+           H.schedule(rays_per_wave=32, steal=1, steal_len=2, steal_idle=16)]
     for sc in bad:
         st = H.lib().hvf_trace_sched(v.handle, None, 1, None, ctypes.byref(sc), None)
         assert H.STATUS[st] == "HVF_E_INPUT", H.schedule_dict(sc)
